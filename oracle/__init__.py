@@ -1,0 +1,1 @@
+"""Plain FP64 CPU oracle (test infrastructure only; see oracle.oracle)."""

@@ -1,0 +1,47 @@
+"""Operation and byte counts of the method, for roofline reporting.
+
+Two counts are kept apart:
+
+* the paper's own cost model (Sec. 3): 20 L^2 + 1 FLOP per pixel for the
+  Dirac delta basis and N L^2 + 2 L^2 + 18 N + 1 for N Gaussian bases, with an
+  L x L kernel;
+* the algorithmic count of the per-pixel-coefficient form used here, with a
+  fused multiply-add counted as 2 FLOP:
+  2 N k^2 (basis responses) + 2 N M (coefficients c_n) + 2 N (dot with c)
+  + 1 (subtraction of I).
+
+The minimum HBM traffic of D = (R (x) K) - I is one read of R and I and one
+write of D: 12 bytes per pixel in float32.
+"""
+
+PAN_STARRS_TILE = (4846, 4868)
+PAN_STARRS_TILES = 60
+
+
+def paper_flops_dfb(L):
+    """Paper's Dirac-delta-basis count per pixel (Sec. 3)."""
+    return 20 * L * L + 1
+
+
+def paper_flops_gfb(N, L):
+    """Paper's Gaussian-basis count per pixel (Sec. 3)."""
+    return N * L * L + 2 * L * L + 18 * N + 1
+
+
+def flops_per_pixel(N, M, k):
+    """Algorithmic FLOP per pixel of the per-pixel-coefficient form."""
+    return 2 * N * k * k + 2 * N * M + 2 * N + 1
+
+
+def regrouped_flops_per_pixel(M, k):
+    """FLOP per pixel of the regrouped form sum_m P_m (R (x) Kt_m) - I."""
+    return 2 * M * k * k + 2 * M + 1
+
+
+def executed_flops_per_pixel(n_filters_padded, taps_padded, passes=1):
+    """MFMA FLOP actually issued per pixel by a padded contraction."""
+    return 2 * n_filters_padded * taps_padded * passes
+
+
+BYTES_PER_PIXEL = 12          # R in, I in, D out (float32)
+BYTES_PER_PIXEL_FORWARD = 8   # R in, C out

@@ -1,0 +1,35 @@
+"""The paper's worked cost-model numbers (Sec. 3), from tests/golden."""
+
+import os
+
+from paper_1209_5823_amd import flops
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "flop_model.txt")
+
+
+def _rows():
+    for line in open(GOLD):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            kind, L, N, per_px, tile_g, image, unit = line.split()
+            yield kind, int(L), int(N), int(per_px), float(tile_g), float(image), unit
+
+
+def test_paper_cost_model_numbers():
+    tile = flops.PAN_STARRS_TILE[0] * flops.PAN_STARRS_TILE[1]
+    rows = list(_rows())
+    assert len(rows) == 2
+    for kind, L, N, per_px, tile_g, image, unit in rows:
+        got = flops.paper_flops_dfb(L) if kind == "dfb" else flops.paper_flops_gfb(N, L)
+        assert got == per_px
+        assert round(got * tile / 1e9, 2 if tile_g < 10 else 1) == tile_g
+        scale = 1e12 if unit == "TFLOP" else 1e9
+        digits = 2 if image < 10 else 0
+        assert round(got * tile * flops.PAN_STARRS_TILES / scale, digits) == image
+
+
+def test_algorithmic_counts_at_workloads():
+    # 2 N k^2 + 2 N M + 2 N + 1 with (N, M, k) of the chip and survey workloads
+    assert flops.flops_per_pixel(49, 6, 21) == 43905
+    assert flops.flops_per_pixel(49, 15, 31) == 95747
+    assert flops.flops_per_pixel(22, 6, 15) == 10209
