@@ -1,0 +1,183 @@
+/*
+ * svconv.h - C ABI of the MI355X (gfx950) spatially-varying-kernel
+ * convolution and image-subtraction library (libsvconv.so).
+ *
+ * The method (Hartung, Shukla, Miller & Pennypacker, Sec. 2):
+ *
+ *   D = (R (x) K) - I                                           (Eq. 1)
+ *   K(x,y) = sum_n c_n(x,y) B_n,  c_n(x,y) = sum_m a[n][m] P_m(x,y)
+ *                                                         (Eq. 2, Eq. 3)
+ *
+ * R is the reference image, I the image it is matched to, B_n the basis
+ * functions, P_m the spatial polynomial terms and a[n][m] the coefficients.
+ * The kernel differs at every pixel and is used in full at every pixel
+ * (Sec. 3).
+ *
+ * Conventions used by every entry point:
+ *   - images: float32, row-major [height][width], contiguous, x = column,
+ *     y = row; R is treated as 0 outside the supplied array;
+ *   - (R (x) K)(x,y) = sum_{u,v} K(x,y)[u,v] R(x-u, y-v), u,v in [-h, h]
+ *     (true convolution; the kernel is taken at the output pixel);
+ *   - basis: for Gaussian g (width sigma_g, degree d_g), for t = 0..d_g and
+ *     i = t..0, j = t-i: exp(-(u^2+v^2)/(2 sigma_g^2)) u^i v^j scaled to unit
+ *     L1 norm; sigma_g = 0 is a Kronecker delta (d_g must be 0);
+ *   - spatial terms: P_m = xh^i yh^j for t = 0..spatial_degree, i = t..0,
+ *     with xh = 2 (x + x0) / (frame_width - 1) - 1 and yh likewise, over the
+ *     frame set by svconv_plan_set_frame (default: the image itself);
+ *   - coefficients: a is float32 [N][M], n-major (N bases, M spatial terms).
+ *
+ * Memory: every image, coefficient, gradient and matrix pointer is a DEVICE
+ * pointer owned by the caller, unless a comment says "host".  The plan owns
+ * its tables and scratch, which are allocated by svconv_plan_create; the
+ * compute entry points allocate nothing.
+ *
+ * Asynchrony: compute entry points enqueue work on the plan's stream and
+ * return.  Invalid arguments are rejected with SVCONV_EINVAL before any HIP
+ * call.  Launch failures return SVCONV_EDEVICE; faults inside a kernel
+ * surface at the caller's next synchronisation.  Entry points that return a
+ * value computed on the device (svconv_cholesky_factor, svconv_gn_step)
+ * synchronise the plan's stream and say so.
+ *
+ * Threads: a plan must not be used by two threads at once; distinct plans
+ * are independent.  No entry point aborts or exits.
+ */
+#ifndef SVCONV_H
+#define SVCONV_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct svconv_plan svconv_plan;
+
+enum svconv_status {
+    SVCONV_OK = 0,
+    SVCONV_EINVAL = -1,       /* invalid argument (checked before any HIP call) */
+    SVCONV_ENOMEM = -2,       /* device or host allocation failed */
+    SVCONV_EDEVICE = -3,      /* HIP runtime or launch error */
+    SVCONV_EUNSUPPORTED = -4, /* valid but outside what the kernels support */
+    SVCONV_ENOTSPD = -5       /* matrix not symmetric positive definite */
+};
+
+/* Arithmetic of the basis contraction (the dominant step). */
+enum svconv_precision {
+    SVCONV_FP32 = 0,    /* float32 matrix cores (v_mfma_f32_16x16x4_f32)      */
+    SVCONV_BF16 = 1,    /* bf16 inputs, fp32 accumulation, 1 product          */
+    SVCONV_FP16 = 2,    /* fp16 inputs, fp32 accumulation, 1 product          */
+    SVCONV_BF16X3 = 3,  /* R and B split hi+lo in bf16: hh + lh + hl          */
+    SVCONV_FP16X2 = 4,  /* R split hi+lo in fp16, B in fp16: hh + lh          */
+    SVCONV_FP16X3 = 5   /* R and B split hi+lo in fp16: hh + lh + hl          */
+};
+
+/* How the per-pixel kernel is contracted (both give D of Eq. 1 exactly, up
+ * to rounding).  BASIS: N basis responses T_n = B_n (x) R, then
+ * D = sum_n c_n T_n - I.  REGROUPED: Kt_m = sum_n a[n][m] B_n (built on the
+ * device per call), then D = sum_m P_m (Kt_m (x) R) - I, which needs M
+ * instead of N filters because P_m depends only on the output pixel. */
+enum svconv_form { SVCONV_FORM_BASIS = 0, SVCONV_FORM_REGROUPED = 1 };
+
+/*
+ * Create a plan for images of height x width with a (2 half_width + 1)^2
+ * kernel, n_gauss Gaussian families (host arrays sigmas[n_gauss] in pixels,
+ * degrees[n_gauss]) and spatial polynomial degree spatial_degree (Sec. 2,
+ * Eq. 2, Eq. 3).  Builds the basis in float64 on the host and uploads its
+ * tables; allocates all scratch.  Uses the current HIP device.
+ * Limits: 0 <= half_width <= 31, 0 <= spatial_degree <= 6, N*M <= 1024,
+ * N <= 64 (BASIS form).  EINVAL for bad values, EUNSUPPORTED beyond limits.
+ */
+int svconv_plan_create(svconv_plan** out, int height, int width, int half_width, int n_gauss,
+                       const double* sigmas, const int* degrees, int spatial_degree,
+                       int precision);
+
+/* Crop support: the image is the sub-array at (x0, y0) of a frame of
+ * frame_width x frame_height pixels; spatial terms use frame coordinates.
+ * EINVAL unless 0 <= x0, 0 <= y0, x0 + width <= frame_width, y0 + height
+ * <= frame_height. */
+int svconv_plan_set_frame(svconv_plan* plan, int x0, int y0, int frame_width, int frame_height);
+
+/* Stream for all later work of the plan (a hipStream_t; NULL = default). */
+int svconv_plan_set_stream(svconv_plan* plan, void* stream);
+
+/* Select the arithmetic (enum svconv_precision) for later calls. */
+int svconv_plan_set_precision(svconv_plan* plan, int precision);
+
+/* Select the contraction form (enum svconv_form) for later calls. */
+int svconv_plan_set_form(svconv_plan* plan, int form);
+
+/* Pedestal s subtracted from R before the contraction and restored exactly
+ * through s * sum_n c_n sum(B_n); it shrinks the magnitude of partial sums
+ * (default 0).  EINVAL if not finite. */
+int svconv_plan_set_pedestal(svconv_plan* plan, float pedestal);
+
+/* Number of bases N and spatial terms M (host outputs; either may be NULL). */
+int svconv_plan_sizes(const svconv_plan* plan, int* n_basis, int* n_spatial);
+
+/* Copy the float64 basis table B[n][v+h][u+h] to host memory host_out
+ * (N * k * k doubles). */
+int svconv_plan_get_basis(const svconv_plan* plan, double* host_out);
+
+/* Free the plan and everything it owns (synchronises its stream).  NULL is
+ * accepted. */
+int svconv_plan_destroy(svconv_plan* plan);
+
+/* out = R (x) K(x,y)  (Eq. 1 without the subtraction, Eq. 2).
+ * R, out: [height][width]; a: [N][M].  out must not alias R. */
+int svconv_forward(svconv_plan* plan, const float* R, const float* a, float* out);
+
+/* D = (R (x) K(x,y)) - I  (Eq. 1).  D may alias I but not R. */
+int svconv_difference(svconv_plan* plan, const float* R, const float* I, const float* a,
+                      float* D);
+
+/* Adjoint of svconv_difference for a loss L(D), given gD = dL/dD:
+ *   gR[q]    = sum_{u,v} gD(q+(u,v)) K(q+(u,v))[u,v]         (float32, [H][W])
+ *   ga[n][m] = sum_p gD(p) P_m(p) (B_n (x) R)(p)              (float64, [N][M])
+ * (dL/dI = -gD needs no kernel.)  Either output may be NULL to skip it.
+ * gR must not alias R or gD. */
+int svconv_backward(svconv_plan* plan, const float* R, const float* a, const float* gD,
+                    float* gR, double* ga);
+
+/* Loss of the least-squares fit (OIS, Sec. 2) and its gradient in D:
+ * L = sum_{p in mask} D(p)^2, gD = 2 D 1_mask.  mask: uint8 [H][W] (nonzero =
+ * in), or NULL for the interior (pixels at least h from every edge).
+ * loss: device float64 scalar (may be NULL); gD may alias D. */
+int svconv_loss_grad(svconv_plan* plan, const float* D, const unsigned char* mask, float* gD,
+                     double* loss);
+
+/* Normal matrix of the fit: JtJ[(n,m)][(n',m')] = sum_{p in mask}
+ * P_m P_m' T_n T_n' with T_n = B_n (x) R, index (n,m) -> n*M + m; float64
+ * [NM][NM] device.  mask as in svconv_loss_grad. */
+int svconv_normal_matrix(svconv_plan* plan, const float* R, const unsigned char* mask,
+                         double* JtJ);
+
+/* In-place Cholesky factorisation A = L L^T of an n x n float64 device
+ * matrix (lower triangle of A is overwritten with L; the strict upper
+ * triangle is zeroed).  Synchronises the plan's stream; returns
+ * SVCONV_ENOTSPD if a pivot is not positive. */
+int svconv_cholesky_factor(svconv_plan* plan, double* A, int n);
+
+/* x = (L L^T)^-1 rhs for a factor from svconv_cholesky_factor; float64
+ * device vectors of length n.  x may alias rhs. */
+int svconv_cholesky_solve(svconv_plan* plan, const double* L, const double* rhs, double* x,
+                          int n);
+
+/* One Gauss-Newton iteration of the fit of a to min sum_mask D^2:
+ * D = R (x) K(a) - I; ga = dL/da; delta = (JtJ)^-1 ga / 2; a -= delta.
+ * a64: float64 [N][M] master copy (updated); a32: float32 copy written from
+ * it before the forward; D: float32 [H][W] output of this iteration's
+ * residual; L: Cholesky factor of JtJ.  host_stats (host, 2 doubles, may be
+ * NULL) receives (L before the step, ||delta||_2); when given, the call
+ * synchronises the plan's stream. */
+int svconv_gn_step(svconv_plan* plan, const float* R, const float* I, const unsigned char* mask,
+                   const double* L, double* a64, float* a32, float* D, double* host_stats);
+
+/* Static description of a status code. */
+const char* svconv_strerror(int status);
+
+/* Detail of the last error raised on the calling thread ("" if none). */
+const char* svconv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SVCONV_H */

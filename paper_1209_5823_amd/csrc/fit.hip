@@ -1,0 +1,403 @@
+// Least-squares fit of the coefficients (Optimal Image Subtraction, Sec. 2):
+// loss and its gradient in D, the float64 normal matrix, an in-place
+// Cholesky factorisation, the two triangular solves and the Gauss-Newton
+// update.  Everything here is float64 except the basis responses, which come
+// from the float32 matrix-core contraction.
+//
+// Normal matrix.  With Phi[p][(n,m)] = P_m(p) T_n(p),
+//   JtJ[(n,m)][(n',m')] = sum_p mask(p) T_n(p) T_n'(p) P_m(p) P_m'(p),
+// and P_m P_m' is itself one monomial xh^(i+i') yh^(j+j') of degree at most
+// 2 d_s.  So JtJ is assembled from
+//   S[mu][n][n'] = sum_p mask(p) Q_mu(p) T_n(p) T_n'(p)
+// over the (d_s + 1)(2 d_s + 1) monomials Q_mu of degree <= 2 d_s, which needs
+// N^2 per monomial instead of (N M)^2 products per pixel.  The T_n of a band
+// of rows are produced by the forward contraction (written out instead of
+// being contracted with c_n), then S is accumulated on the float64 matrix
+// cores (v_mfma_f64_16x16x4_f64).
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace svc {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------ loss ----
+
+__device__ __forceinline__ bool in_mask(const unsigned char* mask, int H, int W, int h, int x, int y) {
+    if (mask) return mask[(size_t)y * W + x] != 0;
+    return x >= h && x <= W - 1 - h && y >= h && y <= H - 1 - h;
+}
+
+constexpr int LOSS_BLOCKS = 1024;
+
+__global__ void loss_grad_kernel(const float* __restrict__ D, const unsigned char* __restrict__ mask,
+                                 int H, int W, int h, float* __restrict__ gD,
+                                 double* __restrict__ part) {
+    double s = 0.0;
+    const size_t n = (size_t)H * W;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const int y = (int)(i / W), x = (int)(i % W);
+        const float d = D[i];
+        const bool m = in_mask(mask, H, W, h, x, y);
+        gD[i] = m ? 2.f * d : 0.f;
+        if (m) s += (double)d * d;
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void sum_kernel(const double* __restrict__ part, int n, double* __restrict__ out) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+int launch_loss_grad(svconv_plan* p, const float* D, const unsigned char* mask, float* gD,
+                     double* loss) {
+    hipLaunchKernelGGL(loss_grad_kernel, dim3(LOSS_BLOCKS), dim3(256), 0, p->stream, D, mask, p->H,
+                       p->W, p->h, gD, p->dRed);
+    int st = hip_status(hipGetLastError(), "loss_grad_kernel");
+    if (st || !loss) return st;
+    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, p->stream, p->dRed, LOSS_BLOCKS, loss);
+    return hip_status(hipGetLastError(), "sum_kernel");
+}
+
+// --------------------------------------------------- normal matrix ----
+
+constexpr int NM_PIX_CHUNK = 4096;    // pixels per workgroup and band
+constexpr size_t NM_BAND_BYTES = (size_t)512 << 20;
+
+__device__ __forceinline__ double ipow_f(double x, int e) {
+    double r = 1.0;
+    for (int t = 0; t < e; ++t) r *= x;
+    return r;
+}
+
+// S_part[chunk][mu][n][n'] for 64 x 64 (n, n') and one monomial mu per
+// workgroup: wave w owns rows n = 16 w .. 16 w + 15, all 64 columns.
+// A operand: T_n(p_k); B operand: T_n'(p_k) Q_mu(p_k) mask(p_k).
+__global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ T, int N, int band_px,
+                                                   int y_begin, int W, int H, int h,
+                                                   const unsigned char* __restrict__ mask,
+                                                   double sx, double ox, double sy, double oy,
+                                                   int n_mu, double* __restrict__ part) {
+    const int mu = blockIdx.x;
+    const int chunk = blockIdx.y;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int kq = lane >> 4, j = lane & 15;
+    int tt = 0;
+    while ((tt + 1) * (tt + 2) / 2 <= mu) ++tt;
+    const int ej = mu - tt * (tt + 1) / 2;
+    const int ei = tt - ej;
+
+    d4 acc[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
+    const int na = 16 * w + j;                         // A row of this lane
+    const int p_begin = chunk * NM_PIX_CHUNK;
+    const int p_end = min(band_px, p_begin + NM_PIX_CHUNK);
+    for (int p0 = p_begin; p0 < p_end; p0 += 4) {
+        const int pp = p0 + kq;
+        double wq = 0.0;
+        if (pp < p_end) {
+            const int y = y_begin + pp / W, x = pp % W;
+            if (in_mask(mask, H, W, h, x, y))
+                wq = ipow_f(sx * x + ox, ei) * ipow_f(sy * y + oy, ej);
+        }
+        const bool ok = pp < p_end;
+        const double av = (ok && na < N) ? (double)T[(size_t)na * band_px + pp] : 0.0;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            const int nb = 16 * cb + j;
+            const double bv = (ok && nb < N) ? (double)T[(size_t)nb * band_px + pp] * wq : 0.0;
+            acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[cb], 0, 0, 0);
+        }
+    }
+    // lane (kq, j) holds S[n = 16 w + 4 kq + e][n' = 16 cb + j]
+    double* dst = part + ((size_t)chunk * n_mu + mu) * 64 * 64;
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dst[(16 * w + 4 * kq + e) * 64 + 16 * cb + j] = acc[cb][e];
+}
+
+// S[mu][.][.] += sum over chunks (fixed order)
+__global__ void gram_reduce(const double* __restrict__ part, int n_chunks, int n_mu,
+                            double* __restrict__ S) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_mu * 4096) return;
+    double s = 0.0;
+    for (int c = 0; c < n_chunks; ++c) s += part[(size_t)c * n_mu * 4096 + idx];
+    S[idx] += s;
+}
+
+__global__ void zero_kernel(double* __restrict__ v, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        v[i] = 0.0;
+}
+
+// JtJ[(n,m)][(n',m')] = S[mu(i_m + i_m', j_m + j_m')][n][n']
+__global__ void assemble_jtj(const double* __restrict__ S, int N, int M, double* __restrict__ JtJ) {
+    const int NM = N * M;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= NM * NM) return;
+    const int r = idx / NM, c = idx % NM;
+    const int n = r / M, m = r % M, n2 = c / M, m2 = c % M;
+    auto expo = [](int q, int& i, int& jj) {
+        int t = 0;
+        while ((t + 1) * (t + 2) / 2 <= q) ++t;
+        jj = q - t * (t + 1) / 2;
+        i = t - jj;
+    };
+    int i1, j1, i2, j2;
+    expo(m, i1, j1);
+    expo(m2, i2, j2);
+    const int a = i1 + i2, b = j1 + j2, t = a + b;
+    const int mu = t * (t + 1) / 2 + b;
+    JtJ[idx] = S[(size_t)mu * 4096 + n * 64 + n2];
+}
+
+int launch_normal_matrix(svconv_plan* p, const float* R, const unsigned char* mask, double* JtJ) {
+    if (p->N > 64) return fail(SVCONV_EUNSUPPORTED, "normal matrix needs N <= 64");
+    const int n_mu = (2 * p->d_s + 1) * (2 * p->d_s + 2) / 2;
+    const size_t row_bytes = (size_t)p->N * p->W * sizeof(float);
+    int band = (int)(NM_BAND_BYTES / row_bytes);
+    if (band < 8) band = 8;
+    if (band > p->H) band = p->H;
+    const int max_px = band * p->W;
+    const int n_chunks = (max_px + NM_PIX_CHUNK - 1) / NM_PIX_CHUNK;
+    const size_t part_elems = (size_t)n_chunks * n_mu * 4096;
+    const size_t s_elems = (size_t)n_mu * 4096;
+    // scratch of the normal matrix: allocated on its first call, kept by the plan
+    if (!p->dTband || p->band_rows != band) {
+        if (p->dTband) (void)hipFree(p->dTband);
+        if (p->dNMpart) (void)hipFree(p->dNMpart);
+        p->dTband = nullptr;
+        p->dNMpart = nullptr;
+        if (hipMalloc((void**)&p->dTband, (size_t)band * row_bytes) != hipSuccess ||
+            hipMalloc((void**)&p->dNMpart, (part_elems + s_elems) * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            if (p->dTband) (void)hipFree(p->dTband);
+            p->dTband = nullptr;
+            p->dNMpart = nullptr;
+            return fail(SVCONV_ENOMEM, "normal-matrix scratch");
+        }
+        p->band_rows = band;
+    }
+    double* S = p->dNMpart + part_elems;
+    hipLaunchKernelGGL(zero_kernel, dim3(256), dim3(256), 0, p->stream, S, s_elems);
+    int st = hip_status(hipGetLastError(), "zero_kernel");
+    if (st) return st;
+
+    ContractArgs c{};
+    c.X = R;
+    c.H = p->H;
+    c.W = p->W;
+    c.h = p->h;
+    c.NF = p->N;
+    c.M = p->M;
+    c.d_s = p->d_s;
+    c.coef = nullptr;
+    c.beta = p->dBeta;
+    c.ped = p->pedestal;
+    c.I = nullptr;
+    c.out = nullptr;
+    double sx = 0, ox = 0, sy = 0, oy = 0;
+    if (p->Wf > 1) { sx = 2.0 / (p->Wf - 1); ox = sx * p->x0 - 1.0; }
+    if (p->Hf > 1) { sy = 2.0 / (p->Hf - 1); oy = sy * p->y0 - 1.0; }
+    c.sx = sx; c.ox = ox; c.sy = sy; c.oy = oy;
+    c.tout = p->dTband;
+    // basis-form kernel with out == nullptr: coefficients are neither read nor used
+    c.coef = reinterpret_cast<const float*>(p->dF32);
+    const int nb = (p->N + 15) / 16;
+    for (int y0 = 0; y0 < p->H; y0 += band) {
+        const int rows = (y0 + band <= p->H) ? band : p->H - y0;
+        c.y_begin = y0;
+        c.n_rows = rows;
+        st = launch_contract_f32(c, p->dFragF32, nb, p->stream);
+        if (st) return st;
+        const int band_px = rows * p->W;
+        const int chunks = (band_px + NM_PIX_CHUNK - 1) / NM_PIX_CHUNK;
+        hipLaunchKernelGGL(gram_kernel, dim3(n_mu, chunks), dim3(256), 0, p->stream, p->dTband,
+                           p->N, band_px, y0, p->W, p->H, p->h, mask, sx, ox, sy, oy, n_mu,
+                           p->dNMpart);
+        st = hip_status(hipGetLastError(), "gram_kernel");
+        if (st) return st;
+        hipLaunchKernelGGL(gram_reduce, dim3((n_mu * 4096 + 255) / 256), dim3(256), 0, p->stream,
+                           p->dNMpart, chunks, n_mu, S);
+        st = hip_status(hipGetLastError(), "gram_reduce");
+        if (st) return st;
+    }
+    const int NM = p->N * p->M;
+    hipLaunchKernelGGL(assemble_jtj, dim3((NM * NM + 255) / 256), dim3(256), 0, p->stream, S, p->N,
+                       p->M, JtJ);
+    return hip_status(hipGetLastError(), "assemble_jtj");
+}
+
+// -------------------------------------------------------- Cholesky ----
+
+// Right-looking in-place factorisation by one workgroup; A stays in global
+// memory (at most 1024 x 1024 doubles, resident in L2).  status[0] becomes
+// the first non-positive pivot index + 1 (0 = SPD).
+__global__ __launch_bounds__(1024) void cholesky_kernel(double* __restrict__ A, int n,
+                                                        int* __restrict__ status) {
+    __shared__ int bad;
+    __shared__ double piv;
+    const int tid = threadIdx.x;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    for (int jc = 0; jc < n; ++jc) {
+        if (tid == 0) {
+            const double d = A[(size_t)jc * n + jc];
+            if (!(d > 0.0) || !isfinite(d)) {
+                bad = jc + 1;
+                piv = 1.0;
+            } else {
+                piv = sqrt(d);
+                A[(size_t)jc * n + jc] = piv;
+            }
+        }
+        __syncthreads();
+        if (bad) break;
+        const double inv = 1.0 / piv;
+        for (int i = jc + 1 + tid; i < n; i += 1024) A[(size_t)i * n + jc] *= inv;
+        __syncthreads();
+        // trailing update of the lower triangle: A[i][c] -= L[i][jc] L[c][jc], jc < c <= i
+        const int m = n - jc - 1;
+        const long cnt = (long)m * (m + 1) / 2;
+        for (long q = tid; q < cnt; q += 1024) {
+            // row-major enumeration of the lower triangle of an m x m block
+            long i = (long)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+            while (i * (i + 1) / 2 > q) --i;
+            while ((i + 1) * (i + 2) / 2 <= q) ++i;
+            const long c = q - i * (i + 1) / 2;
+            const int ii = jc + 1 + (int)i, cc = jc + 1 + (int)c;
+            A[(size_t)ii * n + cc] -= A[(size_t)ii * n + jc] * A[(size_t)cc * n + jc];
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    if (!bad) {
+        for (long q = tid; q < (long)n * n; q += 1024) {
+            const int i = (int)(q / n), c = (int)(q % n);
+            if (c > i) A[q] = 0.0;
+        }
+    }
+    if (tid == 0) status[0] = bad;
+}
+
+int launch_cholesky(svconv_plan* p, double* A, int n) {
+    hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(1024), 0, p->stream, A, n, p->dStatus);
+    int st = hip_status(hipGetLastError(), "cholesky_kernel");
+    if (st) return st;
+    int bad = 0;
+    st = hip_status(hipMemcpyAsync(&bad, p->dStatus, sizeof(int), hipMemcpyDeviceToHost, p->stream),
+                    "copy status");
+    if (!st) st = hip_status(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+    if (st) return st;
+    if (bad) return fail(SVCONV_ENOTSPD, "pivot " + std::to_string(bad - 1) + " is not positive");
+    return SVCONV_OK;
+}
+
+// x = L^-T L^-1 rhs, one workgroup, column-oriented substitutions.
+__global__ __launch_bounds__(1024) void chol_solve_kernel(const double* __restrict__ L,
+                                                          const double* __restrict__ rhs,
+                                                          double* __restrict__ x, int n) {
+    extern __shared__ double v[];   // n doubles
+    const int tid = threadIdx.x;
+    for (int i = tid; i < n; i += 1024) v[i] = rhs[i];
+    __syncthreads();
+    // forward: L y = b
+    for (int jc = 0; jc < n; ++jc) {
+        const double yj = v[jc] / L[(size_t)jc * n + jc];
+        __syncthreads();
+        if (tid == 0) v[jc] = yj;
+        for (int i = jc + 1 + tid; i < n; i += 1024) v[i] -= L[(size_t)i * n + jc] * yj;
+        __syncthreads();
+    }
+    // backward: L^T x = y
+    for (int jc = n - 1; jc >= 0; --jc) {
+        const double xj = v[jc] / L[(size_t)jc * n + jc];
+        __syncthreads();
+        if (tid == 0) v[jc] = xj;
+        for (int i = tid; i < jc; i += 1024) v[i] -= L[(size_t)jc * n + i] * xj;
+        __syncthreads();
+    }
+    for (int i = tid; i < n; i += 1024) x[i] = v[i];
+}
+
+int launch_cholesky_solve(svconv_plan* p, const double* L, const double* rhs, double* x, int n) {
+    hipLaunchKernelGGL(chol_solve_kernel, dim3(1), dim3(1024), (size_t)n * sizeof(double), p->stream,
+                       L, rhs, x, n);
+    return hip_status(hipGetLastError(), "chol_solve_kernel");
+}
+
+// --------------------------------------------------------- updates ----
+
+__global__ void scale_kernel(double* v, double s, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] *= s;
+}
+
+__global__ void copy_a_kernel(const double* a64, float* a32, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a32[i] = (float)a64[i];
+}
+
+// a64 -= delta, a32 = float(a64), norm = ||delta||_2 (one workgroup)
+__global__ __launch_bounds__(1024) void gn_update_kernel(const double* __restrict__ delta,
+                                                         double* __restrict__ a64,
+                                                         float* __restrict__ a32, int n,
+                                                         double* __restrict__ norm) {
+    __shared__ double red[1024];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 1024) {
+        const double d = delta[i];
+        const double v = a64[i] - d;
+        a64[i] = v;
+        a32[i] = (float)v;
+        s += d * d;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *norm = sqrt(red[0]);
+}
+
+int launch_scale(svconv_plan* p, double* v, double s, int n) {
+    hipLaunchKernelGGL(scale_kernel, dim3((n + 255) / 256), dim3(256), 0, p->stream, v, s, n);
+    return hip_status(hipGetLastError(), "scale_kernel");
+}
+
+int launch_copy_a(svconv_plan* p, const double* a64, float* a32, int n) {
+    hipLaunchKernelGGL(copy_a_kernel, dim3((n + 255) / 256), dim3(256), 0, p->stream, a64, a32, n);
+    return hip_status(hipGetLastError(), "copy_a_kernel");
+}
+
+int launch_gn_update(svconv_plan* p, const double* delta, double* a64, float* a32, int n) {
+    // the step norm lands right after the loss scalar in the plan's vector scratch
+    double* norm = p->dVec + 2 * (size_t)p->N * p->M + 1;
+    hipLaunchKernelGGL(gn_update_kernel, dim3(1), dim3(1024), 0, p->stream, delta, a64, a32, n, norm);
+    return hip_status(hipGetLastError(), "gn_update_kernel");
+}
+
+}  // namespace svc

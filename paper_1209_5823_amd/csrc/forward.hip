@@ -1,0 +1,390 @@
+// Forward contraction of the spatially-varying convolution on gfx950.
+//
+// Every forward-shaped computation of the library is one "weighted
+// multi-filter correlation":
+//
+//   out(p) = sum_f w_f(p) * T_f(p) - I(p),
+//   T_f(p) = sum_{dv,du} F_f[dv][du] * X(p + (du - h, dv - h)),
+//
+// with w_f(p) = sum_m coef[f][m] P_m(p) (basis form, Eq. 2 - Eq. 3) or
+// w_f(p) = P_f(p) (regrouped form and the adjoint in R).  The T_f of a tile
+// of output pixels are a dense product (filters x taps) . (taps x pixels) run
+// on the matrix cores; the patch matrix is never stored: its columns are read
+// straight out of an LDS copy of the input tile plus its halo.
+#include <cstdlib>
+
+#include "internal.hpp"
+
+namespace svc {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------- helpers --
+
+// Workgroups are dispatched round-robin over the 8 XCDs.  Give each XCD a
+// contiguous run of tiles so that neighbouring tiles (which share halo rows)
+// meet in the same L2.
+__device__ __forceinline__ int xcd_remap(int bid, int n) {
+    const int x = bid & 7, t = bid >> 3;
+    const int q = n >> 3, r = n & 7;
+    return x * q + (x < r ? x : r) + t;
+}
+
+__device__ __forceinline__ double ipow_d(double x, int e) {
+    double r = 1.0;
+#pragma unroll
+    for (int t = 0; t < kMaxSpatialDegree; ++t)
+        if (t < e) r *= x;
+    return r;
+}
+
+// Exponents (i, j) of spatial term m: t = 0..d, i = t..0, j = t - i.
+__device__ __forceinline__ void term_exponents(int m, int& i, int& j) {
+    int t = 0;
+    while ((t + 1) * (t + 2) / 2 <= m) ++t;
+    const int o = m - t * (t + 1) / 2;
+    i = t - o;
+    j = o;
+}
+
+static int pitch_16mod64(int cols) {
+    int p = 16;
+    while (p < cols) p += 64;
+    return p;
+}
+
+// ------------------------------------------------------ FP32 geometry ----
+
+constexpr int F32_TW = 64;   // output tile width: 4 waves x 16 columns
+
+// Output rows per tile (= 16-pixel blocks per wave): fewer rows for more
+// filter blocks so that the float32 sub-chain and float64 total fit in 256
+// registers (two waves per SIMD).
+constexpr int f32_tile_h(int nb) { return nb >= 3 ? 4 : 8; }
+
+F32Geometry f32_geometry(int k, int nb) {
+    F32Geometry g;
+    g.k = k;
+    g.n_rg = (k + 3) / 4;
+    g.n_chunks = g.n_rg * k;
+    g.nb = nb;
+    g.tile_w = F32_TW;
+    g.tile_h = f32_tile_h(nb);
+    g.lds_rows = g.tile_h + 4 * g.n_rg - 1;
+    g.lds_cols = g.tile_w + k - 1;
+    g.lds_pitch = pitch_16mod64(g.lds_cols);
+    g.lds_bytes = (size_t)g.lds_rows * g.lds_pitch * 4 + (size_t)kMaxFilters * kMaxSpatialTerms * 4;
+    return g;
+}
+
+size_t f32_fragment_floats(int k, int nb) {
+    const F32Geometry g = f32_geometry(k, nb);
+    return (size_t)g.n_chunks * nb * 64;
+}
+
+// A-operand fragments of v_mfma_f32_16x16x4_f32.  Chunk c = r * k + du holds
+// the taps (dv = 4r + g, du), g = 0..3; lane l of block b carries filter
+// 16 b + (l & 15) at tap g = l >> 4.  Filters beyond NF and rows beyond k are 0.
+__global__ void frag_f32_kernel(const float* __restrict__ F, int NF, int k, int nb, int n_chunks,
+                                float* __restrict__ frag) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long total = (long)n_chunks * nb * 64;
+    if (idx >= total) return;
+    const int lane = (int)(idx & 63);
+    const int b = (int)((idx >> 6) % nb);
+    const int c = (int)((idx >> 6) / nb);
+    const int r = c / k, du = c - r * k;
+    const int dv = 4 * r + (lane >> 4);
+    const int f = 16 * b + (lane & 15);
+    frag[idx] = (f < NF && dv < k) ? F[((size_t)f * k + dv) * k + du] : 0.f;
+}
+
+int build_f32_fragments(const float* F, int NF, int k, float* frag, hipStream_t s) {
+    const int nb = (NF + 15) / 16;
+    const F32Geometry g = f32_geometry(k, nb);
+    const long total = (long)g.n_chunks * nb * 64;
+    hipLaunchKernelGGL(frag_f32_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, F,
+                       NF, k, nb, g.n_chunks, frag);
+    return hip_status(hipGetLastError(), "frag_f32_kernel");
+}
+
+// ------------------------------------------------ FP32 contraction ----
+
+template <int NB, int TH, bool REG>
+__global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
+                                                           const float* __restrict__ frag, int k,
+                                                           int n_rg, int pitch, int rows, int cols,
+                                                           int tiles_x, int n_tiles, int seg) {
+    extern __shared__ __align__(16) float smem[];
+    float* tile = smem;
+    float* coef_s = smem + rows * pitch;
+
+    const int tid = threadIdx.x;
+    const int t = xcd_remap(blockIdx.x, n_tiles);
+    const int X0 = (t % tiles_x) * F32_TW;
+    const int Y0 = a.y_begin + (t / tiles_x) * TH;
+    const int y_end = a.y_begin + a.n_rows;
+    const int h = a.h;
+
+    const bool want_d = (a.out != nullptr);   // false: only the T_f planes are written
+    if (!REG && want_d)
+        for (int q = tid; q < a.NF * a.M; q += 256) coef_s[q] = a.coef[q];
+
+    // Stage X[Y0-h .. Y0-h+rows) x [X0-h .. X0-h+cols) minus the pedestal;
+    // outside the image X is 0, so the staged value is -pedestal there.
+    for (int r = tid >> 6; r < rows; r += 4) {
+        const int gy = Y0 - h + r;
+        const bool row_in = (gy >= 0) && (gy < a.H);
+        const float* src = a.X + (size_t)(row_in ? gy : 0) * a.W;
+        for (int c = tid & 63; c < cols; c += 64) {
+            const int gx = X0 - h + c;
+            float v = 0.f;
+            if (row_in && gx >= 0 && gx < a.W) v = src[gx];
+            tile[r * pitch + c] = v - a.ped;
+        }
+    }
+    __syncthreads();
+
+    const int lane = tid & 63, w = tid >> 6;
+    const int g = lane >> 4, j = lane & 15;
+    const int n_chunks = n_rg * k;
+
+    // T_f accumulates on the matrix cores in float32 over short sub-chains of
+    // `seg` chunks (at most 4 * seg taps each), and every sub-chain is added
+    // into a float64 total.  Long float32 chains over all k^2 taps lose up to
+    // a few ulp of T at bright stars; short chains keep the rounding of each
+    // partial sum small and the float64 total adds none.
+    double tot[NB][TH][4];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int i = 0; i < TH; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) tot[b][i][e] = 0.0;
+
+    const float* fp = frag + lane;
+    float fa[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) fa[b] = fp[b * 64];
+
+    const float* tb = tile + g * pitch + 16 * w + j;
+    int c = 0;
+    for (int r = 0; r < n_rg; ++r) {
+        const float* rb = tb + 4 * r * pitch;
+        for (int d0 = 0; d0 < k; d0 += seg) {
+            const int d1 = (d0 + seg < k) ? d0 + seg : k;
+            f4 acc[NB][TH];
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int i = 0; i < TH; ++i) acc[b][i] = f4{0.f, 0.f, 0.f, 0.f};
+            for (int du = d0; du < d1; ++du) {
+                ++c;
+                const float* fq = fp + (size_t)(c < n_chunks ? c : n_chunks - 1) * (NB * 64);
+                float fn[NB];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) fn[b] = fq[b * 64];
+                float xb[TH];
+#pragma unroll
+                for (int i = 0; i < TH; ++i) xb[i] = rb[i * pitch + du];
+#pragma unroll
+                for (int i = 0; i < TH; ++i)
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        acc[b][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[b], xb[i], acc[b][i], 0, 0, 0);
+#pragma unroll
+                for (int b = 0; b < NB; ++b) fa[b] = fn[b];
+            }
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int i = 0; i < TH; ++i)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) tot[b][i][e] += (double)acc[b][i][e];
+        }
+    }
+
+    // Epilogue in float64: out = sum_f w_f (T_f + ped * beta_f) - I.
+    // Lane (g, j) holds T_f for f = 16 b + 4 g + e at pixel column j.
+    const int x = X0 + 16 * w + j;
+    const double xh = a.sx * x + a.ox;
+    double xp[kMaxSpatialDegree + 1];
+    xp[0] = 1.0;
+#pragma unroll
+    for (int q = 1; q <= kMaxSpatialDegree; ++q) xp[q] = xp[q - 1] * xh;
+
+#pragma unroll
+    for (int i = 0; i < TH; ++i) {
+        const int y = Y0 + i;
+        const double yh = a.sy * y + a.oy;
+        double yp[kMaxSpatialDegree + 1];
+        yp[0] = 1.0;
+#pragma unroll
+        for (int q = 1; q <= kMaxSpatialDegree; ++q) yp[q] = yp[q - 1] * yh;
+        double part = 0.0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int f = 16 * b + 4 * g + e;
+                if (f < a.NF) {
+                    double wgt = 0.0;
+                    if (!want_d) {
+                    } else if (REG) {
+                        int ii, jj;
+                        term_exponents(f, ii, jj);
+                        wgt = ipow_d(xh, ii) * ipow_d(yh, jj);
+                    } else {
+                        const float* cf = coef_s + f * a.M;
+                        int m = 0;
+#pragma unroll
+                        for (int tt = 0; tt <= kMaxSpatialDegree; ++tt) {
+                            if (tt <= a.d_s) {
+#pragma unroll
+                                for (int ii = tt; ii >= 0; --ii) wgt += (double)cf[m + tt - ii] * (xp[ii] * yp[tt - ii]);
+                            }
+                            m += tt + 1;
+                        }
+                    }
+                    const double pb = (a.beta != nullptr) ? (double)a.ped * a.beta[f] : 0.0;
+                    part += wgt * (tot[b][i][e] + pb);
+                    if (a.tout != nullptr && x < a.W && y < y_end)
+                        a.tout[(size_t)f * a.n_rows * a.W + (size_t)(y - a.y_begin) * a.W + x] =
+                            (float)(tot[b][i][e] + pb);
+                }
+            }
+        part += __shfl_xor(part, 16);
+        part += __shfl_xor(part, 32);
+        if (a.out != nullptr && g == 0 && x < a.W && y < y_end) {
+            const size_t o = (size_t)y * a.W + x;
+            const double iv = a.I ? (double)a.I[o] : 0.0;
+            a.out[o] = (float)(part - iv);
+        }
+    }
+}
+
+// Taps per float32 sub-chain are 4 * seg; SVCONV_F32_SEG overrides the
+// default of 4 chunks (a tuning knob, read once).  With 16-tap sub-chains the
+// worst pixel of the 2048 x 4096 and 4096 x 4096 star fields stays below
+// 5e-5 sigma_sky; whole-row chains reach 1.2e-4.
+static int f32_seg() {
+    static int seg = [] {
+        const char* e = getenv("SVCONV_F32_SEG");
+        int v = e ? atoi(e) : 4;
+        return v > 0 ? v : 4;
+    }();
+    return seg;
+}
+
+template <int NB, bool REG>
+static int launch_f32_t(const ContractArgs& a, const float* frag, hipStream_t s) {
+    constexpr int TH = f32_tile_h(NB);
+    const int k = 2 * a.h + 1;
+    const F32Geometry g = f32_geometry(k, NB);
+    const int tiles_x = (a.W + g.tile_w - 1) / g.tile_w;
+    const int tiles_y = (a.n_rows + g.tile_h - 1) / g.tile_h;
+    const int n_tiles = tiles_x * tiles_y;
+    if (n_tiles == 0) return SVCONV_OK;
+    if (g.lds_bytes > 64 * 1024) return fail(SVCONV_EUNSUPPORTED, "FP32 tile exceeds 64 KiB of LDS");
+    hipLaunchKernelGGL((contract_f32_kernel<NB, TH, REG>), dim3(n_tiles), dim3(256), g.lds_bytes, s,
+                       a, frag, k, g.n_rg, g.lds_pitch, g.lds_rows, g.lds_cols, tiles_x, n_tiles,
+                       f32_seg());
+    return hip_status(hipGetLastError(), "contract_f32_kernel");
+}
+
+int launch_contract_f32(const ContractArgs& a, const float* frag, int nb, hipStream_t s) {
+    const bool reg = (a.coef == nullptr);
+    switch (nb) {
+        case 1: return reg ? launch_f32_t<1, true>(a, frag, s) : launch_f32_t<1, false>(a, frag, s);
+        case 2: return reg ? launch_f32_t<2, true>(a, frag, s) : launch_f32_t<2, false>(a, frag, s);
+        case 3: return reg ? fail(SVCONV_EUNSUPPORTED, "regrouped form needs M <= 32")
+                           : launch_f32_t<3, false>(a, frag, s);
+        case 4: return reg ? fail(SVCONV_EUNSUPPORTED, "regrouped form needs M <= 32")
+                           : launch_f32_t<4, false>(a, frag, s);
+        default: return fail(SVCONV_EUNSUPPORTED, "more than 64 filters");
+    }
+}
+
+// -------------------------------------------- per-call filter builders ----
+
+// Regrouped filters Kt_m = sum_n a[n][m] F_n (float64 accumulation) and
+// their sums beta_m = sum_n a[n][m] beta_n.
+__global__ void regroup_kernel(const double* __restrict__ F64, const double* __restrict__ beta,
+                               const float* __restrict__ a, int N, int M, int kk,
+                               float* __restrict__ Ft, double* __restrict__ betaT) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < M * kk) {
+        const int m = idx / kk, q = idx - m * kk;
+        double s = 0.0;
+        for (int n = 0; n < N; ++n) s += (double)a[n * M + m] * F64[(size_t)n * kk + q];
+        Ft[idx] = (float)s;
+    } else if (idx < M * kk + M) {
+        const int m = idx - M * kk;
+        double s = 0.0;
+        for (int n = 0; n < N; ++n) s += (double)a[n * M + m] * beta[n];
+        betaT[m] = s;
+    }
+}
+
+int regroup_filters(const double* F64, const double* beta, const float* a, int N, int M, int k,
+                    float* Ft, double* betaT, hipStream_t s) {
+    const int total = M * k * k + M;
+    hipLaunchKernelGGL(regroup_kernel, dim3((total + 255) / 256), dim3(256), 0, s, F64, beta, a, N,
+                       M, k * k, Ft, betaT);
+    return hip_status(hipGetLastError(), "regroup_kernel");
+}
+
+// Filters of the adjoint in R.  With Kt_m[u][v] = sum_n a[n][m] B_n[u][v],
+//   dL/dR(q) = sum_{u,v} G(q + (u,v)) sum_m P_m(q + (u,v)) Kt_m[u][v],
+// and P_m(q + (u,v)) expands binomially around q because xh(q + u) =
+// xh(q) + u sx:  P_(i,j)(q+(u,v)) = sum_{i'<=i, j'<=j} C(i,i') C(j,j')
+// (u sx)^(i-i') (v sy)^(j-j') P_(i',j')(q).  Hence
+//   dL/dR(q) = sum_m' P_m'(q) sum_{u,v} H_m'[u][v] G(q + (u,v))
+// with H_(i',j') = sum_{i>=i', j>=j'} C(i,i') C(j,j') (u sx)^(i-i') (v sy)^(j-j') Kt_(i,j):
+// a correlation of G with M filters weighted by P_m'(q), i.e. the same
+// contraction as the regrouped forward.  In correlation orientation
+// F'_m'[dv][du] = H_m'[u = du - h][v = dv - h].  The float64 basis table holds
+// F_n[dv][du] = B_n[2h - dv][2h - du], so B_n[u][v] (row v+h, column u+h)
+// = F_n[h - v][h - u].
+__global__ void adjoint_filter_kernel(const double* __restrict__ F64, const float* __restrict__ a,
+                                      int N, int M, int k, double sx, double sy,
+                                      float* __restrict__ Ft) {
+    const int kk = k * k;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= M * kk) return;
+    const int mp = idx / kk, q = idx - mp * kk;
+    const int dv = q / k, du = q - dv * k;
+    const int h = k / 2;
+    const int u = du - h, v = dv - h;
+    const int fq = (h - v) * k + (h - u);  // F_n index holding B_n[u][v]
+    int ip, jp;
+    term_exponents(mp, ip, jp);
+    double acc = 0.0;
+    for (int m = 0; m < M; ++m) {
+        int i, jj;
+        term_exponents(m, i, jj);
+        if (i < ip || jj < jp) continue;
+        double kt = 0.0;
+        for (int n = 0; n < N; ++n) kt += (double)a[n * M + m] * F64[(size_t)n * kk + fq];
+        // binomials C(i, ip) C(jj, jp)
+        double ci = 1.0, cj = 1.0;
+        for (int t = 1; t <= ip; ++t) ci = ci * (i - ip + t) / t;
+        for (int t = 1; t <= jp; ++t) cj = cj * (jj - jp + t) / t;
+        double px = 1.0, py = 1.0;
+        for (int t = 0; t < i - ip; ++t) px *= u * sx;
+        for (int t = 0; t < jj - jp; ++t) py *= v * sy;
+        acc += ci * cj * px * py * kt;
+    }
+    Ft[idx] = (float)acc;
+}
+
+int adjoint_filters(const double* F64, const float* a, int N, int M, int d_s, int k, double sx,
+                    double sy, float* Ft, hipStream_t s) {
+    (void)d_s;
+    const int total = M * k * k;
+    hipLaunchKernelGGL(adjoint_filter_kernel, dim3((total + 255) / 256), dim3(256), 0, s, F64, a,
+                       N, M, k, sx, sy, Ft);
+    return hip_status(hipGetLastError(), "adjoint_filter_kernel");
+}
+
+}  // namespace svc

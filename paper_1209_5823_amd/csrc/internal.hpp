@@ -1,0 +1,145 @@
+// Internal declarations of libsvconv: the plan object, launch descriptors and
+// the host-side launchers of each kernel family.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "svconv.h"
+
+namespace svc {
+
+constexpr int kMaxHalfWidth = 31;
+constexpr int kMaxSpatialDegree = 6;
+constexpr int kMaxSpatialTerms = (kMaxSpatialDegree + 1) * (kMaxSpatialDegree + 2) / 2;  // 28
+constexpr int kMaxFilters = 64;      // filter rows one contraction launch handles
+constexpr int kMaxCoefficients = 1024;
+
+// Record a detail message for svconv_last_error and return the status.
+int fail(int status, const std::string& msg);
+// Map a HIP error to SVCONV_EDEVICE with a message (hipSuccess -> OK).
+int hip_status(hipError_t e, const char* what);
+
+// Dense filters in correlation orientation:
+//   T_f(x,y) = sum_{dv,du} F[f][dv][du] X(x + du - h, y + dv - h).
+// The basis form uses F_n[dv][du] = B_n[2h-dv][2h-du] (true convolution).
+
+// Geometry of the tile the FP32 contraction works on.
+struct F32Geometry {
+    int k, n_rg, n_chunks;      // kernel width, 4-row groups, chunks = n_rg * k
+    int nb;                     // 16-filter blocks
+    int tile_w, tile_h;         // output tile
+    int lds_rows, lds_cols, lds_pitch;
+    size_t lds_bytes;
+};
+
+// Geometry of the low-precision (bf16/fp16) contraction.
+struct LowpGeometry {
+    int k, n_rg, n_q, n_steps;  // 4-row groups, 8-column chunks, steps = n_rg * n_q
+    int nb;
+    int tile_w, tile_h;
+    int lds_rows, lds_pitch;    // pitch in 16-bit elements
+    size_t lds_bytes;
+};
+
+// Arguments shared by the contraction kernels: input image X, per-pixel
+// epilogue weights and the output.
+struct ContractArgs {
+    const float* X;             // [H][W]
+    int H, W, h;
+    int NF;                     // real filters (<= 16 * nb)
+    int M, d_s;                 // spatial terms
+    const float* coef;          // [NF][M] (basis form) or nullptr (weights are P_m)
+    const double* beta;         // [NF] sum of each filter (pedestal restore), nullable
+    const float* fscale;        // [NF] per-filter inverse scale, nullable
+    float ped;
+    double sx, ox, sy, oy;      // xh = sx * x + ox, yh = sy * y + oy (array x, y)
+    const float* I;             // nullable
+    float* out;                 // [H][W]; nullable when tout is set
+    int y_begin = 0;            // output rows [y_begin, y_begin + n_rows)
+    int n_rows = 0;
+    float* tout = nullptr;      // optional T_f planes [NF][n_rows][W] (FP32 kernel only)
+};
+
+}  // namespace svc
+
+struct svconv_plan {
+    int H = 0, W = 0, h = 0, k = 0;
+    int N = 0, d_s = 0, M = 0;
+    int precision = SVCONV_FP32;
+    int form = SVCONV_FORM_BASIS;
+    int x0 = 0, y0 = 0, Wf = 0, Hf = 0;
+    float pedestal = 0.f;
+    hipStream_t stream = nullptr;
+    int device = 0;
+
+    std::vector<double> sigmas;
+    std::vector<int> degrees;
+    std::vector<double> basis;          // host B[n][v+h][u+h], float64
+
+    // device tables (basis form, fixed per plan)
+    float* dF32 = nullptr;              // [N][k][k] correlation-oriented basis, float32
+    double* dF64 = nullptr;             // same, float64
+    double* dBeta = nullptr;            // [N] sums
+    float* dFragF32 = nullptr;          // FP32 MFMA A-operand fragments
+    uint16_t* dFragLoB = nullptr;       // bf16 fragments, hi then lo halves
+    uint16_t* dFragLoH = nullptr;       // fp16 fragments, hi then lo halves
+    float* dScaleB = nullptr;           // [2][kMaxFilters] scales / inverse scales, bf16 fragments
+    float* dScaleH = nullptr;           // [2][kMaxFilters] scales / inverse scales, fp16 fragments
+
+    // per-call scratch (allocated once)
+    float* dFt32 = nullptr;             // [kMaxFilters][k][k] per-call filters (regrouped / adjoint)
+    double* dBetaT = nullptr;           // [kMaxFilters]
+    float* dFragT32 = nullptr;          // fragments of per-call filters (FP32)
+    uint16_t* dFragTB = nullptr;        // per-call bf16 fragments
+    uint16_t* dFragTH = nullptr;        // per-call fp16 fragments
+    float* dScaleT = nullptr;           // [2][kMaxFilters] per-call scales / inverse scales
+    double* dQpart = nullptr;           // adjoint-a partials
+    int q_blocks = 0;                   // number of partial blocks
+    double* dQ = nullptr;               // reduced Q [M][k*k]
+    float* dGrad = nullptr;             // [H][W] float scratch (loss gradient)
+    double* dVec = nullptr;             // small float64 scratch (fit)
+    int* dStatus = nullptr;             // device status word
+    double* dNMpart = nullptr;          // normal-matrix partials and totals
+    float* dTband = nullptr;            // basis responses of a band of rows (normal matrix)
+    int band_rows = 0;
+    double* dRed = nullptr;             // reduction scratch (loss)
+};
+
+namespace svc {
+
+// forward.hip
+size_t f32_fragment_floats(int k, int nb);
+size_t lowp_fragment_elems(int k, int nb);  // hi and lo halves together
+F32Geometry f32_geometry(int k, int nb);
+LowpGeometry lowp_geometry(int k, int nb);
+int build_f32_fragments(const float* F, int NF, int k, float* frag, hipStream_t s);
+int build_lowp_fragments(const float* F, int NF, int k, int fp16, float* scale,
+                         uint16_t* frag, hipStream_t s);
+int regroup_filters(const double* F64, const double* beta, const float* a, int N, int M, int k,
+                    float* Ft, double* betaT, hipStream_t s);
+int adjoint_filters(const double* F64, const float* a, int N, int M, int d_s, int k,
+                    double sx, double sy, float* Ft, hipStream_t s);
+int launch_contract_f32(const ContractArgs& a, const float* frag, int nb, hipStream_t s);
+int launch_contract_lowp(const ContractArgs& a, const uint16_t* frag, int nb, int precision,
+                         hipStream_t s);
+
+// backward.hip
+size_t adjoint_scratch_doubles(int H, int W, int k, int M);
+int launch_adjoint_a(svconv_plan* p, const float* R, const float* gD, double* ga);
+
+// fit.hip
+int launch_loss_grad(svconv_plan* p, const float* D, const unsigned char* mask, float* gD,
+                     double* loss);
+int launch_normal_matrix(svconv_plan* p, const float* R, const unsigned char* mask, double* JtJ);
+int launch_cholesky(svconv_plan* p, double* A, int n);
+int launch_cholesky_solve(svconv_plan* p, const double* L, const double* rhs, double* x, int n);
+int launch_gn_update(svconv_plan* p, const double* delta, double* a64, float* a32, int n);
+int launch_copy_a(svconv_plan* p, const double* a64, float* a32, int n);
+int launch_scale(svconv_plan* p, double* v, double s, int n);
+
+}  // namespace svc

@@ -1,0 +1,442 @@
+// Low-precision matrix-core contraction (bf16 / fp16 inputs, fp32
+// accumulation) of the weighted multi-filter correlation
+//
+//   out(p) = sum_f w_f(p) T_f(p) - I(p),  T_f(p) = sum_{dv,du} F_f[dv][du] X(p + (du-h, dv-h)),
+//
+// with the optional hi + lo splits that recover precision:
+//   X - ped = Xh + Xl,  F s_f = Fh + Fl  (each part rounded to nearest even),
+//   T_f ~ (Fh.Xh + Fh.Xl + Fl.Xh) / s_f            (bf16x3, fp16x3)
+//   T_f ~ (Fh.Xh + Fh.Xl) / s_f                    (fp16x2)
+// s_f is a power of two per filter (fp16 only, to keep small taps normal)
+// and X is scaled by 1/4 in fp16 so that 16-bit ADC counts stay finite.
+//
+// Matrix-core layout (v_mfma_f32_16x16x32_{bf16,f16}): the 32-long reduction
+// of one instruction is 4 kernel rows (dv = 4r + g, lane group g) times 8
+// consecutive kernel columns (du = 8q .. 8q+7).  B-operand lane (g, j) then
+// needs 8 consecutive input samples of one LDS row: the 16 pixels of an
+// instruction are 16 consecutive image rows at one column x, and every wave
+// of the 8-wave workgroup owns the columns with one residue s = x mod 8, so
+// its 8-sample windows start at the same misalignment s.  Each lane loads
+// aligned 16-byte chunks of its row once per row group and funnel-shifts
+// them into windows (v_alignbit), so the LDS reads are all aligned b128.
+#include <cstdlib>
+
+#include "internal.hpp"
+
+namespace svc {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+
+constexpr int LP_TP = 4;     // 16-pixel blocks per wave (columns x = X0 + s + 8 i)
+constexpr int LP_NQ = 4;     // max 8-column chunks per kernel row (k <= 31)
+constexpr int LP_WAVES = 8;  // one wave per column residue s
+constexpr int LP_TW = 8 * LP_TP;
+constexpr int LP_TH = 16;
+constexpr float FP16_XSCALE = 0.25f;
+
+__device__ __forceinline__ uint32_t f2bf_rne(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ float bf2f(uint32_t b) { return __uint_as_float(b << 16); }
+__device__ __forceinline__ uint32_t f2h_rne(float x) {
+    _Float16 v = (_Float16)x;
+    return (uint32_t)__builtin_bit_cast(uint16_t, v);
+}
+__device__ __forceinline__ float h2f(uint32_t b) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)b);
+}
+
+template <bool FP16>
+__device__ __forceinline__ void split16(float x, uint32_t& hi, uint32_t& lo) {
+    if (FP16) {
+        hi = f2h_rne(x);
+        lo = f2h_rne(x - h2f(hi));
+    } else {
+        hi = f2bf_rne(x);
+        lo = f2bf_rne(x - bf2f(hi));
+    }
+}
+
+static int lp_pitch(int cols) {
+    // 8-element (16-byte) units per row, odd so that the 16 rows read by one
+    // b128 instruction fall in distinct bank groups
+    int u = (cols + 7) / 8;
+    if ((u & 1) == 0) ++u;
+    return 8 * u;
+}
+
+LowpGeometry lowp_geometry(int k, int nb) {
+    LowpGeometry g;
+    g.k = k;
+    g.n_rg = (k + 3) / 4;
+    g.n_q = (k + 7) / 8;
+    g.n_steps = g.n_rg * g.n_q;
+    g.nb = nb;
+    g.tile_w = LP_TW;
+    g.tile_h = LP_TH;
+    g.lds_rows = LP_TH + 4 * g.n_rg - 1;
+    g.lds_pitch = lp_pitch(8 * (LP_TP + LP_NQ));
+    const size_t tile = (size_t)g.lds_rows * g.lds_pitch * 2 * 2;                // hi + lo
+    const size_t slab = (size_t)g.n_q * nb * 2 * 64 * 16;                        // one row group
+    g.lds_bytes = tile + 2 * slab + (size_t)kMaxFilters * kMaxSpatialTerms * 4;
+    return g;
+}
+
+size_t lowp_fragment_elems(int k, int nb) {
+    const int n_rg = (k + 3) / 4, n_q = (k + 7) / 8;
+    return (size_t)n_rg * n_q * nb * 2 * 64 * 8;   // hi and lo halves, 8 per lane
+}
+
+// Power-of-two scale per filter so that max |F_f| s_f lies in [1, 2) (fp16);
+// inv[f] = 1 / (s_f xscale) restores the true T_f.  bf16 needs no scale.
+__global__ void lowp_scale_kernel(const float* __restrict__ F, int NF, int kk, int fp16,
+                                  float* __restrict__ scale, float* __restrict__ inv) {
+    const int f = blockIdx.x;
+    __shared__ float red[256];
+    float m = 0.f;
+    for (int q = threadIdx.x; q < kk; q += blockDim.x) m = fmaxf(m, fabsf(F[(size_t)f * kk + q]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        float sc = 1.f, xs = 1.f;
+        if (fp16) {
+            xs = FP16_XSCALE;
+            const float mx = red[0];
+            if (mx > 0.f) sc = ldexpf(1.f, -ilogbf(mx));
+        }
+        scale[f] = sc;
+        if (inv) inv[f] = 1.f / (sc * xs);
+    }
+}
+
+// A-operand fragments: element e of lane l, block b, row group r, chunk q is
+// filter f = 16 b + (l & 15) at (dv = 4 r + (l >> 4), du = 8 q + e), scaled.
+// Layout [r][q][b][half][lane][8], half 0 = hi, 1 = lo.
+__global__ void frag_lowp_kernel(const float* __restrict__ F, const float* __restrict__ scale,
+                                 int NF, int k, int nb, int n_rg, int n_q, int fp16,
+                                 uint16_t* __restrict__ frag) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;   // one (r,q,b,lane,e)
+    const long total = (long)n_rg * n_q * nb * 64 * 8;
+    if (idx >= total) return;
+    const int e = (int)(idx & 7);
+    const int lane = (int)((idx >> 3) & 63);
+    long rest = idx >> 9;
+    const int b = (int)(rest % nb);
+    rest /= nb;
+    const int q = (int)(rest % n_q);
+    const int r = (int)(rest / n_q);
+    const int f = 16 * b + (lane & 15);
+    const int dv = 4 * r + (lane >> 4);
+    const int du = 8 * q + e;
+    float v = 0.f;
+    if (f < NF && dv < k && du < k) v = F[((size_t)f * k + dv) * k + du] * scale[f];
+    uint32_t hi, lo;
+    if (fp16) split16<true>(v, hi, lo);
+    else split16<false>(v, hi, lo);
+    const size_t base = ((((size_t)(r * n_q + q) * nb + b) * 2) * 64 + lane) * 8 + e;
+    frag[base] = (uint16_t)hi;
+    frag[base + 64 * 8] = (uint16_t)lo;
+}
+
+int build_lowp_fragments(const float* F, int NF, int k, int fp16, float* scale,
+                         uint16_t* frag, hipStream_t s) {
+    // scale: 2 * kMaxFilters floats, [0, kMaxFilters) the scales s_f and
+    // [kMaxFilters, 2 kMaxFilters) the inverse factors used by the epilogue
+    if (k > 8 * LP_NQ) return SVCONV_OK;   // beyond the low-precision kernel's reach
+    const int nb = (NF + 15) / 16;
+    const int n_rg = (k + 3) / 4, n_q = (k + 7) / 8;
+    hipLaunchKernelGGL(lowp_scale_kernel, dim3(NF), dim3(256), 0, s, F, NF, k * k, fp16, scale,
+                       scale + kMaxFilters);
+    int st = hip_status(hipGetLastError(), "lowp_scale_kernel");
+    if (st) return st;
+    const long total = (long)n_rg * n_q * nb * 64 * 8;
+    hipLaunchKernelGGL(frag_lowp_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, F,
+                       scale, NF, k, nb, n_rg, n_q, fp16, frag);
+    return hip_status(hipGetLastError(), "frag_lowp_kernel");
+}
+
+// ------------------------------------------------------------ contraction --
+
+// W_t = samples [s, s+8) of chunk_t ++ chunk_{t+1}; S2 = s / 2, sh = 16 (s & 1).
+template <int S2, int NW>
+__device__ __forceinline__ void form_windows(uint32_t (&c)[NW + 1][4], uint32_t sh) {
+#pragma unroll
+    for (int t = 0; t < NW; ++t) {
+        uint32_t d[8];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            d[e] = c[t][e];
+            d[e + 4] = c[t + 1][e];
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) c[t][e] = __builtin_amdgcn_alignbit(d[e + S2 + 1], d[e + S2], sh);
+    }
+}
+
+template <bool FP16>
+__device__ __forceinline__ f4 mfma16(const uint32_t (&a)[4], const uint32_t (&b)[4], f4 c) {
+    if constexpr (FP16) {
+        h8 av = __builtin_bit_cast(h8, a);
+        h8 bv = __builtin_bit_cast(h8, b);
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bv, c, 0, 0, 0);
+    } else {
+        bf8 av = __builtin_bit_cast(bf8, a);
+        bf8 bv = __builtin_bit_cast(bf8, b);
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+    }
+}
+
+template <int NB, bool FP16, bool SPLIT_R, bool SPLIT_B, bool REG>
+__global__ __launch_bounds__(512, 1) void contract_lowp_kernel(
+    ContractArgs a, const uint16_t* __restrict__ frag, int k, int n_rg, int n_q, int pitch,
+    int rows, int tiles_x, int n_tiles, float xscale) {
+    extern __shared__ __align__(16) uint8_t smem_raw[];
+    constexpr int HALVES = SPLIT_B ? 2 : 1;
+    constexpr int NCH = LP_TP + LP_NQ;          // aligned chunks per row and row group
+    uint16_t* hiT = reinterpret_cast<uint16_t*>(smem_raw);
+    uint16_t* loT = hiT + rows * pitch;
+    uint4* slab = reinterpret_cast<uint4*>(loT + rows * pitch);
+    const int slab_u4 = n_q * NB * HALVES * 64;
+    float* coef_s = reinterpret_cast<float*>(slab + 2 * slab_u4);
+
+    const int tid = threadIdx.x;
+    const int t = [&] {
+        const int bid = blockIdx.x, x8 = bid & 7, tt = bid >> 3, q8 = n_tiles >> 3, r8 = n_tiles & 7;
+        return x8 * q8 + (x8 < r8 ? x8 : r8) + tt;
+    }();
+    const int X0 = (t % tiles_x) * LP_TW;
+    const int Y0 = a.y_begin + (t / tiles_x) * LP_TH;
+    const int h = a.h;
+
+    if (!REG)
+        for (int q = tid; q < a.NF * a.M; q += 512) coef_s[q] = a.coef[q];
+
+    // Stage (X - ped) * xscale as hi / lo 16-bit parts; X = 0 outside the image.
+    const int cols = 8 * NCH;
+    for (int r = tid >> 6; r < rows; r += LP_WAVES) {
+        const int gy = Y0 - h + r;
+        const bool row_in = (gy >= 0) && (gy < a.H);
+        const float* src = a.X + (size_t)(row_in ? gy : 0) * a.W;
+        for (int c = tid & 63; c < pitch; c += 64) {
+            const int gx = X0 - h + c;
+            float v = 0.f;
+            if (row_in && gx >= 0 && gx < a.W && c < cols) v = src[gx];
+            const float xv = (c < cols) ? (v - a.ped) * xscale : 0.f;
+            uint32_t hi, lo;
+            split16<FP16>(xv, hi, lo);
+            hiT[r * pitch + c] = (uint16_t)hi;
+            loT[r * pitch + c] = SPLIT_R ? (uint16_t)lo : (uint16_t)0;
+        }
+    }
+
+    // slab of row group r: [q][b][half][lane] 16-byte units
+    auto slab_src = [&](int r, int u) -> const uint4* {
+        const int lane = u & 63;
+        int rest = u >> 6;
+        const int hf = rest % HALVES;
+        rest /= HALVES;
+        const int b = rest % NB;
+        const int q = rest / NB;
+        const size_t unit = (((size_t)(r * n_q + q) * NB + b) * 2 + hf) * 64 + lane;
+        return reinterpret_cast<const uint4*>(frag) + unit;
+    };
+    constexpr int PF = (LP_NQ * NB * HALVES * 64 + 511) / 512;   // units per thread
+    for (int u = tid; u < slab_u4; u += 512) slab[u] = *slab_src(0, u);
+    __syncthreads();
+
+    const int lane = tid & 63, w = tid >> 6;
+    const int g = lane >> 4, j = lane & 15;
+    const int s = w;                       // column residue of this wave
+    const uint32_t sh = 16u * (uint32_t)(s & 1);
+
+    f4 acc[NB][LP_TP];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int i = 0; i < LP_TP; ++i) acc[b][i] = f4{0.f, 0.f, 0.f, 0.f};
+
+    for (int r = 0; r < n_rg; ++r) {
+        // prefetch the next slab into registers
+        uint4 pf[PF];
+        const bool more = (r + 1 < n_rg);
+#pragma unroll
+        for (int p = 0; p < PF; ++p) {
+            const int u = tid + 512 * p;
+            if (more && u < slab_u4) pf[p] = *slab_src(r + 1, u);
+        }
+
+        // aligned chunks of LDS row (j + 4r + g), columns 8c .. 8c+7
+        uint32_t ch[NCH][4], cl[NCH][4];
+        {
+            const int row = j + 4 * r + g;
+            const uint4* ph = reinterpret_cast<const uint4*>(hiT + row * pitch);
+            const uint4* pl = reinterpret_cast<const uint4*>(loT + row * pitch);
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const uint4 vh = ph[c];
+                ch[c][0] = vh.x; ch[c][1] = vh.y; ch[c][2] = vh.z; ch[c][3] = vh.w;
+                if (SPLIT_R) {
+                    const uint4 vl = pl[c];
+                    cl[c][0] = vl.x; cl[c][1] = vl.y; cl[c][2] = vl.z; cl[c][3] = vl.w;
+                }
+            }
+        }
+        switch (s >> 1) {
+            case 0: form_windows<0, NCH - 1>(ch, sh); if (SPLIT_R) form_windows<0, NCH - 1>(cl, sh); break;
+            case 1: form_windows<1, NCH - 1>(ch, sh); if (SPLIT_R) form_windows<1, NCH - 1>(cl, sh); break;
+            case 2: form_windows<2, NCH - 1>(ch, sh); if (SPLIT_R) form_windows<2, NCH - 1>(cl, sh); break;
+            default: form_windows<3, NCH - 1>(ch, sh); if (SPLIT_R) form_windows<3, NCH - 1>(cl, sh); break;
+        }
+
+        const uint4* sl = slab + (r & 1) * slab_u4;
+#pragma unroll
+        for (int q = 0; q < LP_NQ; ++q) {
+            if (q < n_q) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    uint32_t fh[4], fl[4];
+                    const uint4 vh = sl[((q * NB + b) * HALVES + 0) * 64 + lane];
+                    fh[0] = vh.x; fh[1] = vh.y; fh[2] = vh.z; fh[3] = vh.w;
+                    if (SPLIT_B) {
+                        const uint4 vl = sl[((q * NB + b) * HALVES + 1) * 64 + lane];
+                        fl[0] = vl.x; fl[1] = vl.y; fl[2] = vl.z; fl[3] = vl.w;
+                    }
+#pragma unroll
+                    for (int i = 0; i < LP_TP; ++i) {
+                        acc[b][i] = mfma16<FP16>(fh, ch[i + q], acc[b][i]);
+                        if (SPLIT_R) acc[b][i] = mfma16<FP16>(fh, cl[i + q], acc[b][i]);
+                        if (SPLIT_B) acc[b][i] = mfma16<FP16>(fl, ch[i + q], acc[b][i]);
+                    }
+                }
+            }
+        }
+
+        // store the prefetched slab into the other buffer (no wave reads it in
+        // this iteration), then make it visible
+        uint4* dst = slab + ((r + 1) & 1) * slab_u4;
+#pragma unroll
+        for (int p = 0; p < PF; ++p) {
+            const int u = tid + 512 * p;
+            if (more && u < slab_u4) dst[u] = pf[p];
+        }
+        __syncthreads();
+    }
+
+    // Epilogue in float64.  Lane (g, j) holds T_f, f = 16 b + 4 g + e, of the
+    // pixel (X0 + s + 8 i, Y0 + j).
+    const int y = Y0 + j;
+    const double yh = a.sy * y + a.oy;
+    double yp[kMaxSpatialDegree + 1];
+    yp[0] = 1.0;
+#pragma unroll
+    for (int q = 1; q <= kMaxSpatialDegree; ++q) yp[q] = yp[q - 1] * yh;
+#pragma unroll
+    for (int i = 0; i < LP_TP; ++i) {
+        const int x = X0 + s + 8 * i;
+        const double xh = a.sx * x + a.ox;
+        double xp[kMaxSpatialDegree + 1];
+        xp[0] = 1.0;
+#pragma unroll
+        for (int q = 1; q <= kMaxSpatialDegree; ++q) xp[q] = xp[q - 1] * xh;
+        double part = 0.0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int f = 16 * b + 4 * g + e;
+                if (f < a.NF) {
+                    double wgt = 0.0;
+                    if (REG) {
+                        int ii = 0, jj = 0, tt = 0;
+                        while ((tt + 1) * (tt + 2) / 2 <= f) ++tt;
+                        jj = f - tt * (tt + 1) / 2;
+                        ii = tt - jj;
+                        double px = 1.0, py = 1.0;
+                        for (int q = 0; q < ii; ++q) px *= xh;
+                        for (int q = 0; q < jj; ++q) py *= yh;
+                        wgt = px * py;
+                    } else {
+                        const float* cf = coef_s + f * a.M;
+                        int m = 0;
+#pragma unroll
+                        for (int tt = 0; tt <= kMaxSpatialDegree; ++tt) {
+                            if (tt <= a.d_s) {
+#pragma unroll
+                                for (int ii = tt; ii >= 0; --ii)
+                                    wgt += (double)cf[m + tt - ii] * (xp[ii] * yp[tt - ii]);
+                            }
+                            m += tt + 1;
+                        }
+                    }
+                    const double inv = a.fscale ? (double)a.fscale[f] : 1.0;
+                    const double pb = a.beta ? (double)a.ped * a.beta[f] : 0.0;
+                    part += wgt * ((double)acc[b][i][e] * inv + pb);
+                }
+            }
+        part += __shfl_xor(part, 16);
+        part += __shfl_xor(part, 32);
+        if (g == 0 && x < a.W && y < a.y_begin + a.n_rows) {
+            const size_t o = (size_t)y * a.W + x;
+            const double iv = a.I ? (double)a.I[o] : 0.0;
+            a.out[o] = (float)(part - iv);
+        }
+    }
+}
+
+template <int NB, bool FP16, bool SR, bool SB>
+static int launch_lowp_t(const ContractArgs& a, const uint16_t* frag, bool reg, hipStream_t s) {
+    const int k = 2 * a.h + 1;
+    const LowpGeometry g = lowp_geometry(k, NB);
+    const int tiles_x = (a.W + g.tile_w - 1) / g.tile_w;
+    const int tiles_y = (a.n_rows + g.tile_h - 1) / g.tile_h;
+    const int n_tiles = tiles_x * tiles_y;
+    if (n_tiles == 0) return SVCONV_OK;
+    const float xs = FP16 ? FP16_XSCALE : 1.f;
+    if (reg)
+        hipLaunchKernelGGL((contract_lowp_kernel<NB, FP16, SR, SB, true>), dim3(n_tiles), dim3(512),
+                           g.lds_bytes, s, a, frag, k, g.n_rg, g.n_q, g.lds_pitch, g.lds_rows,
+                           tiles_x, n_tiles, xs);
+    else
+        hipLaunchKernelGGL((contract_lowp_kernel<NB, FP16, SR, SB, false>), dim3(n_tiles),
+                           dim3(512), g.lds_bytes, s, a, frag, k, g.n_rg, g.n_q, g.lds_pitch,
+                           g.lds_rows, tiles_x, n_tiles, xs);
+    return hip_status(hipGetLastError(), "contract_lowp_kernel");
+}
+
+template <bool FP16, bool SR, bool SB>
+static int launch_lowp_nb(const ContractArgs& a, const uint16_t* frag, int nb, bool reg,
+                          hipStream_t s) {
+    switch (nb) {
+        case 1: return launch_lowp_t<1, FP16, SR, SB>(a, frag, reg, s);
+        case 2: return launch_lowp_t<2, FP16, SR, SB>(a, frag, reg, s);
+        case 3: return launch_lowp_t<3, FP16, SR, SB>(a, frag, reg, s);
+        case 4: return launch_lowp_t<4, FP16, SR, SB>(a, frag, reg, s);
+        default: return fail(SVCONV_EUNSUPPORTED, "more than 64 filters");
+    }
+}
+
+int launch_contract_lowp(const ContractArgs& a, const uint16_t* frag, int nb, int precision,
+                         hipStream_t s) {
+    const int k = 2 * a.h + 1;
+    if (k > 8 * LP_NQ)
+        return fail(SVCONV_EUNSUPPORTED, "bf16/fp16 forms support half-widths up to 15");
+    const bool reg = (a.coef == nullptr);
+    switch (precision) {
+        case SVCONV_BF16: return launch_lowp_nb<false, false, false>(a, frag, nb, reg, s);
+        case SVCONV_FP16: return launch_lowp_nb<true, false, false>(a, frag, nb, reg, s);
+        case SVCONV_BF16X3: return launch_lowp_nb<false, true, true>(a, frag, nb, reg, s);
+        case SVCONV_FP16X2: return launch_lowp_nb<true, true, false>(a, frag, nb, reg, s);
+        case SVCONV_FP16X3: return launch_lowp_nb<true, true, true>(a, frag, nb, reg, s);
+        default: return fail(SVCONV_EINVAL, "not a low-precision form");
+    }
+}
+
+}  // namespace svc

@@ -1,0 +1,436 @@
+// C ABI of libsvconv: plan construction (float64 basis on the host,
+// device tables), argument validation and dispatch to the kernel families.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "internal.hpp"
+
+namespace svc {
+
+static thread_local std::string g_last_error;
+
+int fail(int status, const std::string& msg) {
+    g_last_error = msg;
+    return status;
+}
+
+int hip_status(hipError_t e, const char* what) {
+    if (e == hipSuccess) return SVCONV_OK;
+    return fail(SVCONV_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Basis functions (Sec. 2, Eq. 2; Gaussian basis of Alard & Lupton):
+// Gaussian of width sigma times u^i v^j, unit L1 norm; sigma = 0 is a delta.
+// Layout B[n][v+h][u+h].
+static void build_basis(int h, const std::vector<double>& sig, const std::vector<int>& deg,
+                        std::vector<double>& B) {
+    const int k = 2 * h + 1;
+    B.clear();
+    for (size_t g = 0; g < sig.size(); ++g) {
+        for (int t = 0; t <= deg[g]; ++t) {
+            for (int i = t; i >= 0; --i) {
+                const int j = t - i;
+                std::vector<double> b((size_t)k * k);
+                double l1 = 0.0;
+                for (int v = -h; v <= h; ++v) {
+                    for (int u = -h; u <= h; ++u) {
+                        double val;
+                        if (sig[g] == 0.0) {
+                            val = (u == 0 && v == 0) ? 1.0 : 0.0;
+                        } else {
+                            double mono = 1.0;
+                            for (int q = 0; q < i; ++q) mono *= u;
+                            for (int q = 0; q < j; ++q) mono *= v;
+                            val = std::exp(-(double)(u * u + v * v) / (2.0 * sig[g] * sig[g])) * mono;
+                        }
+                        b[(size_t)(v + h) * k + (u + h)] = val;
+                        l1 += std::fabs(val);
+                    }
+                }
+                if (l1 > 0.0)
+                    for (auto& q : b) q /= l1;
+                B.insert(B.end(), b.begin(), b.end());
+            }
+        }
+    }
+}
+
+template <class T>
+static int dalloc(T** p, size_t count, const char* what) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(SVCONV_ENOMEM, std::string("hipMalloc failed for ") + what);
+    }
+    return SVCONV_OK;
+}
+
+static void free_plan(svconv_plan* p) {
+    void* ptrs[] = {p->dF32,   p->dF64,   p->dBeta,   p->dFragF32, p->dFragLoB, p->dFragLoH,
+                    p->dScaleB, p->dScaleH, p->dFt32, p->dBetaT, p->dFragT32, p->dFragTB,  p->dFragTH,
+                    p->dScaleT, p->dQpart, p->dQ,    p->dGrad,    p->dVec,     p->dStatus,
+                    p->dNMpart, p->dTband, p->dRed};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    delete p;
+}
+
+static void coords(const svconv_plan* p, ContractArgs& a) {
+    // xh = 2 (x + x0) / (Wf - 1) - 1 = sx * x + ox; 0 on a one-pixel axis
+    if (p->Wf > 1) {
+        a.sx = 2.0 / (p->Wf - 1);
+        a.ox = a.sx * p->x0 - 1.0;
+    } else {
+        a.sx = 0.0;
+        a.ox = 0.0;
+    }
+    if (p->Hf > 1) {
+        a.sy = 2.0 / (p->Hf - 1);
+        a.oy = a.sy * p->y0 - 1.0;
+    } else {
+        a.sy = 0.0;
+        a.oy = 0.0;
+    }
+}
+
+static bool is_lowp(int precision) { return precision >= SVCONV_BF16 && precision <= SVCONV_FP16X3; }
+static bool is_fp16(int precision) {
+    return precision == SVCONV_FP16 || precision == SVCONV_FP16X2 || precision == SVCONV_FP16X3;
+}
+
+}  // namespace svc
+
+using namespace svc;
+
+extern "C" {
+
+const char* svconv_strerror(int status) {
+    switch (status) {
+        case SVCONV_OK: return "success";
+        case SVCONV_EINVAL: return "invalid argument";
+        case SVCONV_ENOMEM: return "out of memory";
+        case SVCONV_EDEVICE: return "device (HIP) error";
+        case SVCONV_EUNSUPPORTED: return "unsupported configuration";
+        case SVCONV_ENOTSPD: return "matrix is not symmetric positive definite";
+        default: return "unknown status";
+    }
+}
+
+const char* svconv_last_error(void) { return g_last_error.c_str(); }
+
+int svconv_plan_create(svconv_plan** out, int height, int width, int half_width, int n_gauss,
+                       const double* sigmas, const int* degrees, int spatial_degree,
+                       int precision) {
+    g_last_error.clear();
+    if (!out) return fail(SVCONV_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (height <= 0 || width <= 0) return fail(SVCONV_EINVAL, "image size must be positive");
+    if (half_width < 0) return fail(SVCONV_EINVAL, "half_width < 0");
+    if (n_gauss <= 0 || !sigmas || !degrees) return fail(SVCONV_EINVAL, "no basis families");
+    if (spatial_degree < 0) return fail(SVCONV_EINVAL, "spatial_degree < 0");
+    if (precision < SVCONV_FP32 || precision > SVCONV_FP16X3)
+        return fail(SVCONV_EINVAL, "unknown precision");
+    long N = 0;
+    for (int g = 0; g < n_gauss; ++g) {
+        if (!(sigmas[g] >= 0.0) || !std::isfinite(sigmas[g]))
+            return fail(SVCONV_EINVAL, "sigma must be finite and >= 0");
+        if (degrees[g] < 0) return fail(SVCONV_EINVAL, "degree < 0");
+        if (sigmas[g] == 0.0 && degrees[g] != 0)
+            return fail(SVCONV_EINVAL, "a delta basis (sigma 0) must have degree 0");
+        if (degrees[g] > 64) return fail(SVCONV_EINVAL, "degree too large");
+        N += (long)(degrees[g] + 1) * (degrees[g] + 2) / 2;
+    }
+    if (half_width > kMaxHalfWidth) return fail(SVCONV_EUNSUPPORTED, "half_width > 31");
+    if (spatial_degree > kMaxSpatialDegree) return fail(SVCONV_EUNSUPPORTED, "spatial_degree > 6");
+    const int M = (spatial_degree + 1) * (spatial_degree + 2) / 2;
+    if (N * M > kMaxCoefficients) return fail(SVCONV_EUNSUPPORTED, "N * M > 1024");
+    if (N > kMaxFilters) return fail(SVCONV_EUNSUPPORTED, "more than 64 basis functions");
+
+    svconv_plan* p = new (std::nothrow) svconv_plan();
+    if (!p) return fail(SVCONV_ENOMEM, "host allocation of the plan");
+    p->H = height;
+    p->W = width;
+    p->h = half_width;
+    p->k = 2 * half_width + 1;
+    p->N = (int)N;
+    p->d_s = spatial_degree;
+    p->M = M;
+    p->precision = precision;
+    p->Wf = width;
+    p->Hf = height;
+    p->sigmas.assign(sigmas, sigmas + n_gauss);
+    p->degrees.assign(degrees, degrees + n_gauss);
+    build_basis(p->h, p->sigmas, p->degrees, p->basis);
+
+    int st = hip_status(hipGetDevice(&p->device), "hipGetDevice");
+    if (st) { free_plan(p); return st; }
+
+    const int k = p->k, kk = k * k;
+    // correlation-oriented tables: F_n[dv][du] = B_n[2h-dv][2h-du]
+    std::vector<float> F32((size_t)p->N * kk);
+    std::vector<double> F64((size_t)p->N * kk), beta(p->N);
+    for (int n = 0; n < p->N; ++n) {
+        double s = 0.0;
+        for (int dv = 0; dv < k; ++dv)
+            for (int du = 0; du < k; ++du) {
+                const double b = p->basis[(size_t)n * kk + (size_t)(k - 1 - dv) * k + (k - 1 - du)];
+                F64[(size_t)n * kk + dv * k + du] = b;
+                F32[(size_t)n * kk + dv * k + du] = (float)b;
+                s += b;
+            }
+        beta[n] = s;
+    }
+
+    const int nbN = (p->N + 15) / 16;
+    const size_t frag32 = f32_fragment_floats(k, nbN);
+    const size_t fragT32 = f32_fragment_floats(k, (kMaxSpatialTerms + 15) / 16);
+    const size_t fraglN = lowp_fragment_elems(k, nbN);
+    const size_t fraglT = lowp_fragment_elems(k, (kMaxSpatialTerms + 15) / 16);
+    if ((st = dalloc(&p->dF32, F32.size(), "basis table")) ||
+        (st = dalloc(&p->dF64, F64.size(), "basis table (f64)")) ||
+        (st = dalloc(&p->dBeta, beta.size(), "basis sums")) ||
+        (st = dalloc(&p->dFragF32, frag32, "fp32 fragments")) ||
+        (st = dalloc(&p->dFragLoB, fraglN, "bf16 fragments")) ||
+        (st = dalloc(&p->dFragLoH, fraglN, "fp16 fragments")) ||
+        (st = dalloc(&p->dScaleB, (size_t)2 * kMaxFilters, "bf16 scales")) ||
+        (st = dalloc(&p->dScaleH, (size_t)2 * kMaxFilters, "fp16 scales")) ||
+        (st = dalloc(&p->dFt32, (size_t)kMaxFilters * kk, "per-call filters")) ||
+        (st = dalloc(&p->dBetaT, (size_t)kMaxFilters, "per-call sums")) ||
+        (st = dalloc(&p->dFragT32, fragT32, "per-call fp32 fragments")) ||
+        (st = dalloc(&p->dFragTB, fraglT, "per-call bf16 fragments")) ||
+        (st = dalloc(&p->dFragTH, fraglT, "per-call fp16 fragments")) ||
+        (st = dalloc(&p->dScaleT, (size_t)2 * kMaxFilters, "per-call scales")) ||
+        (st = dalloc(&p->dVec, (size_t)4 * kMaxCoefficients + 64, "vector scratch")) ||
+        (st = dalloc(&p->dStatus, (size_t)4, "status word")) ||
+        (st = dalloc(&p->dGrad, (size_t)p->H * p->W, "loss gradient")) ||
+        (st = dalloc(&p->dRed, (size_t)2048, "reduction scratch")) ||
+        (st = dalloc(&p->dQpart, adjoint_scratch_doubles(p->H, p->W, p->k, p->M), "adjoint scratch"))) {
+        free_plan(p);
+        return st;
+    }
+    st = hip_status(hipMemcpy(p->dF32, F32.data(), F32.size() * 4, hipMemcpyHostToDevice), "upload");
+    if (!st) st = hip_status(hipMemcpy(p->dF64, F64.data(), F64.size() * 8, hipMemcpyHostToDevice), "upload");
+    if (!st) st = hip_status(hipMemcpy(p->dBeta, beta.data(), beta.size() * 8, hipMemcpyHostToDevice), "upload");
+    if (!st) st = build_f32_fragments(p->dF32, p->N, k, p->dFragF32, nullptr);
+    if (!st) st = build_lowp_fragments(p->dF32, p->N, k, 0, p->dScaleB, p->dFragLoB, nullptr);
+    if (!st) st = build_lowp_fragments(p->dF32, p->N, k, 1, p->dScaleH, p->dFragLoH, nullptr);
+    if (!st) st = hip_status(hipDeviceSynchronize(), "plan table build");
+    if (st) { free_plan(p); return st; }
+    *out = p;
+    return SVCONV_OK;
+}
+
+int svconv_plan_set_frame(svconv_plan* p, int x0, int y0, int frame_width, int frame_height) {
+    if (!p) return fail(SVCONV_EINVAL, "plan is NULL");
+    if (x0 < 0 || y0 < 0 || frame_width <= 0 || frame_height <= 0 ||
+        (long)x0 + p->W > frame_width || (long)y0 + p->H > frame_height)
+        return fail(SVCONV_EINVAL, "image does not lie inside the frame");
+    p->x0 = x0;
+    p->y0 = y0;
+    p->Wf = frame_width;
+    p->Hf = frame_height;
+    return SVCONV_OK;
+}
+
+int svconv_plan_set_stream(svconv_plan* p, void* stream) {
+    if (!p) return fail(SVCONV_EINVAL, "plan is NULL");
+    p->stream = (hipStream_t)stream;
+    return SVCONV_OK;
+}
+
+int svconv_plan_set_precision(svconv_plan* p, int precision) {
+    if (!p) return fail(SVCONV_EINVAL, "plan is NULL");
+    if (precision < SVCONV_FP32 || precision > SVCONV_FP16X3)
+        return fail(SVCONV_EINVAL, "unknown precision");
+    p->precision = precision;
+    return SVCONV_OK;
+}
+
+int svconv_plan_set_form(svconv_plan* p, int form) {
+    if (!p) return fail(SVCONV_EINVAL, "plan is NULL");
+    if (form != SVCONV_FORM_BASIS && form != SVCONV_FORM_REGROUPED)
+        return fail(SVCONV_EINVAL, "unknown form");
+    p->form = form;
+    return SVCONV_OK;
+}
+
+int svconv_plan_set_pedestal(svconv_plan* p, float pedestal) {
+    if (!p) return fail(SVCONV_EINVAL, "plan is NULL");
+    if (!std::isfinite(pedestal)) return fail(SVCONV_EINVAL, "pedestal must be finite");
+    p->pedestal = pedestal;
+    return SVCONV_OK;
+}
+
+int svconv_plan_sizes(const svconv_plan* p, int* n_basis, int* n_spatial) {
+    if (!p) return fail(SVCONV_EINVAL, "plan is NULL");
+    if (n_basis) *n_basis = p->N;
+    if (n_spatial) *n_spatial = p->M;
+    return SVCONV_OK;
+}
+
+int svconv_plan_get_basis(const svconv_plan* p, double* host_out) {
+    if (!p || !host_out) return fail(SVCONV_EINVAL, "NULL argument");
+    std::memcpy(host_out, p->basis.data(), p->basis.size() * sizeof(double));
+    return SVCONV_OK;
+}
+
+int svconv_plan_destroy(svconv_plan* p) {
+    if (!p) return SVCONV_OK;
+    int st = hip_status(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+    free_plan(p);
+    return st;
+}
+
+// Shared body of svconv_forward and svconv_difference.
+static int run_forward(svconv_plan* p, const float* R, const float* I, const float* a, float* out) {
+    ContractArgs c{};
+    c.X = R;
+    c.H = p->H;
+    c.W = p->W;
+    c.h = p->h;
+    c.M = p->M;
+    c.d_s = p->d_s;
+    c.ped = p->pedestal;
+    c.I = I;
+    c.out = out;
+    c.y_begin = 0;
+    c.n_rows = p->H;
+    coords(p, c);
+    const bool lowp = is_lowp(p->precision);
+    if (p->form == SVCONV_FORM_BASIS) {
+        c.NF = p->N;
+        c.coef = a;
+        c.beta = p->dBeta;
+        const int nb = (p->N + 15) / 16;
+        if (!lowp) return launch_contract_f32(c, p->dFragF32, nb, p->stream);
+        c.fscale = (is_fp16(p->precision) ? p->dScaleH : p->dScaleB) + kMaxFilters;
+        return launch_contract_lowp(c, is_fp16(p->precision) ? p->dFragLoH : p->dFragLoB, nb,
+                                    p->precision, p->stream);
+    }
+    // regrouped: Kt_m built on the device for this call
+    if (p->M > 32) return fail(SVCONV_EUNSUPPORTED, "regrouped form needs M <= 32");
+    int st = regroup_filters(p->dF64, p->dBeta, a, p->N, p->M, p->k, p->dFt32, p->dBetaT, p->stream);
+    if (st) return st;
+    c.NF = p->M;
+    c.coef = nullptr;
+    c.beta = p->dBetaT;
+    const int nb = (p->M + 15) / 16;
+    if (!lowp) {
+        st = build_f32_fragments(p->dFt32, p->M, p->k, p->dFragT32, p->stream);
+        if (st) return st;
+        return launch_contract_f32(c, p->dFragT32, nb, p->stream);
+    }
+    const bool h16 = is_fp16(p->precision);
+    uint16_t* frag = h16 ? p->dFragTH : p->dFragTB;
+    st = build_lowp_fragments(p->dFt32, p->M, p->k, h16 ? 1 : 0, p->dScaleT, frag, p->stream);
+    if (st) return st;
+    c.fscale = p->dScaleT + kMaxFilters;
+    return launch_contract_lowp(c, frag, nb, p->precision, p->stream);
+}
+
+int svconv_forward(svconv_plan* p, const float* R, const float* a, float* out) {
+    if (!p || !R || !a || !out) return fail(SVCONV_EINVAL, "NULL argument");
+    if ((const void*)out == (const void*)R) return fail(SVCONV_EINVAL, "out aliases R");
+    return run_forward(p, R, nullptr, a, out);
+}
+
+int svconv_difference(svconv_plan* p, const float* R, const float* I, const float* a, float* D) {
+    if (!p || !R || !I || !a || !D) return fail(SVCONV_EINVAL, "NULL argument");
+    if ((const void*)D == (const void*)R) return fail(SVCONV_EINVAL, "D aliases R");
+    return run_forward(p, R, I, a, D);
+}
+
+int svconv_backward(svconv_plan* p, const float* R, const float* a, const float* gD, float* gR,
+                    double* ga) {
+    if (!p || !R || !a || !gD) return fail(SVCONV_EINVAL, "NULL argument");
+    if (gR && ((const void*)gR == (const void*)R || (const void*)gR == (const void*)gD))
+        return fail(SVCONV_EINVAL, "gR aliases R or gD");
+    if (p->M > 32) return fail(SVCONV_EUNSUPPORTED, "adjoint in R needs M <= 32");
+    int st = SVCONV_OK;
+    if (gR) {
+        ContractArgs c{};
+        c.X = gD;
+        c.H = p->H;
+        c.W = p->W;
+        c.h = p->h;
+        c.M = p->M;
+        c.d_s = p->d_s;
+        c.ped = 0.f;
+        c.I = nullptr;
+        c.out = gR;
+        c.y_begin = 0;
+        c.n_rows = p->H;
+        coords(p, c);
+        st = adjoint_filters(p->dF64, a, p->N, p->M, p->d_s, p->k, c.sx, c.sy, p->dFt32, p->stream);
+        if (st) return st;
+        st = build_f32_fragments(p->dFt32, p->M, p->k, p->dFragT32, p->stream);
+        if (st) return st;
+        c.NF = p->M;
+        c.coef = nullptr;
+        c.beta = nullptr;
+        st = launch_contract_f32(c, p->dFragT32, (p->M + 15) / 16, p->stream);
+        if (st) return st;
+    }
+    if (ga) st = launch_adjoint_a(p, R, gD, ga);
+    return st;
+}
+
+int svconv_loss_grad(svconv_plan* p, const float* D, const unsigned char* mask, float* gD,
+                     double* loss) {
+    if (!p || !D || !gD) return fail(SVCONV_EINVAL, "NULL argument");
+    return launch_loss_grad(p, D, mask, gD, loss);
+}
+
+int svconv_normal_matrix(svconv_plan* p, const float* R, const unsigned char* mask, double* JtJ) {
+    if (!p || !R || !JtJ) return fail(SVCONV_EINVAL, "NULL argument");
+    return launch_normal_matrix(p, R, mask, JtJ);
+}
+
+int svconv_cholesky_factor(svconv_plan* p, double* A, int n) {
+    if (!p || !A) return fail(SVCONV_EINVAL, "NULL argument");
+    if (n <= 0 || n > kMaxCoefficients) return fail(SVCONV_EINVAL, "n out of range");
+    return launch_cholesky(p, A, n);
+}
+
+int svconv_cholesky_solve(svconv_plan* p, const double* L, const double* rhs, double* x, int n) {
+    if (!p || !L || !rhs || !x) return fail(SVCONV_EINVAL, "NULL argument");
+    if (n <= 0 || n > kMaxCoefficients) return fail(SVCONV_EINVAL, "n out of range");
+    return launch_cholesky_solve(p, L, rhs, x, n);
+}
+
+int svconv_gn_step(svconv_plan* p, const float* R, const float* I, const unsigned char* mask,
+                   const double* L, double* a64, float* a32, float* D, double* host_stats) {
+    if (!p || !R || !I || !L || !a64 || !a32 || !D) return fail(SVCONV_EINVAL, "NULL argument");
+    if ((const void*)D == (const void*)R) return fail(SVCONV_EINVAL, "D aliases R");
+    const int NM = p->N * p->M;
+    double* ga = p->dVec;            // [NM]
+    double* delta = p->dVec + NM;    // [NM]
+    double* loss = p->dVec + 2 * NM; // scalar
+    int st = launch_copy_a(p, a64, a32, NM);
+    if (!st) st = run_forward(p, R, I, a32, D);
+    if (!st) st = launch_loss_grad(p, D, mask, p->dGrad, loss);
+    if (!st) st = launch_adjoint_a(p, R, p->dGrad, ga);
+    if (!st) st = launch_scale(p, ga, 0.5, NM);
+    if (!st) st = launch_cholesky_solve(p, L, ga, delta, NM);
+    if (!st) st = launch_gn_update(p, delta, a64, a32, NM);
+    if (st) return st;
+    if (host_stats) {
+        double stats[2] = {0.0, 0.0};
+        st = hip_status(hipMemcpyAsync(&stats[0], loss, sizeof(double), hipMemcpyDeviceToHost, p->stream),
+                        "copy loss");
+        if (!st) st = hip_status(hipMemcpyAsync(&stats[1], p->dVec + 2 * NM + 1, sizeof(double),
+                                                hipMemcpyDeviceToHost, p->stream), "copy step norm");
+        if (!st) st = hip_status(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+        if (st) return st;
+        host_stats[0] = stats[0];
+        host_stats[1] = stats[1];
+    }
+    return SVCONV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+"""The C ABI without a GPU: the library loads, exports every entry point the
+header declares, and rejects invalid arguments with SVCONV_EINVAL (or
+SVCONV_EUNSUPPORTED) before making any HIP call."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1209_5823_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "svconv.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(svconv_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 19
+    for n in names:
+        assert hasattr(lib, n), n
+    # and the binding knows every one of them
+    assert set(names) == set(_lib.SIGNATURES)
+
+
+def _create(lib, H=64, W=64, h=3, sig=(1.5,), deg=(2,), ds=2, prec=0):
+    p = ctypes.c_void_p()
+    s = (ctypes.c_double * len(sig))(*sig)
+    d = (ctypes.c_int * len(deg))(*deg)
+    rc = lib.svconv_plan_create(ctypes.byref(p), H, W, h, len(sig), s, d, ds, prec)
+    return rc, p
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(H=0), _lib.EINVAL),
+    (dict(W=-3), _lib.EINVAL),
+    (dict(h=-1), _lib.EINVAL),
+    (dict(sig=(-1.0,)), _lib.EINVAL),
+    (dict(sig=(float("nan"),)), _lib.EINVAL),
+    (dict(sig=(0.0,), deg=(1,)), _lib.EINVAL),      # delta basis must have degree 0
+    (dict(deg=(-2,)), _lib.EINVAL),
+    (dict(ds=-1), _lib.EINVAL),
+    (dict(prec=9), _lib.EINVAL),
+    (dict(h=32), _lib.EUNSUPPORTED),
+    (dict(ds=7), _lib.EUNSUPPORTED),
+    (dict(deg=(10,)), _lib.EUNSUPPORTED),           # 66 bases > 64
+    (dict(sig=(1.0, 2.0), deg=(6, 6), ds=6), _lib.EUNSUPPORTED),  # N*M = 56*28 > 1024
+])
+def test_plan_create_rejects_before_any_device_call(lib, kw, status):
+    rc, p = _create(lib, **kw)
+    assert rc == status
+    assert not p.value
+    assert lib.svconv_last_error().decode() != ""
+
+
+def test_null_plan_and_null_pointers(lib):
+    E = _lib.EINVAL
+    assert lib.svconv_plan_create(None, 8, 8, 1, 1, None, None, 0, 0) == E
+    assert lib.svconv_plan_set_frame(None, 0, 0, 8, 8) == E
+    assert lib.svconv_plan_set_stream(None, None) == E
+    assert lib.svconv_plan_set_precision(None, 0) == E
+    assert lib.svconv_plan_set_form(None, 0) == E
+    assert lib.svconv_plan_set_pedestal(None, 1.0) == E
+    assert lib.svconv_plan_sizes(None, None, None) == E
+    assert lib.svconv_plan_get_basis(None, None) == E
+    assert lib.svconv_forward(None, None, None, None) == E
+    assert lib.svconv_difference(None, None, None, None, None) == E
+    assert lib.svconv_backward(None, None, None, None, None, None) == E
+    assert lib.svconv_loss_grad(None, None, None, None, None) == E
+    assert lib.svconv_normal_matrix(None, None, None, None) == E
+    assert lib.svconv_cholesky_factor(None, None, 4) == E
+    assert lib.svconv_cholesky_solve(None, None, None, None, 4) == E
+    assert lib.svconv_gn_step(None, None, None, None, None, None, None, None, None) == E
+    assert lib.svconv_plan_destroy(None) == _lib.OK
+
+
+def test_strerror(lib):
+    for st in (0, -1, -2, -3, -4, -5):
+        assert lib.svconv_strerror(st).decode()
+    assert lib.svconv_strerror(-99).decode() == "unknown status"
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        _lib.load()
