@@ -128,12 +128,15 @@ __global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ T, 
             acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[cb], 0, 0, 0);
         }
     }
-    // lane (kq, j) holds S[n = 16 w + 4 kq + e][n' = 16 cb + j]
+    // the float64 16x16x4 instruction stores row 4 e + kq of the 16 x 16
+    // block in register e of lane (kq, j) (groups of one row, unlike the
+    // float32 form's groups of four): lane (kq, j) holds
+    // S[n = 16 w + 4 e + kq][n' = 16 cb + j]
     double* dst = part + ((size_t)chunk * n_mu + mu) * 64 * 64;
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) dst[(16 * w + 4 * kq + e) * 64 + 16 * cb + j] = acc[cb][e];
+        for (int e = 0; e < 4; ++e) dst[(16 * w + 4 * e + kq) * 64 + 16 * cb + j] = acc[cb][e];
 }
 
 // S[mu][.][.] += sum over chunks (fixed order)

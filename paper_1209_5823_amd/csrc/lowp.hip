@@ -248,7 +248,6 @@ __global__ __launch_bounds__(512, 1) void contract_lowp_kernel(
         const size_t unit = (((size_t)(r * n_q + q) * NB + b) * 2 + hf) * 64 + lane;
         return reinterpret_cast<const uint4*>(frag) + unit;
     };
-    constexpr int PF = (LP_NQ * NB * HALVES * 64 + 511) / 512;   // units per thread
     for (int u = tid; u < slab_u4; u += 512) slab[u] = *slab_src(0, u);
     __syncthreads();
 
@@ -263,15 +262,13 @@ __global__ __launch_bounds__(512, 1) void contract_lowp_kernel(
 #pragma unroll
         for (int i = 0; i < LP_TP; ++i) acc[b][i] = f4{0.f, 0.f, 0.f, 0.f};
 
+    constexpr int UPQ = NB * HALVES * 64;       // slab units of one chunk q (<= 512)
     for (int r = 0; r < n_rg; ++r) {
-        // prefetch the next slab into registers
-        uint4 pf[PF];
+        // the next row group's slab is copied one chunk q per iteration of
+        // the q loop below (one 16-byte unit per thread at most), into the
+        // buffer no wave reads during this row group
         const bool more = (r + 1 < n_rg);
-#pragma unroll
-        for (int p = 0; p < PF; ++p) {
-            const int u = tid + 512 * p;
-            if (more && u < slab_u4) pf[p] = *slab_src(r + 1, u);
-        }
+        uint4* dst = slab + ((r + 1) & 1) * slab_u4;
 
         // aligned chunks of LDS row (j + 4r + g), columns 8c .. 8c+7
         uint32_t ch[NCH][4], cl[NCH][4];
@@ -297,37 +294,61 @@ __global__ __launch_bounds__(512, 1) void contract_lowp_kernel(
         }
 
         const uint4* sl = slab + (r & 1) * slab_u4;
+        // A fragments of chunk q for all filter blocks, the next chunk's
+        // loaded while this one's matrix-core work runs
+        uint32_t fh[NB][4], fl[NB][4];
+        auto load_frags = [&](int q, uint32_t (&h_)[NB][4], uint32_t (&l_)[NB][4]) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const uint4 vh = sl[((q * NB + b) * HALVES + 0) * 64 + lane];
+                h_[b][0] = vh.x; h_[b][1] = vh.y; h_[b][2] = vh.z; h_[b][3] = vh.w;
+                if (SPLIT_B) {
+                    const uint4 vl = sl[((q * NB + b) * HALVES + 1) * 64 + lane];
+                    l_[b][0] = vl.x; l_[b][1] = vl.y; l_[b][2] = vl.z; l_[b][3] = vl.w;
+                }
+            }
+        };
+        load_frags(0, fh, fl);
 #pragma unroll
         for (int q = 0; q < LP_NQ; ++q) {
             if (q < n_q) {
+                const bool do_pf = more && tid < UPQ;
+                uint4 pfq;
+                if (do_pf) pfq = *slab_src(r + 1, q * UPQ + tid);
+                uint32_t nh[NB][4], nl[NB][4];
+                if (q + 1 < n_q) load_frags(q + 1, nh, nl);
+                // pass-outer order: 4 NB independent accumulators between
+                // two products that update the same one
 #pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    uint32_t fh[4], fl[4];
-                    const uint4 vh = sl[((q * NB + b) * HALVES + 0) * 64 + lane];
-                    fh[0] = vh.x; fh[1] = vh.y; fh[2] = vh.z; fh[3] = vh.w;
-                    if (SPLIT_B) {
-                        const uint4 vl = sl[((q * NB + b) * HALVES + 1) * 64 + lane];
-                        fl[0] = vl.x; fl[1] = vl.y; fl[2] = vl.z; fl[3] = vl.w;
-                    }
+                for (int b = 0; b < NB; ++b)
 #pragma unroll
-                    for (int i = 0; i < LP_TP; ++i) {
-                        acc[b][i] = mfma16<FP16>(fh, ch[i + q], acc[b][i]);
-                        if (SPLIT_R) acc[b][i] = mfma16<FP16>(fh, cl[i + q], acc[b][i]);
-                        if (SPLIT_B) acc[b][i] = mfma16<FP16>(fl, ch[i + q], acc[b][i]);
-                    }
+                    for (int i = 0; i < LP_TP; ++i) acc[b][i] = mfma16<FP16>(fh[b], ch[i + q], acc[b][i]);
+                if (SPLIT_R) {
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+#pragma unroll
+                        for (int i = 0; i < LP_TP; ++i) acc[b][i] = mfma16<FP16>(fh[b], cl[i + q], acc[b][i]);
                 }
+                if (SPLIT_B) {
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+#pragma unroll
+                        for (int i = 0; i < LP_TP; ++i) acc[b][i] = mfma16<FP16>(fl[b], ch[i + q], acc[b][i]);
+                }
+                if (q + 1 < n_q) {
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            fh[b][e] = nh[b][e];
+                            if (SPLIT_B) fl[b][e] = nl[b][e];
+                        }
+                }
+                if (do_pf) dst[q * UPQ + tid] = pfq;
             }
         }
 
-        // store the prefetched slab into the other buffer (no wave reads it in
-        // this iteration), then make it visible
-        uint4* dst = slab + ((r + 1) & 1) * slab_u4;
-#pragma unroll
-        for (int p = 0; p < PF; ++p) {
-            const int u = tid + 512 * p;
-            if (more && u < slab_u4) dst[u] = pf[p];
-        }
-        __syncthreads();
+        __syncthreads();   // the next slab is complete and this one is free
     }
 
     // Epilogue in float64.  Lane (g, j) holds T_f, f = 16 b + 4 g + e, of the
