@@ -82,7 +82,7 @@ LowpGeometry lowp_geometry(int k, int nb) {
     g.lds_pitch = lp_pitch(8 * (LP_TP + LP_NQ));
     const size_t tile = (size_t)g.lds_rows * g.lds_pitch * 2 * 2;                // hi + lo
     const size_t slab = (size_t)g.n_q * nb * 2 * 64 * 16;                        // one row group
-    g.lds_bytes = tile + 2 * slab + (size_t)kMaxFilters * kMaxSpatialTerms * 4;
+    g.lds_bytes = tile + 2 * slab + (size_t)kMaxSpatialTerms * 4;
     return g;
 }
 
@@ -194,39 +194,20 @@ __device__ __forceinline__ f4 mfma16(const uint32_t (&a)[4], const uint32_t (&b)
     }
 }
 
-template <int NB, bool FP16, bool SPLIT_R, bool SPLIT_B, bool REG>
-__global__ __launch_bounds__(512, 1) void contract_lowp_kernel(
-    ContractArgs a, const uint16_t* __restrict__ frag, int k, int n_rg, int n_q, int pitch,
-    int rows, int tiles_x, int n_tiles, float xscale) {
-    extern __shared__ __align__(16) uint8_t smem_raw[];
-    constexpr int HALVES = SPLIT_B ? 2 : 1;
-    constexpr int NCH = LP_TP + LP_NQ;          // aligned chunks per row and row group
-    uint16_t* hiT = reinterpret_cast<uint16_t*>(smem_raw);
-    uint16_t* loT = hiT + rows * pitch;
-    uint4* slab = reinterpret_cast<uint4*>(loT + rows * pitch);
-    const int slab_u4 = n_q * NB * HALVES * 64;
-    float* coef_s = reinterpret_cast<float*>(slab + 2 * slab_u4);
-
-    const int tid = threadIdx.x;
-    const int t = [&] {
-        const int bid = blockIdx.x, x8 = bid & 7, tt = bid >> 3, q8 = n_tiles >> 3, r8 = n_tiles & 7;
-        return x8 * q8 + (x8 < r8 ? x8 : r8) + tt;
-    }();
-    const int X0 = (t % tiles_x) * LP_TW;
-    const int Y0 = a.y_begin + (t / tiles_x) * LP_TH;
-    const int h = a.h;
-
-    if (!REG)
-        for (int q = tid; q < a.NF * a.M; q += 512) coef_s[q] = a.coef[q];
-
-    // Stage (X - ped) * xscale as hi / lo 16-bit parts; X = 0 outside the image.
-    const int cols = 8 * NCH;
+// Stage rows [r0, r1) of the input tile, (X - ped) * xscale split into
+// 16-bit hi / lo parts, X = 0 outside the image.  Tile row r is image row
+// Y0 - h + r, tile column c is image column X0 - h + c.
+template <bool FP16, bool SPLIT_R>
+__device__ __forceinline__ void lp_stage(const ContractArgs& a, uint16_t* hiT, uint16_t* loT,
+                                         int pitch, int rows, int X0, int Y0, float xscale,
+                                         int tid) {
+    const int cols = 8 * (LP_TP + LP_NQ);
     for (int r = tid >> 6; r < rows; r += LP_WAVES) {
-        const int gy = Y0 - h + r;
+        const int gy = Y0 - a.h + r;
         const bool row_in = (gy >= 0) && (gy < a.H);
         const float* src = a.X + (size_t)(row_in ? gy : 0) * a.W;
         for (int c = tid & 63; c < pitch; c += 64) {
-            const int gx = X0 - h + c;
+            const int gx = X0 - a.h + c;
             float v = 0.f;
             if (row_in && gx >= 0 && gx < a.W && c < cols) v = src[gx];
             const float xv = (c < cols) ? (v - a.ped) * xscale : 0.f;
@@ -236,6 +217,224 @@ __global__ __launch_bounds__(512, 1) void contract_lowp_kernel(
             loT[r * pitch + c] = SPLIT_R ? (uint16_t)lo : (uint16_t)0;
         }
     }
+}
+
+// One 4-row group r of the contraction for this wave's 4 pixel blocks:
+// windows from LDS row (j + 4r + g), A fragments of chunk q from `sl`
+// ([q][b][half][lane] 16-byte units), the next chunk's fragments loaded while
+// this chunk's products run.  `hook(q)` runs once per chunk (used to stream
+// the next slab in the slab kernel).
+template <int NB, bool FP16, bool SPLIT_R, bool SPLIT_B, class Hook>
+__device__ __forceinline__ void lp_rowgroup(f4 (&acc)[NB][LP_TP], const uint16_t* hiT,
+                                            const uint16_t* loT, int pitch, int row,
+                                            const uint4* sl, int n_q, int lane, int s,
+                                            Hook&& hook) {
+    constexpr int HALVES = SPLIT_B ? 2 : 1;
+    constexpr int NCH = LP_TP + LP_NQ;
+    const uint32_t sh = 16u * (uint32_t)(s & 1);
+    uint32_t ch[NCH][4], cl[NCH][4];
+    {
+        const uint4* ph = reinterpret_cast<const uint4*>(hiT + row * pitch);
+        const uint4* pl = reinterpret_cast<const uint4*>(loT + row * pitch);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const uint4 vh = ph[c];
+            ch[c][0] = vh.x; ch[c][1] = vh.y; ch[c][2] = vh.z; ch[c][3] = vh.w;
+            if (SPLIT_R) {
+                const uint4 vl = pl[c];
+                cl[c][0] = vl.x; cl[c][1] = vl.y; cl[c][2] = vl.z; cl[c][3] = vl.w;
+            }
+        }
+    }
+    switch (s >> 1) {
+        case 0: form_windows<0, NCH - 1>(ch, sh); if (SPLIT_R) form_windows<0, NCH - 1>(cl, sh); break;
+        case 1: form_windows<1, NCH - 1>(ch, sh); if (SPLIT_R) form_windows<1, NCH - 1>(cl, sh); break;
+        case 2: form_windows<2, NCH - 1>(ch, sh); if (SPLIT_R) form_windows<2, NCH - 1>(cl, sh); break;
+        default: form_windows<3, NCH - 1>(ch, sh); if (SPLIT_R) form_windows<3, NCH - 1>(cl, sh); break;
+    }
+
+    uint32_t fh[NB][4], fl[NB][4];
+    auto load_frags = [&](int q, uint32_t (&h_)[NB][4], uint32_t (&l_)[NB][4]) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const uint4 vh = sl[((q * NB + b) * HALVES + 0) * 64 + lane];
+            h_[b][0] = vh.x; h_[b][1] = vh.y; h_[b][2] = vh.z; h_[b][3] = vh.w;
+            if (SPLIT_B) {
+                const uint4 vl = sl[((q * NB + b) * HALVES + 1) * 64 + lane];
+                l_[b][0] = vl.x; l_[b][1] = vl.y; l_[b][2] = vl.z; l_[b][3] = vl.w;
+            }
+        }
+    };
+    load_frags(0, fh, fl);
+#pragma unroll
+    for (int q = 0; q < LP_NQ; ++q) {
+        if (q < n_q) {
+            hook(q, 0);
+            uint32_t nh[NB][4], nl[NB][4];
+            if (q + 1 < n_q) load_frags(q + 1, nh, nl);
+            // pass-outer order: NB * LP_TP independent accumulators between two
+            // products that update the same one
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int i = 0; i < LP_TP; ++i) acc[b][i] = mfma16<FP16>(fh[b], ch[i + q], acc[b][i]);
+            if (SPLIT_R) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+#pragma unroll
+                    for (int i = 0; i < LP_TP; ++i) acc[b][i] = mfma16<FP16>(fh[b], cl[i + q], acc[b][i]);
+            }
+            if (SPLIT_B) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+#pragma unroll
+                    for (int i = 0; i < LP_TP; ++i) acc[b][i] = mfma16<FP16>(fl[b], ch[i + q], acc[b][i]);
+            }
+            if (q + 1 < n_q) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        fh[b][e] = nh[b][e];
+                        if (SPLIT_B) fl[b][e] = nl[b][e];
+                    }
+            }
+            hook(q, 1);
+        }
+    }
+}
+
+// Epilogue.  With U_m(p) = sum_f coef[f][m] T_f(p) / (s_f xscale) and
+// gamma_m = sum_f coef[f][m] beta_f,
+//   out(p) = sum_m P_m(p) (U_m(p) + ped gamma_m) - I(p)
+// (regrouped form: coef = identity).  U for one 16-pixel block is a
+// (16 terms x 64 filters) . (64 filters x 16 pixels) product on the float32
+// matrix cores: accumulator register (b, e) of lane (g, j) is T_f for
+// f = 16 b + 4 g + e at pixel j, which is exactly the B operand of
+// v_mfma_f32_16x16x4_f32 with K index g, so no data moves between lanes.
+// A operand (b, e, mb): lane (k, m_l) holds coef[16 b + 4 k + e][16 mb + m_l] / (s_f xscale).
+// The result U[m][j] sits in lane (g, j), register e' for m = 16 mb + 4 g + e'.
+// float32 throughout: its rounding (~1e-7 relative) is far below the
+// tolerance of the 16-bit forms.
+template <int NB, int MB>
+__device__ __forceinline__ void lp_epilogue(const ContractArgs& a, const f4 (&acc)[NB][LP_TP],
+                                            const float (&afr)[NB][4][MB],
+                                            const float* gamma_s, int X0, int Y0, int s, int g,
+                                            int j) {
+    const int y = Y0 + j;
+    const float yh = (float)(a.sy * y + a.oy);
+    // exponents of the lane's four terms per term block
+    int ei[MB][4], ej[MB][4];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int m = 16 * mb + 4 * g + e;
+            int tt = 0;
+            while ((tt + 1) * (tt + 2) / 2 <= m) ++tt;
+            ej[mb][e] = m - tt * (tt + 1) / 2;
+            ei[mb][e] = tt - ej[mb][e];
+        }
+#pragma unroll
+    for (int i = 0; i < LP_TP; ++i) {
+        f4 u[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) u[mb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+                    u[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[b][e][mb], acc[b][i][e], u[mb], 0, 0, 0);
+        const int x = X0 + s + 8 * i;
+        const float xh = (float)(a.sx * x + a.ox);
+        float part = 0.f;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int m = 16 * mb + 4 * g + e;
+                if (m < a.M) {
+                    float px = 1.f, py = 1.f;
+                    for (int q = 0; q < ei[mb][e]; ++q) px *= xh;
+                    for (int q = 0; q < ej[mb][e]; ++q) py *= yh;
+                    part += px * py * (u[mb][e] + a.ped * gamma_s[m]);
+                }
+            }
+        part += __shfl_xor(part, 16);
+        part += __shfl_xor(part, 32);
+        if (g == 0 && x < a.W && y < a.y_begin + a.n_rows) {
+            const size_t o = (size_t)y * a.W + x;
+            const float iv = a.I ? a.I[o] : 0.f;
+            a.out[o] = part - iv;
+        }
+    }
+}
+
+// Prologue of the epilogue: A fragments of the U product and gamma (in LDS).
+template <int NB, int MB, bool REG>
+__device__ __forceinline__ void lp_epilogue_setup(const ContractArgs& a, float (&afr)[NB][4][MB],
+                                                  float* gamma_s, int tid, int lane) {
+    const int k = lane >> 4, ml = lane & 15;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                const int f = 16 * b + 4 * k + e;
+                const int m = 16 * mb + ml;
+                float v = 0.f;
+                if (f < a.NF && m < a.M) {
+                    const float inv = a.fscale ? a.fscale[f] : 1.f;
+                    const float c = REG ? (f == m ? 1.f : 0.f) : a.coef[f * a.M + m];
+                    v = c * inv;
+                }
+                afr[b][e][mb] = v;
+            }
+    if (tid < a.M) {
+        double gm = 0.0;
+        if (a.beta) {
+            if (REG) {
+                gm = a.beta[tid];
+            } else {
+                for (int f = 0; f < a.NF; ++f) gm += (double)a.coef[f * a.M + tid] * a.beta[f];
+            }
+        }
+        gamma_s[tid] = (float)gm;
+    }
+}
+
+__device__ __forceinline__ int lp_xcd_remap(int bid, int n) {
+    const int x8 = bid & 7, tt = bid >> 3, q8 = n >> 3, r8 = n & 7;
+    return x8 * q8 + (x8 < r8 ? x8 : r8) + tt;
+}
+
+// Slab kernel: one tile per workgroup; the A fragments of one 4-row group at a
+// time sit in a double-buffered LDS slab, the next group's slab streamed in
+// one chunk per q iteration.  Used when the whole fragment table does not
+// fit in LDS (large kernels).
+template <int NB, int MB, bool FP16, bool SPLIT_R, bool SPLIT_B, bool REG>
+__global__ __launch_bounds__(512, 1) void contract_lowp_kernel(
+    ContractArgs a, const uint16_t* __restrict__ frag, int k, int n_rg, int n_q, int pitch,
+    int rows, int tiles_x, int n_tiles, float xscale) {
+    extern __shared__ __align__(16) uint8_t smem_raw[];
+    constexpr int HALVES = SPLIT_B ? 2 : 1;
+    uint16_t* hiT = reinterpret_cast<uint16_t*>(smem_raw);
+    uint16_t* loT = hiT + rows * pitch;
+    uint4* slab = reinterpret_cast<uint4*>(loT + rows * pitch);
+    const int slab_u4 = n_q * NB * HALVES * 64;
+    float* gamma_s = reinterpret_cast<float*>(slab + 2 * slab_u4);
+
+    const int tid = threadIdx.x;
+    const int t = lp_xcd_remap(blockIdx.x, n_tiles);
+    const int X0 = (t % tiles_x) * LP_TW;
+    const int Y0 = a.y_begin + (t / tiles_x) * LP_TH;
+
+    float afr[NB][4][MB];
+    lp_epilogue_setup<NB, MB, REG>(a, afr, gamma_s, tid, tid & 63);
+    lp_stage<FP16, SPLIT_R>(a, hiT, loT, pitch, rows, X0, Y0, xscale, tid);
 
     // slab of row group r: [q][b][half][lane] 16-byte units
     auto slab_src = [&](int r, int u) -> const uint4* {
@@ -253,8 +452,6 @@ __global__ __launch_bounds__(512, 1) void contract_lowp_kernel(
 
     const int lane = tid & 63, w = tid >> 6;
     const int g = lane >> 4, j = lane & 15;
-    const int s = w;                       // column residue of this wave
-    const uint32_t sh = 16u * (uint32_t)(s & 1);
 
     f4 acc[NB][LP_TP];
 #pragma unroll
@@ -264,156 +461,137 @@ __global__ __launch_bounds__(512, 1) void contract_lowp_kernel(
 
     constexpr int UPQ = NB * HALVES * 64;       // slab units of one chunk q (<= 512)
     for (int r = 0; r < n_rg; ++r) {
-        // the next row group's slab is copied one chunk q per iteration of
-        // the q loop below (one 16-byte unit per thread at most), into the
-        // buffer no wave reads during this row group
+        // the next row group's slab is copied one chunk q per iteration (one
+        // 16-byte unit per thread at most) into the buffer no wave reads now
         const bool more = (r + 1 < n_rg);
         uint4* dst = slab + ((r + 1) & 1) * slab_u4;
-
-        // aligned chunks of LDS row (j + 4r + g), columns 8c .. 8c+7
-        uint32_t ch[NCH][4], cl[NCH][4];
-        {
-            const int row = j + 4 * r + g;
-            const uint4* ph = reinterpret_cast<const uint4*>(hiT + row * pitch);
-            const uint4* pl = reinterpret_cast<const uint4*>(loT + row * pitch);
-#pragma unroll
-            for (int c = 0; c < NCH; ++c) {
-                const uint4 vh = ph[c];
-                ch[c][0] = vh.x; ch[c][1] = vh.y; ch[c][2] = vh.z; ch[c][3] = vh.w;
-                if (SPLIT_R) {
-                    const uint4 vl = pl[c];
-                    cl[c][0] = vl.x; cl[c][1] = vl.y; cl[c][2] = vl.z; cl[c][3] = vl.w;
-                }
-            }
-        }
-        switch (s >> 1) {
-            case 0: form_windows<0, NCH - 1>(ch, sh); if (SPLIT_R) form_windows<0, NCH - 1>(cl, sh); break;
-            case 1: form_windows<1, NCH - 1>(ch, sh); if (SPLIT_R) form_windows<1, NCH - 1>(cl, sh); break;
-            case 2: form_windows<2, NCH - 1>(ch, sh); if (SPLIT_R) form_windows<2, NCH - 1>(cl, sh); break;
-            default: form_windows<3, NCH - 1>(ch, sh); if (SPLIT_R) form_windows<3, NCH - 1>(cl, sh); break;
-        }
-
-        const uint4* sl = slab + (r & 1) * slab_u4;
-        // A fragments of chunk q for all filter blocks, the next chunk's
-        // loaded while this one's matrix-core work runs
-        uint32_t fh[NB][4], fl[NB][4];
-        auto load_frags = [&](int q, uint32_t (&h_)[NB][4], uint32_t (&l_)[NB][4]) {
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const uint4 vh = sl[((q * NB + b) * HALVES + 0) * 64 + lane];
-                h_[b][0] = vh.x; h_[b][1] = vh.y; h_[b][2] = vh.z; h_[b][3] = vh.w;
-                if (SPLIT_B) {
-                    const uint4 vl = sl[((q * NB + b) * HALVES + 1) * 64 + lane];
-                    l_[b][0] = vl.x; l_[b][1] = vl.y; l_[b][2] = vl.z; l_[b][3] = vl.w;
-                }
-            }
+        const bool do_pf = more && tid < UPQ;
+        uint4 pfq;
+        auto hook = [&](int q, int phase) {
+            if (!do_pf) return;
+            if (phase == 0) pfq = *slab_src(r + 1, q * UPQ + tid);
+            else dst[q * UPQ + tid] = pfq;
         };
-        load_frags(0, fh, fl);
-#pragma unroll
-        for (int q = 0; q < LP_NQ; ++q) {
-            if (q < n_q) {
-                const bool do_pf = more && tid < UPQ;
-                uint4 pfq;
-                if (do_pf) pfq = *slab_src(r + 1, q * UPQ + tid);
-                uint32_t nh[NB][4], nl[NB][4];
-                if (q + 1 < n_q) load_frags(q + 1, nh, nl);
-                // pass-outer order: 4 NB independent accumulators between
-                // two products that update the same one
-#pragma unroll
-                for (int b = 0; b < NB; ++b)
-#pragma unroll
-                    for (int i = 0; i < LP_TP; ++i) acc[b][i] = mfma16<FP16>(fh[b], ch[i + q], acc[b][i]);
-                if (SPLIT_R) {
-#pragma unroll
-                    for (int b = 0; b < NB; ++b)
-#pragma unroll
-                        for (int i = 0; i < LP_TP; ++i) acc[b][i] = mfma16<FP16>(fh[b], cl[i + q], acc[b][i]);
-                }
-                if (SPLIT_B) {
-#pragma unroll
-                    for (int b = 0; b < NB; ++b)
-#pragma unroll
-                        for (int i = 0; i < LP_TP; ++i) acc[b][i] = mfma16<FP16>(fl[b], ch[i + q], acc[b][i]);
-                }
-                if (q + 1 < n_q) {
-#pragma unroll
-                    for (int b = 0; b < NB; ++b)
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            fh[b][e] = nh[b][e];
-                            if (SPLIT_B) fl[b][e] = nl[b][e];
-                        }
-                }
-                if (do_pf) dst[q * UPQ + tid] = pfq;
-            }
-        }
-
+        lp_rowgroup<NB, FP16, SPLIT_R, SPLIT_B>(acc, hiT, loT, pitch, j + 4 * r + g,
+                                               slab + (r & 1) * slab_u4, n_q, lane, w, hook);
         __syncthreads();   // the next slab is complete and this one is free
     }
+    lp_epilogue<NB, MB>(a, acc, afr, gamma_s, X0, Y0, w, g, j);
+}
 
-    // Epilogue in float64.  Lane (g, j) holds T_f, f = 16 b + 4 g + e, of the
-    // pixel (X0 + s + 8 i, Y0 + j).
-    const int y = Y0 + j;
-    const double yh = a.sy * y + a.oy;
-    double yp[kMaxSpatialDegree + 1];
-    yp[0] = 1.0;
+// Resident kernel: the whole A-fragment table lives in LDS and a persistent
+// workgroup walks a contiguous run of tiles (one XCD's workgroups cover
+// neighbouring runs); the next tile's input is loaded into registers while
+// the current tile is contracted, so the only barriers are the two around
+// each tile's staging.
+constexpr int LP_PF = 8;   // staged elements per thread and tile (rows * pitch <= 512 * LP_PF)
+
+template <int NB, int MB, bool FP16, bool SPLIT_R, bool SPLIT_B, bool REG>
+__global__ __launch_bounds__(512, 1) void contract_lowp_resident_kernel(
+    ContractArgs a, const uint16_t* __restrict__ frag, int k, int n_rg, int n_q, int pitch,
+    int rows, int tiles_x, int n_tiles, int tiles_per_wg, float xscale) {
+    extern __shared__ __align__(16) uint8_t smem_raw[];
+    constexpr int HALVES = SPLIT_B ? 2 : 1;
+    uint16_t* hiT = reinterpret_cast<uint16_t*>(smem_raw);
+    uint16_t* loT = hiT + rows * pitch;
+    uint4* table = reinterpret_cast<uint4*>(loT + rows * pitch);
+    const int rg_u4 = n_q * NB * HALVES * 64;   // units of one row group
+    float* gamma_s = reinterpret_cast<float*>(table + n_rg * rg_u4);
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int g = lane >> 4, j = lane & 15;
+    const int wg = lp_xcd_remap(blockIdx.x, gridDim.x);
+    const int t_begin = wg * tiles_per_wg;
+    const int t_end = min(n_tiles, t_begin + tiles_per_wg);
+    if (t_begin >= t_end) return;   // uniform for the workgroup
+
+    float afr[NB][4][MB];
+    lp_epilogue_setup<NB, MB, REG>(a, afr, gamma_s, tid, lane);
+    // whole table: unit (r, q, b, hf, lane) from the [r][q][b][2][lane] global layout
+    for (int u = tid; u < n_rg * rg_u4; u += 512) {
+        const int ln = u & 63;
+        int rest = u >> 6;
+        const int hf = rest % HALVES;
+        rest /= HALVES;
+        const int b = rest % NB;
+        rest /= NB;
+        const int q = rest % n_q;
+        const int r = rest / n_q;
+        const size_t unit = (((size_t)(r * n_q + q) * NB + b) * 2 + hf) * 64 + ln;
+        table[u] = reinterpret_cast<const uint4*>(frag)[unit];
+    }
+
+    // raw input of a tile, element e = tid + 512 p of the rows x pitch tile
+    float pf[LP_PF];
+    auto fetch = [&](int t) {
+        const int X0 = (t % tiles_x) * LP_TW;
+        const int Y0 = a.y_begin + (t / tiles_x) * LP_TH;
+        const int cols = 8 * (LP_TP + LP_NQ);
 #pragma unroll
-    for (int q = 1; q <= kMaxSpatialDegree; ++q) yp[q] = yp[q - 1] * yh;
+        for (int p = 0; p < LP_PF; ++p) {
+            const int e = tid + 512 * p;
+            const int r = e / pitch, c = e - r * pitch;
+            const int gy = Y0 - a.h + r, gx = X0 - a.h + c;
+            float v = 0.f;
+            if (r < rows && c < cols && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
+                v = a.X[(size_t)gy * a.W + gx];
+            pf[p] = v;
+        }
+    };
+    auto store = [&]() {
+        const int cols = 8 * (LP_TP + LP_NQ);
 #pragma unroll
-    for (int i = 0; i < LP_TP; ++i) {
-        const int x = X0 + s + 8 * i;
-        const double xh = a.sx * x + a.ox;
-        double xp[kMaxSpatialDegree + 1];
-        xp[0] = 1.0;
-#pragma unroll
-        for (int q = 1; q <= kMaxSpatialDegree; ++q) xp[q] = xp[q - 1] * xh;
-        double part = 0.0;
+        for (int p = 0; p < LP_PF; ++p) {
+            const int e = tid + 512 * p;
+            const int r = e / pitch, c = e - r * pitch;
+            if (r < rows) {
+                const float xv = (c < cols) ? (pf[p] - a.ped) * xscale : 0.f;
+                uint32_t hi, lo;
+                split16<FP16>(xv, hi, lo);
+                hiT[e] = (uint16_t)hi;
+                loT[e] = SPLIT_R ? (uint16_t)lo : (uint16_t)0;
+            }
+        }
+    };
+    fetch(t_begin);
+    for (int t = t_begin; t < t_end; ++t) {
+        __syncthreads();           // previous tile's LDS reads are done
+        store();
+        __syncthreads();           // tile (and, first time, table) visible
+        if (t + 1 < t_end) fetch(t + 1);
+        const int X0 = (t % tiles_x) * LP_TW;
+        const int Y0 = a.y_begin + (t / tiles_x) * LP_TH;
+        f4 acc[NB][LP_TP];
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int f = 16 * b + 4 * g + e;
-                if (f < a.NF) {
-                    double wgt = 0.0;
-                    if (REG) {
-                        int ii = 0, jj = 0, tt = 0;
-                        while ((tt + 1) * (tt + 2) / 2 <= f) ++tt;
-                        jj = f - tt * (tt + 1) / 2;
-                        ii = tt - jj;
-                        double px = 1.0, py = 1.0;
-                        for (int q = 0; q < ii; ++q) px *= xh;
-                        for (int q = 0; q < jj; ++q) py *= yh;
-                        wgt = px * py;
-                    } else {
-                        const float* cf = coef_s + f * a.M;
-                        int m = 0;
-#pragma unroll
-                        for (int tt = 0; tt <= kMaxSpatialDegree; ++tt) {
-                            if (tt <= a.d_s) {
-#pragma unroll
-                                for (int ii = tt; ii >= 0; --ii)
-                                    wgt += (double)cf[m + tt - ii] * (xp[ii] * yp[tt - ii]);
-                            }
-                            m += tt + 1;
-                        }
-                    }
-                    const double inv = a.fscale ? (double)a.fscale[f] : 1.0;
-                    const double pb = a.beta ? (double)a.ped * a.beta[f] : 0.0;
-                    part += wgt * ((double)acc[b][i][e] * inv + pb);
-                }
-            }
-        part += __shfl_xor(part, 16);
-        part += __shfl_xor(part, 32);
-        if (g == 0 && x < a.W && y < a.y_begin + a.n_rows) {
-            const size_t o = (size_t)y * a.W + x;
-            const double iv = a.I ? (double)a.I[o] : 0.0;
-            a.out[o] = (float)(part - iv);
-        }
+            for (int i = 0; i < LP_TP; ++i) acc[b][i] = f4{0.f, 0.f, 0.f, 0.f};
+        auto nohook = [](int, int) {};
+        for (int r = 0; r < n_rg; ++r)
+            lp_rowgroup<NB, FP16, SPLIT_R, SPLIT_B>(acc, hiT, loT, pitch, j + 4 * r + g,
+                                                   table + r * rg_u4, n_q, lane, w, nohook);
+        lp_epilogue<NB, MB>(a, acc, afr, gamma_s, X0, Y0, w, g, j);
     }
 }
 
-template <int NB, bool FP16, bool SR, bool SB>
+static int g_num_cus = 0;
+
+static int num_cus() {
+    if (g_num_cus == 0) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+            g_num_cus = n;
+        else
+            g_num_cus = 256;
+    }
+    return g_num_cus;
+}
+
+template <int NB, int MB, bool FP16, bool SR, bool SB>
 static int launch_lowp_t(const ContractArgs& a, const uint16_t* frag, bool reg, hipStream_t s) {
+    constexpr int HALVES = SB ? 2 : 1;
     const int k = 2 * a.h + 1;
     const LowpGeometry g = lowp_geometry(k, NB);
     const int tiles_x = (a.W + g.tile_w - 1) / g.tile_w;
@@ -421,27 +599,52 @@ static int launch_lowp_t(const ContractArgs& a, const uint16_t* frag, bool reg, 
     const int n_tiles = tiles_x * tiles_y;
     if (n_tiles == 0) return SVCONV_OK;
     const float xs = FP16 ? FP16_XSCALE : 1.f;
+    const size_t tile_bytes = (size_t)g.lds_rows * g.lds_pitch * 2 * 2;
+    const size_t table_bytes = (size_t)g.n_rg * g.n_q * NB * HALVES * 64 * 16;
+    const size_t coef_bytes = (size_t)kMaxSpatialTerms * 4;   // gamma
+    const size_t resident_bytes = tile_bytes + table_bytes + coef_bytes;
+    const bool fits_pf = (size_t)g.lds_rows * g.lds_pitch <= (size_t)512 * LP_PF;
+    if (resident_bytes <= (size_t)160 * 1024 && fits_pf && n_tiles >= 2 * num_cus()) {
+        const int n_wg = num_cus();
+        const int per = (n_tiles + n_wg - 1) / n_wg;
+        if (reg)
+            hipLaunchKernelGGL((contract_lowp_resident_kernel<NB, MB, FP16, SR, SB, true>), dim3(n_wg),
+                               dim3(512), resident_bytes, s, a, frag, k, g.n_rg, g.n_q, g.lds_pitch,
+                               g.lds_rows, tiles_x, n_tiles, per, xs);
+        else
+            hipLaunchKernelGGL((contract_lowp_resident_kernel<NB, MB, FP16, SR, SB, false>), dim3(n_wg),
+                               dim3(512), resident_bytes, s, a, frag, k, g.n_rg, g.n_q, g.lds_pitch,
+                               g.lds_rows, tiles_x, n_tiles, per, xs);
+        return hip_status(hipGetLastError(), "contract_lowp_resident_kernel");
+    }
     if (reg)
-        hipLaunchKernelGGL((contract_lowp_kernel<NB, FP16, SR, SB, true>), dim3(n_tiles), dim3(512),
+        hipLaunchKernelGGL((contract_lowp_kernel<NB, MB, FP16, SR, SB, true>), dim3(n_tiles), dim3(512),
                            g.lds_bytes, s, a, frag, k, g.n_rg, g.n_q, g.lds_pitch, g.lds_rows,
                            tiles_x, n_tiles, xs);
     else
-        hipLaunchKernelGGL((contract_lowp_kernel<NB, FP16, SR, SB, false>), dim3(n_tiles),
+        hipLaunchKernelGGL((contract_lowp_kernel<NB, MB, FP16, SR, SB, false>), dim3(n_tiles),
                            dim3(512), g.lds_bytes, s, a, frag, k, g.n_rg, g.n_q, g.lds_pitch,
                            g.lds_rows, tiles_x, n_tiles, xs);
     return hip_status(hipGetLastError(), "contract_lowp_kernel");
 }
 
+template <int MB, bool FP16, bool SR, bool SB>
+static int launch_lowp_nbm(const ContractArgs& a, const uint16_t* frag, int nb, bool reg,
+                           hipStream_t s) {
+    switch (nb) {
+        case 1: return launch_lowp_t<1, MB, FP16, SR, SB>(a, frag, reg, s);
+        case 2: return launch_lowp_t<2, MB, FP16, SR, SB>(a, frag, reg, s);
+        case 3: return launch_lowp_t<3, MB, FP16, SR, SB>(a, frag, reg, s);
+        case 4: return launch_lowp_t<4, MB, FP16, SR, SB>(a, frag, reg, s);
+        default: return fail(SVCONV_EUNSUPPORTED, "more than 64 filters");
+    }
+}
+
 template <bool FP16, bool SR, bool SB>
 static int launch_lowp_nb(const ContractArgs& a, const uint16_t* frag, int nb, bool reg,
                           hipStream_t s) {
-    switch (nb) {
-        case 1: return launch_lowp_t<1, FP16, SR, SB>(a, frag, reg, s);
-        case 2: return launch_lowp_t<2, FP16, SR, SB>(a, frag, reg, s);
-        case 3: return launch_lowp_t<3, FP16, SR, SB>(a, frag, reg, s);
-        case 4: return launch_lowp_t<4, FP16, SR, SB>(a, frag, reg, s);
-        default: return fail(SVCONV_EUNSUPPORTED, "more than 64 filters");
-    }
+    if (a.M <= 16) return launch_lowp_nbm<1, FP16, SR, SB>(a, frag, nb, reg, s);
+    return launch_lowp_nbm<2, FP16, SR, SB>(a, frag, nb, reg, s);
 }
 
 int launch_contract_lowp(const ContractArgs& a, const uint16_t* frag, int nb, int precision,
