@@ -236,40 +236,46 @@ def fit_least_squares(R, I, h, B, d_s, mask=None, frame=None):
 # the per-pixel form up to rounding, not an approximation.
 # ---------------------------------------------------------------------------
 
-def _fft_conv_same(R, K):
-    """Zero-padded linear convolution of R with a (k x k) kernel centred at h."""
+def _fft_shape(H, W, k):
+    from scipy import fft as sfft
+    return sfft.next_fast_len(H + k - 1, real=True), sfft.next_fast_len(W + k - 1, real=True)
+
+
+def _fft_conv_same(R, K, FR=None, shape=None, workers=-1):
+    """Zero-padded linear convolution of R with a (k x k) kernel centred at h.
+
+    FR (the transform of R at `shape`) may be passed to reuse it."""
+    from scipy import fft as sfft
     H, W = R.shape
     k = K.shape[0]
     h = k // 2
-    sh, sw = H + k - 1, W + k - 1
-    fh = 1 << int(np.ceil(np.log2(sh)))
-    fw = 1 << int(np.ceil(np.log2(sw)))
-    F = np.fft.rfft2(R, s=(fh, fw)) * np.fft.rfft2(K, s=(fh, fw))
-    full = np.fft.irfft2(F, s=(fh, fw))
+    if shape is None:
+        shape = _fft_shape(H, W, k)
+    if FR is None:
+        FR = sfft.rfft2(R, s=shape, workers=workers)
+    full = sfft.irfft2(FR * sfft.rfft2(K, s=shape, workers=workers), s=shape, workers=workers)
     return full[h:h + H, h:h + W]
-
-
-def spatial_term_images(shape, d_s, frame=None):
-    """P_m on the whole array, stacked [M][H][W] (float64)."""
-    H, W = shape
-    x0, y0, Wf, Hf = frame if frame is not None else (0, 0, W, H)
-    x = np.arange(W, dtype=np.float64) + x0
-    y = np.arange(H, dtype=np.float64) + y0
-    xh = 2.0 * x / (Wf - 1) - 1.0 if Wf > 1 else 0.0 * x
-    yh = 2.0 * y / (Hf - 1) - 1.0 if Hf > 1 else 0.0 * y
-    out = []
-    for t in range(d_s + 1):
-        for i in range(t, -1, -1):
-            out.append(np.outer(yh ** (t - i), xh ** i))
-    return np.stack(out)
 
 
 def convolve_fft(R, h, B, d_s, a, frame=None):
     """R (x) K(x,y) through the regrouping above; float64."""
+    from scipy import fft as sfft
     R = _d(R); B = _d(B); a = _d(a)
-    P = spatial_term_images(R.shape, d_s, frame)
+    shape = _fft_shape(R.shape[0], R.shape[1], B.shape[1])
+    FR = sfft.rfft2(R, s=shape, workers=-1)
     C = np.zeros(R.shape)
-    for m in range(P.shape[0]):
-        Kt = np.tensordot(a[:, m], B, axes=(0, 0))
-        C += P[m] * _fft_conv_same(R, Kt)
+    M = n_spatial(d_s)
+    x0, y0, Wf, Hf = frame if frame is not None else (0, 0, R.shape[1], R.shape[0])
+    xs = np.arange(R.shape[1], dtype=np.float64) + x0
+    ys = np.arange(R.shape[0], dtype=np.float64) + y0
+    xh = 2.0 * xs / (Wf - 1) - 1.0 if Wf > 1 else 0.0 * xs
+    yh = 2.0 * ys / (Hf - 1) - 1.0 if Hf > 1 else 0.0 * ys
+    m = 0
+    for t in range(d_s + 1):
+        for i in range(t, -1, -1):
+            Kt = np.tensordot(a[:, m], B, axes=(0, 0))
+            conv = _fft_conv_same(R, Kt, FR, shape)
+            C += conv * (yh ** (t - i))[:, None] * (xh ** i)[None, :]
+            m += 1
+    assert m == M
     return C

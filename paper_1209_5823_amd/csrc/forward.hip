@@ -149,6 +149,16 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
     const int g = lane >> 4, j = lane & 15;
     const int n_chunks = n_rg * k;
 
+    // I at this lane's output pixels, loaded now so that its latency hides
+    // behind the contraction
+    float iv[TH];
+#pragma unroll
+    for (int i = 0; i < TH; ++i) {
+        const int x = X0 + 16 * w + j, y = Y0 + i;
+        iv[i] = (a.I != nullptr && a.out != nullptr && g == 0 && x < a.W && y < y_end)
+                    ? a.I[(size_t)y * a.W + x] : 0.f;
+    }
+
     // T_f accumulates on the matrix cores in float32 over short sub-chains of
     // `seg` chunks (at most 4 * seg taps each), and every sub-chain is added
     // into a float64 total.  Long float32 chains over all k^2 taps lose up to
@@ -255,11 +265,8 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
             }
         part += __shfl_xor(part, 16);
         part += __shfl_xor(part, 32);
-        if (a.out != nullptr && g == 0 && x < a.W && y < y_end) {
-            const size_t o = (size_t)y * a.W + x;
-            const double iv = a.I ? (double)a.I[o] : 0.0;
-            a.out[o] = (float)(part - iv);
-        }
+        if (a.out != nullptr && g == 0 && x < a.W && y < y_end)
+            a.out[(size_t)y * a.W + x] = (float)(part - (double)iv[i]);
     }
 }
 

@@ -304,6 +304,17 @@ __device__ __forceinline__ void lp_rowgroup(f4 (&acc)[NB][LP_TP], const uint16_t
     }
 }
 
+// I at the lane's pixels (0 where not needed).
+__device__ __forceinline__ void lp_fetch_i(const ContractArgs& a, float (&iv)[LP_TP], int X0, int Y0,
+                                           int s, int g, int j) {
+    const int y = Y0 + j;
+#pragma unroll
+    for (int i = 0; i < LP_TP; ++i) {
+        const int x = X0 + s + 8 * i;
+        iv[i] = (a.I && g == 0 && x < a.W && y < a.y_begin + a.n_rows) ? a.I[(size_t)y * a.W + x] : 0.f;
+    }
+}
+
 // Epilogue.  With U_m(p) = sum_f coef[f][m] T_f(p) / (s_f xscale) and
 // gamma_m = sum_f coef[f][m] beta_f,
 //   out(p) = sum_m P_m(p) (U_m(p) + ped gamma_m) - I(p)
@@ -321,6 +332,10 @@ __device__ __forceinline__ void lp_epilogue(const ContractArgs& a, const f4 (&ac
                                             const float (&afr)[NB][4][MB],
                                             const float* gamma_s, int X0, int Y0, int s, int g,
                                             int j) {
+    // I at the lane's pixels, requested first so that the matrix-core work
+    // below hides its latency (the contraction's registers are free by now)
+    float iv[LP_TP];
+    lp_fetch_i(a, iv, X0, Y0, s, g, j);
     const int y = Y0 + j;
     const float yh = (float)(a.sy * y + a.oy);
     // exponents of the lane's four terms per term block
@@ -364,11 +379,7 @@ __device__ __forceinline__ void lp_epilogue(const ContractArgs& a, const f4 (&ac
             }
         part += __shfl_xor(part, 16);
         part += __shfl_xor(part, 32);
-        if (g == 0 && x < a.W && y < a.y_begin + a.n_rows) {
-            const size_t o = (size_t)y * a.W + x;
-            const float iv = a.I ? a.I[o] : 0.f;
-            a.out[o] = part - iv;
-        }
+        if (g == 0 && x < a.W && y < a.y_begin + a.n_rows) a.out[(size_t)y * a.W + x] = part - iv[i];
     }
 }
 
@@ -559,9 +570,9 @@ __global__ __launch_bounds__(512, 1) void contract_lowp_resident_kernel(
         __syncthreads();           // previous tile's LDS reads are done
         store();
         __syncthreads();           // tile (and, first time, table) visible
-        if (t + 1 < t_end) fetch(t + 1);
         const int X0 = (t % tiles_x) * LP_TW;
         const int Y0 = a.y_begin + (t / tiles_x) * LP_TH;
+        if (t + 1 < t_end) fetch(t + 1);
         f4 acc[NB][LP_TP];
 #pragma unroll
         for (int b = 0; b < NB; ++b)

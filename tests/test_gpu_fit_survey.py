@@ -1,0 +1,61 @@
+"""The fit at survey scale: 8192 x 8192 star field, 31 x 31 kernel, 49
+bases, spatial degree 4 (735 coefficients).  I = float32(Poisson(C(R;
+a_hidden))) with C from the oracle's FFT regrouping; the coefficients are
+fitted by Gauss-Newton with the bf16x3 and FP32 forwards.  Reports the
+recovered-coefficient error, the final D RMS in sigma_sky and the Mpix/s of
+one iteration."""
+
+import numpy as np
+import pytest
+
+import synth
+from tests.helpers import say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def c4_case(orc):
+    wl = synth.WORKLOADS["c4"]
+    R, a_hidden = synth.workload_inputs(wl)
+    B = orc.basis(wl.half_width, wl.sigmas, wl.degrees)
+    say("c4 synthesis (oracle FFT regrouping)")
+    C = orc.convolve_fft(R, wl.half_width, B, wl.spatial_degree, a_hidden)
+    I = synth.poisson_noise(C, seed=4)
+    r = np.random.default_rng(44)
+    a0 = (a_hidden + r.uniform(-0.01, 0.01, a_hidden.shape)).astype(np.float32)
+    return wl, R, I, a_hidden, a0
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "fp32"])
+def test_fit_survey_scale(svc, c4_case, precision):
+    import torch
+    from paper_1209_5823_amd.fit import gauss_newton_fit
+    wl, R, I, a_hidden, a0 = c4_case
+    say("c4 fit", precision)
+    with svc.plan_for(wl, precision=precision, pedestal=synth.SKY_LEVEL) as plan:
+        Rd, Id = to_dev(R), to_dev(I)
+        a64, D, hist, t_setup = gauss_newton_fit(plan, Rd, Id, to_dev(a0), iters=3, timings=True)
+        a_fit = to_host(a64)
+        Dh = to_host(D)
+        L_fit, _ = plan.loss_grad(D)
+        D_true = plan.difference(Rd, Id, to_dev(a_hidden))
+        L_true, _ = plan.loss_grad(D_true)
+        L_fit, L_true = float(to_host(L_fit)), float(to_host(L_true))
+    h = wl.half_width
+    interior = Dh[h:-h, h:-h].astype(np.float64)
+    rms = float(np.sqrt(np.mean(interior ** 2)) / synth.sky_sigma())
+    err = np.abs(a_fit - a_hidden)
+    it_s = min(t for _, _, t in hist)
+    say("  setup (normal matrix + Cholesky) %.3f s" % t_setup)
+    for k, (L, step, t) in enumerate(hist):
+        say("  it %d loss %.6e step %.3e  %.1f ms" % (k, L, step, 1e3 * t))
+    say("  max |a - a_hidden| %.3e, rms %.3e; D rms %.4f sigma_sky; %.0f Mpix/s per iteration"
+        % (err.max(), np.sqrt(np.mean(err ** 2)), rms, wl.height * wl.width / it_s / 1e6))
+    say("  loss at the fit %.9e, at the hidden coefficients %.9e" % (L_fit, L_true))
+    # the least-squares minimiser cannot have a larger loss than the hidden
+    # coefficients (up to the forward pass's rounding)
+    assert L_fit <= L_true * (1 + 1e-6)
+    # Poisson noise of the sky and stars sets D's floor: rms just above 1 sigma
+    assert 0.95 < rms < 1.6
+    assert hist[-1][1] < 1e-2 * hist[0][1]
