@@ -60,13 +60,13 @@ constexpr int F32_TW = 64;   // output tile width: 4 waves x 16 columns
 // Output rows per tile (= 16-pixel blocks per wave): fewer rows for more
 // filter blocks so that the float32 sub-chain and float64 total fit in 256
 // registers (two waves per SIMD).
-constexpr int f32_tile_h(int nb) { return nb >= 3 ? 4 : 8; }
+constexpr int f32_tile_h(int nb) { return nb >= 2 ? 4 : 8; }
 
 F32Geometry f32_geometry(int k, int nb) {
     F32Geometry g;
     g.k = k;
     g.n_rg = (k + 3) / 4;
-    g.n_chunks = g.n_rg * k;
+    g.n_chunks = (g.n_rg * k + 3) / 4 * 4;   // padded to whole groups of 4 chunks
     g.nb = nb;
     g.tile_w = F32_TW;
     g.tile_h = f32_tile_h(nb);
@@ -96,6 +96,7 @@ __global__ void frag_f32_kernel(const float* __restrict__ F, int NF, int k, int 
     const int r = c / k, du = c - r * k;
     const int dv = 4 * r + (lane >> 4);
     const int f = 16 * b + (lane & 15);
+    // chunks past the last row group (padding to a group of 4) carry zeros
     frag[idx] = (f < NF && dv < k) ? F[((size_t)f * k + dv) * k + du] : 0.f;
 }
 
@@ -114,7 +115,7 @@ template <int NB, int TH, bool REG>
 __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
                                                            const float* __restrict__ frag, int k,
                                                            int n_rg, int pitch, int rows, int cols,
-                                                           int tiles_x, int n_tiles, int seg) {
+                                                           int tiles_x, int n_tiles) {
     extern __shared__ __align__(16) float smem[];
     float* tile = smem;
     float* coef_s = smem + rows * pitch;
@@ -147,7 +148,7 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
 
     const int lane = tid & 63, w = tid >> 6;
     const int g = lane >> 4, j = lane & 15;
-    const int n_chunks = n_rg * k;
+    const int n_chunks = (n_rg * k + 3) / 4 * 4;
 
     // I at this lane's output pixels, loaded now so that its latency hides
     // behind the contraction
@@ -159,11 +160,12 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
                     ? a.I[(size_t)y * a.W + x] : 0.f;
     }
 
-    // T_f accumulates on the matrix cores in float32 over short sub-chains of
-    // `seg` chunks (at most 4 * seg taps each), and every sub-chain is added
-    // into a float64 total.  Long float32 chains over all k^2 taps lose up to
-    // a few ulp of T at bright stars; short chains keep the rounding of each
-    // partial sum small and the float64 total adds none.
+    // T_f accumulates on the matrix cores in float32 over sub-chains of 4
+    // chunks (16 taps), and every sub-chain is added into a float64 total.
+    // Long float32 chains over all k^2 taps lose up to a few ulp of T at
+    // bright stars; short chains keep the rounding of each partial sum small
+    // and the float64 total adds none.  The A fragments of the next group of
+    // 4 chunks are requested from L2 while this group's products run.
     double tot[NB][TH][4];
 #pragma unroll
     for (int b = 0; b < NB; ++b)
@@ -173,44 +175,64 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
             for (int e = 0; e < 4; ++e) tot[b][i][e] = 0.0;
 
     const float* fp = frag + lane;
-    float fa[NB];
+    float fa[4][NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) fa[b] = fp[b * 64];
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) fa[u][b] = fp[(size_t)(u * NB + b) * 64];
 
     const float* tb = tile + g * pitch + 16 * w + j;
-    int c = 0;
-    for (int r = 0; r < n_rg; ++r) {
-        const float* rb = tb + 4 * r * pitch;
-        for (int d0 = 0; d0 < k; d0 += seg) {
-            const int d1 = (d0 + seg < k) ? d0 + seg : k;
-            f4 acc[NB][TH];
+    int r = 0, du = 0;       // row group and column of the chunk being issued
+    for (int c0 = 0; c0 < n_chunks; c0 += 4) {
+        // next group's fragments: chunks +4, +5 now, +6, +7 once the first two
+        // chunks of this group no longer need their registers
+        const int cn = (c0 + 4 < n_chunks) ? c0 + 4 : c0;
+        float na[2][NB], nb2[2][NB];
 #pragma unroll
-            for (int b = 0; b < NB; ++b)
+        for (int u = 0; u < 2; ++u)
 #pragma unroll
-                for (int i = 0; i < TH; ++i) acc[b][i] = f4{0.f, 0.f, 0.f, 0.f};
-            for (int du = d0; du < d1; ++du) {
-                ++c;
-                const float* fq = fp + (size_t)(c < n_chunks ? c : n_chunks - 1) * (NB * 64);
-                float fn[NB];
+            for (int b = 0; b < NB; ++b) na[u][b] = fp[(size_t)((cn + u) * NB + b) * 64];
+        f4 acc[NB][TH];
 #pragma unroll
-                for (int b = 0; b < NB; ++b) fn[b] = fq[b * 64];
-                float xb[TH];
+        for (int b = 0; b < NB; ++b)
 #pragma unroll
-                for (int i = 0; i < TH; ++i) xb[i] = rb[i * pitch + du];
+            for (int i = 0; i < TH; ++i) acc[b][i] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int i = 0; i < TH; ++i)
+        for (int u = 0; u < 4; ++u) {
+            if (u == 2) {
 #pragma unroll
-                    for (int b = 0; b < NB; ++b)
-                        acc[b][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[b], xb[i], acc[b][i], 0, 0, 0);
+                for (int v = 0; v < 2; ++v)
 #pragma unroll
-                for (int b = 0; b < NB; ++b) fa[b] = fn[b];
+                    for (int b = 0; b < NB; ++b) nb2[v][b] = fp[(size_t)((cn + 2 + v) * NB + b) * 64];
             }
+            // padded chunks past the last row group read row group n_rg - 1
+            // (in the tile) with zero weights
+            const float* rb = tb + 4 * (r < n_rg ? r : n_rg - 1) * pitch + du;
+            float xb[TH];
 #pragma unroll
-            for (int b = 0; b < NB; ++b)
+            for (int i = 0; i < TH; ++i) xb[i] = rb[i * pitch];
 #pragma unroll
-                for (int i = 0; i < TH; ++i)
+            for (int i = 0; i < TH; ++i)
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) tot[b][i][e] += (double)acc[b][i][e];
+                for (int b = 0; b < NB; ++b)
+                    acc[b][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[u][b], xb[i], acc[b][i], 0, 0, 0);
+            if (++du == k) {
+                du = 0;
+                ++r;
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int i = 0; i < TH; ++i)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) tot[b][i][e] += (double)acc[b][i][e];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            fa[0][b] = na[0][b];
+            fa[1][b] = na[1][b];
+            fa[2][b] = nb2[0][b];
+            fa[3][b] = nb2[1][b];
         }
     }
 
@@ -270,19 +292,6 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
     }
 }
 
-// Taps per float32 sub-chain are 4 * seg; SVCONV_F32_SEG overrides the
-// default of 4 chunks (a tuning knob, read once).  With 16-tap sub-chains the
-// worst pixel of the 2048 x 4096 and 4096 x 4096 star fields stays below
-// 5e-5 sigma_sky; whole-row chains reach 1.2e-4.
-static int f32_seg() {
-    static int seg = [] {
-        const char* e = getenv("SVCONV_F32_SEG");
-        int v = e ? atoi(e) : 4;
-        return v > 0 ? v : 4;
-    }();
-    return seg;
-}
-
 template <int NB, bool REG>
 static int launch_f32_t(const ContractArgs& a, const float* frag, hipStream_t s) {
     constexpr int TH = f32_tile_h(NB);
@@ -294,8 +303,7 @@ static int launch_f32_t(const ContractArgs& a, const float* frag, hipStream_t s)
     if (n_tiles == 0) return SVCONV_OK;
     if (g.lds_bytes > 64 * 1024) return fail(SVCONV_EUNSUPPORTED, "FP32 tile exceeds 64 KiB of LDS");
     hipLaunchKernelGGL((contract_f32_kernel<NB, TH, REG>), dim3(n_tiles), dim3(256), g.lds_bytes, s,
-                       a, frag, k, g.n_rg, g.lds_pitch, g.lds_rows, g.lds_cols, tiles_x, n_tiles,
-                       f32_seg());
+                       a, frag, k, g.n_rg, g.lds_pitch, g.lds_rows, g.lds_cols, tiles_x, n_tiles);
     return hip_status(hipGetLastError(), "contract_f32_kernel");
 }
 
