@@ -201,20 +201,29 @@ template <bool FP16, bool SPLIT_R>
 __device__ __forceinline__ void lp_stage(const ContractArgs& a, uint16_t* hiT, uint16_t* loT,
                                          int pitch, int rows, int X0, int Y0, float xscale,
                                          int tid) {
+    // element pairs, one 32-bit LDS word per part (pitch is even)
     const int cols = 8 * (LP_TP + LP_NQ);
+    const int half = pitch / 2;
     for (int r = tid >> 6; r < rows; r += LP_WAVES) {
         const int gy = Y0 - a.h + r;
         const bool row_in = (gy >= 0) && (gy < a.H);
         const float* src = a.X + (size_t)(row_in ? gy : 0) * a.W;
-        for (int c = tid & 63; c < pitch; c += 64) {
-            const int gx = X0 - a.h + c;
-            float v = 0.f;
-            if (row_in && gx >= 0 && gx < a.W && c < cols) v = src[gx];
-            const float xv = (c < cols) ? (v - a.ped) * xscale : 0.f;
-            uint32_t hi, lo;
-            split16<FP16>(xv, hi, lo);
-            hiT[r * pitch + c] = (uint16_t)hi;
-            loT[r * pitch + c] = SPLIT_R ? (uint16_t)lo : (uint16_t)0;
+        for (int c2 = tid & 63; c2 < half; c2 += 64) {
+            uint32_t hw = 0, lw = 0;
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                const int c = 2 * c2 + v;
+                const int gx = X0 - a.h + c;
+                float x = 0.f;
+                if (row_in && gx >= 0 && gx < a.W && c < cols) x = src[gx];
+                const float xv = (c < cols) ? (x - a.ped) * xscale : 0.f;
+                uint32_t hi, lo;
+                split16<FP16>(xv, hi, lo);
+                hw |= hi << (16 * v);
+                lw |= (SPLIT_R ? lo : 0u) << (16 * v);
+            }
+            reinterpret_cast<uint32_t*>(hiT + r * pitch)[c2] = hw;
+            reinterpret_cast<uint32_t*>(loT + r * pitch)[c2] = lw;
         }
     }
 }
@@ -359,9 +368,10 @@ __device__ __forceinline__ void lp_epilogue(const ContractArgs& a, const f4 (&ac
         for (int b = 0; b < NB; ++b)
 #pragma unroll
             for (int e = 0; e < 4; ++e)
+                if (16 * b + e < a.NF)   // else filters 16 b + 4 k + e are all padding
 #pragma unroll
-                for (int mb = 0; mb < MB; ++mb)
-                    u[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[b][e][mb], acc[b][i][e], u[mb], 0, 0, 0);
+                    for (int mb = 0; mb < MB; ++mb)
+                        u[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[b][e][mb], acc[b][i][e], u[mb], 0, 0, 0);
         const int x = X0 + s + 8 * i;
         const float xh = (float)(a.sx * x + a.ox);
         float part = 0.f;
@@ -495,7 +505,7 @@ __global__ __launch_bounds__(512, 1) void contract_lowp_kernel(
 // neighbouring runs); the next tile's input is loaded into registers while
 // the current tile is contracted, so the only barriers are the two around
 // each tile's staging.
-constexpr int LP_PF = 8;   // staged elements per thread and tile (rows * pitch <= 512 * LP_PF)
+constexpr int LP_PF = 4;   // staged element pairs per thread and tile (rows * pitch <= 1024 * LP_PF)
 
 template <int NB, int MB, bool FP16, bool SPLIT_R, bool SPLIT_B, bool REG>
 __global__ __launch_bounds__(512, 1) void contract_lowp_resident_kernel(
@@ -533,35 +543,46 @@ __global__ __launch_bounds__(512, 1) void contract_lowp_resident_kernel(
         table[u] = reinterpret_cast<const uint4*>(frag)[unit];
     }
 
-    // raw input of a tile, element e = tid + 512 p of the rows x pitch tile
-    float pf[LP_PF];
+    // raw input of a tile: element pair (2 e, 2 e + 1), e = tid + 512 p, of
+    // the rows x pitch tile (pitch is even), stored as one 32-bit word per part
+    float pf[LP_PF][2];
     auto fetch = [&](int t) {
         const int X0 = (t % tiles_x) * LP_TW;
         const int Y0 = a.y_begin + (t / tiles_x) * LP_TH;
         const int cols = 8 * (LP_TP + LP_NQ);
 #pragma unroll
         for (int p = 0; p < LP_PF; ++p) {
-            const int e = tid + 512 * p;
-            const int r = e / pitch, c = e - r * pitch;
+            const int e2 = 2 * (tid + 512 * p);
+            const int r = e2 / pitch, c = e2 - r * pitch;
             const int gy = Y0 - a.h + r, gx = X0 - a.h + c;
-            float v = 0.f;
-            if (r < rows && c < cols && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
-                v = a.X[(size_t)gy * a.W + gx];
-            pf[p] = v;
+            const bool row_ok = r < rows && gy >= 0 && gy < a.H;
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                float x = 0.f;
+                if (row_ok && c + v < cols && gx + v >= 0 && gx + v < a.W)
+                    x = a.X[(size_t)gy * a.W + gx + v];
+                pf[p][v] = x;
+            }
         }
     };
     auto store = [&]() {
         const int cols = 8 * (LP_TP + LP_NQ);
 #pragma unroll
         for (int p = 0; p < LP_PF; ++p) {
-            const int e = tid + 512 * p;
-            const int r = e / pitch, c = e - r * pitch;
+            const int e2 = 2 * (tid + 512 * p);
+            const int r = e2 / pitch, c = e2 - r * pitch;
             if (r < rows) {
-                const float xv = (c < cols) ? (pf[p] - a.ped) * xscale : 0.f;
-                uint32_t hi, lo;
-                split16<FP16>(xv, hi, lo);
-                hiT[e] = (uint16_t)hi;
-                loT[e] = SPLIT_R ? (uint16_t)lo : (uint16_t)0;
+                uint32_t hw = 0, lw = 0;
+#pragma unroll
+                for (int v = 0; v < 2; ++v) {
+                    const float xv = (c + v < cols) ? (pf[p][v] - a.ped) * xscale : 0.f;
+                    uint32_t hi, lo;
+                    split16<FP16>(xv, hi, lo);
+                    hw |= hi << (16 * v);
+                    lw |= (SPLIT_R ? lo : 0u) << (16 * v);
+                }
+                reinterpret_cast<uint32_t*>(hiT)[e2 >> 1] = hw;
+                reinterpret_cast<uint32_t*>(loT)[e2 >> 1] = lw;
             }
         }
     };
@@ -614,7 +635,7 @@ static int launch_lowp_t(const ContractArgs& a, const uint16_t* frag, bool reg, 
     const size_t table_bytes = (size_t)g.n_rg * g.n_q * NB * HALVES * 64 * 16;
     const size_t coef_bytes = (size_t)kMaxSpatialTerms * 4;   // gamma
     const size_t resident_bytes = tile_bytes + table_bytes + coef_bytes;
-    const bool fits_pf = (size_t)g.lds_rows * g.lds_pitch <= (size_t)512 * LP_PF;
+    const bool fits_pf = (size_t)g.lds_rows * g.lds_pitch <= (size_t)1024 * LP_PF;
     if (resident_bytes <= (size_t)160 * 1024 && fits_pf && n_tiles >= 2 * num_cus()) {
         const int n_wg = num_cus();
         const int per = (n_tiles + n_wg - 1) / n_wg;
@@ -646,7 +667,10 @@ static int launch_lowp_nbm(const ContractArgs& a, const uint16_t* frag, int nb, 
         case 1: return launch_lowp_t<1, MB, FP16, SR, SB>(a, frag, reg, s);
         case 2: return launch_lowp_t<2, MB, FP16, SR, SB>(a, frag, reg, s);
         case 3: return launch_lowp_t<3, MB, FP16, SR, SB>(a, frag, reg, s);
-        case 4: return launch_lowp_t<4, MB, FP16, SR, SB>(a, frag, reg, s);
+        case 4:
+            // 49+ filters with more than 16 spatial terms exceed N * M <= 1024
+            if constexpr (MB == 1) return launch_lowp_t<4, MB, FP16, SR, SB>(a, frag, reg, s);
+            return fail(SVCONV_EUNSUPPORTED, "more than 48 filters with more than 16 terms");
         default: return fail(SVCONV_EUNSUPPORTED, "more than 64 filters");
     }
 }
