@@ -66,6 +66,8 @@ def main():
     ap.add_argument("--forms", default="basis,regrouped")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the forward + adjoint timing on the 4096 x 4096 workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (steps times), the "
                          "reference for scaling HBM byte counters")
@@ -119,6 +121,50 @@ def main():
                 results[(form, prec)] = dict(ms=ms, mpix=mpix)
                 log("  %-9s %-7s %8.3f ms  %10.1f Mpix/s" % (form, prec, ms, mpix))
         plan.close()
+
+    # forward + adjoint (dL/dR and dL/da) on the differentiation workload:
+    # 4096 x 4096, 31 x 31 kernel, 49 bases, spatial degree 3
+    adjoint = None
+    if not args.no_adjoint:
+        wl3 = synth.WORKLOADS["c3"]
+        log("inputs: %s %dx%d (adjoint)" % (wl3.name, wl3.height, wl3.width))
+        R3, a3 = synth.workload_inputs(wl3)
+        I3 = synth.second_image(wl3)
+        G3 = synth.uniform_image(wl3.height, wl3.width, seed=3, lo=-60.0, hi=60.0)
+        with torch.cuda.stream(stream):
+            R3d, I3d, a3d, G3d = (torch.from_numpy(x).cuda() for x in (R3, I3, a3, G3))
+            D3 = torch.empty_like(R3d)
+            plan3 = svconv.plan_for(wl3, precision="fp32", pedestal=synth.SKY_LEVEL)
+
+            def timed(fn, n):
+                for _ in range(args.warmup):
+                    fn()
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(n):
+                    fn()
+                e1.record()
+                torch.cuda.synchronize()
+                return e0.elapsed_time(e1) / n
+
+            n3 = max(2, args.steps // 4)
+            adjoint = {"workload": wl3.description}
+            for prec in ("fp32", "bf16x3"):
+                plan3.set_precision(prec)
+                adjoint["forward_%s_ms" % prec] = round(
+                    timed(lambda: plan3.difference(R3d, I3d, a3d, out=D3), n3), 4)
+            adjoint["backward_ms"] = round(timed(lambda: plan3.backward(R3d, a3d, G3d), n3), 4)
+            adjoint["backward_dR_ms"] = round(
+                timed(lambda: plan3.backward(R3d, a3d, G3d, want_ga=False), n3), 4)
+            adjoint["backward_da_ms"] = round(
+                timed(lambda: plan3.backward(R3d, a3d, G3d, want_gR=False), n3), 4)
+            px3 = wl3.height * wl3.width
+            adjoint["forward_backward_mpix"] = round(
+                px3 / ((adjoint["forward_bf16x3_ms"] + adjoint["backward_ms"]) * 1e-3) / 1e6, 2)
+            plan3.close()
+        log("  adjoint: %s" % adjoint)
 
     # CPU baseline: the FP64 oracle on a bounded random sample of pixels; its
     # values also give the error of every form on that sample.
@@ -221,6 +267,8 @@ def main():
                             "ms": round(results[rg]["ms"], 4), "flop_per_pixel": pp,
                             "achieved_tflops": round(ach, 3),
                             "max_err_sigma": results[rg].get("max_err_sigma")}
+    if adjoint is not None:
+        out["adjoint"] = adjoint
     out["forms"] = {"%s/%s" % k_: {kk: (round(v, 6) if isinstance(v, float) else v)
                                    for kk, v in r.items()} for k_, r in results.items()}
     print(json.dumps(out), flush=True)
