@@ -89,6 +89,17 @@ int svconv_plan_create(svconv_plan** out, int height, int width, int half_width,
                        const double* sigmas, const int* degrees, int spatial_degree,
                        int precision);
 
+/*
+ * Create a plan with the Dirac delta basis (Sec. 2: one basis function per
+ * kernel pixel, k^2 bases with k^2 spatial polynomials): basis
+ * n = (v + h) k + (u + h) is 1 at kernel pixel (u, v) and 0 elsewhere, so
+ * K(x,y)[u,v] = sum_m a[n(u,v)][m] P_m(x,y) and a is [k^2][M].  The plan
+ * starts in SVCONV_FORM_REGROUPED; the basis form and the normal matrix need
+ * k^2 <= 64.  Limits as svconv_plan_create (k^2 M <= 1024).
+ */
+int svconv_plan_create_dfb(svconv_plan** out, int height, int width, int half_width,
+                           int spatial_degree, int precision);
+
 /* Crop support: the image is the sub-array at (x0, y0) of a frame of
  * frame_width x frame_height pixels; spatial terms use frame coordinates.
  * EINVAL unless 0 <= x0, 0 <= y0, x0 + width <= frame_width, y0 + height

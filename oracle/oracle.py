@@ -54,6 +54,7 @@ def _load():
         lib.orc_n_basis.argtypes = [i, _ip]
         lib.orc_n_spatial.argtypes = [i]
         lib.orc_basis.argtypes = [i, i, _dp, _ip, _dp]
+        lib.orc_basis_dfb.argtypes = [i, _dp]
         lib.orc_spatial_terms.argtypes = [d, d, i, _dp]
         lib.orc_spatial_terms.restype = None
         lib.orc_kernel_at.argtypes = [i, i, i, i, _dp, i, _dp, i, i, i, i, _dp]
@@ -103,6 +104,14 @@ def basis(h, sigmas, degrees):
     k = 2 * h + 1
     out = np.zeros((N, k, k))
     _check(_load().orc_basis(int(h), len(sig), _ptr(sig), _ptr(deg, _ip), _ptr(out)), "basis")
+    return out
+
+
+def basis_dfb(h):
+    """Dirac delta basis: k*k bases, B[n] = 1 at n = (v+h) k + (u+h) (Sec. 2)."""
+    k = 2 * h + 1
+    out = np.zeros((k * k, k, k))
+    _check(_load().orc_basis_dfb(int(h), _ptr(out)), "basis_dfb")
     return out
 
 

@@ -95,6 +95,20 @@ int orc_basis(int h, int n_gauss, const double* sigmas, const int* degrees, doub
     return n;
 }
 
+/*
+ * Dirac delta basis (Sec. 2: one basis function per kernel pixel): basis
+ * n = (v+h) k + (u+h) is 1 at (u, v) and 0 elsewhere.  out[n][k][k].
+ */
+int orc_basis_dfb(int h, double* out)
+{
+    if (h < 0) return ORC_EINVAL;
+    const int k = 2 * h + 1;
+    const int N = k * k;
+    for (int n = 0; n < N; ++n)
+        for (int q = 0; q < N; ++q) out[(size_t)n * N + q] = (q == n) ? 1.0 : 0.0;
+    return N;
+}
+
 /* Normalised full-frame coordinate of an array index (frame offset off). */
 static double norm_coord(int idx, int off, int frame)
 {

@@ -25,6 +25,7 @@ _i = ctypes.c_int
 SIGNATURES = {
     "svconv_plan_create": (_i, [ctypes.POINTER(_vp), _i, _i, _i, _i,
                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i), _i, _i]),
+    "svconv_plan_create_dfb": (_i, [ctypes.POINTER(_vp), _i, _i, _i, _i, _i]),
     "svconv_plan_set_frame": (_i, [_vp, _i, _i, _i, _i]),
     "svconv_plan_set_stream": (_i, [_vp, _vp]),
     "svconv_plan_set_precision": (_i, [_vp, _i]),

@@ -72,6 +72,7 @@ struct svconv_plan {
     int N = 0, d_s = 0, M = 0;
     int precision = SVCONV_FP32;
     int form = SVCONV_FORM_BASIS;
+    bool dfb = false;                   // Dirac delta basis (one basis per kernel pixel)
     int x0 = 0, y0 = 0, Wf = 0, Hf = 0;
     float pedestal = 0.f;
     hipStream_t stream = nullptr;

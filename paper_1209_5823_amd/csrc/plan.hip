@@ -107,6 +107,74 @@ static bool is_fp16(int precision) {
 
 using namespace svc;
 
+// Device tables, scratch and basis-form fragments of a plan whose sizes and
+// host basis table are set.
+static int finish_plan(svconv_plan* p, svconv_plan** out) {
+    p->Wf = p->W;
+    p->Hf = p->H;
+
+    int st = hip_status(hipGetDevice(&p->device), "hipGetDevice");
+    if (st) { free_plan(p); return st; }
+
+    const int k = p->k, kk = k * k;
+    // correlation-oriented tables: F_n[dv][du] = B_n[2h-dv][2h-du]
+    std::vector<float> F32((size_t)p->N * kk);
+    std::vector<double> F64((size_t)p->N * kk), beta(p->N);
+    for (int n = 0; n < p->N; ++n) {
+        double s = 0.0;
+        for (int dv = 0; dv < k; ++dv)
+            for (int du = 0; du < k; ++du) {
+                const double b = p->basis[(size_t)n * kk + (size_t)(k - 1 - dv) * k + (k - 1 - du)];
+                F64[(size_t)n * kk + dv * k + du] = b;
+                F32[(size_t)n * kk + dv * k + du] = (float)b;
+                s += b;
+            }
+        beta[n] = s;
+    }
+
+    // basis-form fragment tables exist only for N <= 64 (a delta basis with
+    // more kernel pixels is contracted in the regrouped form only)
+    const int nbN = p->N <= kMaxFilters ? (p->N + 15) / 16 : 1;
+    const size_t frag32 = f32_fragment_floats(k, nbN);
+    const size_t fragT32 = f32_fragment_floats(k, (kMaxSpatialTerms + 15) / 16);
+    const size_t fraglN = lowp_fragment_elems(k, nbN);
+    const size_t fraglT = lowp_fragment_elems(k, (kMaxSpatialTerms + 15) / 16);
+    if ((st = dalloc(&p->dF32, F32.size(), "basis table")) ||
+        (st = dalloc(&p->dF64, F64.size(), "basis table (f64)")) ||
+        (st = dalloc(&p->dBeta, beta.size(), "basis sums")) ||
+        (st = dalloc(&p->dFragF32, frag32, "fp32 fragments")) ||
+        (st = dalloc(&p->dFragLoB, fraglN, "bf16 fragments")) ||
+        (st = dalloc(&p->dFragLoH, fraglN, "fp16 fragments")) ||
+        (st = dalloc(&p->dScaleB, (size_t)2 * kMaxFilters, "bf16 scales")) ||
+        (st = dalloc(&p->dScaleH, (size_t)2 * kMaxFilters, "fp16 scales")) ||
+        (st = dalloc(&p->dFt32, (size_t)kMaxFilters * kk, "per-call filters")) ||
+        (st = dalloc(&p->dBetaT, (size_t)kMaxFilters, "per-call sums")) ||
+        (st = dalloc(&p->dFragT32, fragT32, "per-call fp32 fragments")) ||
+        (st = dalloc(&p->dFragTB, fraglT, "per-call bf16 fragments")) ||
+        (st = dalloc(&p->dFragTH, fraglT, "per-call fp16 fragments")) ||
+        (st = dalloc(&p->dScaleT, (size_t)2 * kMaxFilters, "per-call scales")) ||
+        (st = dalloc(&p->dVec, (size_t)4 * kMaxCoefficients + 64, "vector scratch")) ||
+        (st = dalloc(&p->dStatus, (size_t)4, "status word")) ||
+        (st = dalloc(&p->dGrad, (size_t)p->H * p->W, "loss gradient")) ||
+        (st = dalloc(&p->dRed, (size_t)2048, "reduction scratch")) ||
+        (st = dalloc(&p->dQpart, adjoint_scratch_doubles(p->H, p->W, p->k, p->M), "adjoint scratch"))) {
+        free_plan(p);
+        return st;
+    }
+    st = hip_status(hipMemcpy(p->dF32, F32.data(), F32.size() * 4, hipMemcpyHostToDevice), "upload");
+    if (!st) st = hip_status(hipMemcpy(p->dF64, F64.data(), F64.size() * 8, hipMemcpyHostToDevice), "upload");
+    if (!st) st = hip_status(hipMemcpy(p->dBeta, beta.data(), beta.size() * 8, hipMemcpyHostToDevice), "upload");
+    if (!st && p->N <= kMaxFilters) {
+        st = build_f32_fragments(p->dF32, p->N, k, p->dFragF32, nullptr);
+        if (!st) st = build_lowp_fragments(p->dF32, p->N, k, 0, p->dScaleB, p->dFragLoB, nullptr);
+        if (!st) st = build_lowp_fragments(p->dF32, p->N, k, 1, p->dScaleH, p->dFragLoH, nullptr);
+    }
+    if (!st) st = hip_status(hipDeviceSynchronize(), "plan table build");
+    if (st) { free_plan(p); return st; }
+    *out = p;
+    return SVCONV_OK;
+}
+
 extern "C" {
 
 const char* svconv_strerror(int status) {
@@ -161,68 +229,46 @@ int svconv_plan_create(svconv_plan** out, int height, int width, int half_width,
     p->d_s = spatial_degree;
     p->M = M;
     p->precision = precision;
-    p->Wf = width;
-    p->Hf = height;
     p->sigmas.assign(sigmas, sigmas + n_gauss);
     p->degrees.assign(degrees, degrees + n_gauss);
     build_basis(p->h, p->sigmas, p->degrees, p->basis);
+    return finish_plan(p, out);
+}
 
-    int st = hip_status(hipGetDevice(&p->device), "hipGetDevice");
-    if (st) { free_plan(p); return st; }
-
-    const int k = p->k, kk = k * k;
-    // correlation-oriented tables: F_n[dv][du] = B_n[2h-dv][2h-du]
-    std::vector<float> F32((size_t)p->N * kk);
-    std::vector<double> F64((size_t)p->N * kk), beta(p->N);
-    for (int n = 0; n < p->N; ++n) {
-        double s = 0.0;
-        for (int dv = 0; dv < k; ++dv)
-            for (int du = 0; du < k; ++du) {
-                const double b = p->basis[(size_t)n * kk + (size_t)(k - 1 - dv) * k + (k - 1 - du)];
-                F64[(size_t)n * kk + dv * k + du] = b;
-                F32[(size_t)n * kk + dv * k + du] = (float)b;
-                s += b;
-            }
-        beta[n] = s;
-    }
-
-    const int nbN = (p->N + 15) / 16;
-    const size_t frag32 = f32_fragment_floats(k, nbN);
-    const size_t fragT32 = f32_fragment_floats(k, (kMaxSpatialTerms + 15) / 16);
-    const size_t fraglN = lowp_fragment_elems(k, nbN);
-    const size_t fraglT = lowp_fragment_elems(k, (kMaxSpatialTerms + 15) / 16);
-    if ((st = dalloc(&p->dF32, F32.size(), "basis table")) ||
-        (st = dalloc(&p->dF64, F64.size(), "basis table (f64)")) ||
-        (st = dalloc(&p->dBeta, beta.size(), "basis sums")) ||
-        (st = dalloc(&p->dFragF32, frag32, "fp32 fragments")) ||
-        (st = dalloc(&p->dFragLoB, fraglN, "bf16 fragments")) ||
-        (st = dalloc(&p->dFragLoH, fraglN, "fp16 fragments")) ||
-        (st = dalloc(&p->dScaleB, (size_t)2 * kMaxFilters, "bf16 scales")) ||
-        (st = dalloc(&p->dScaleH, (size_t)2 * kMaxFilters, "fp16 scales")) ||
-        (st = dalloc(&p->dFt32, (size_t)kMaxFilters * kk, "per-call filters")) ||
-        (st = dalloc(&p->dBetaT, (size_t)kMaxFilters, "per-call sums")) ||
-        (st = dalloc(&p->dFragT32, fragT32, "per-call fp32 fragments")) ||
-        (st = dalloc(&p->dFragTB, fraglT, "per-call bf16 fragments")) ||
-        (st = dalloc(&p->dFragTH, fraglT, "per-call fp16 fragments")) ||
-        (st = dalloc(&p->dScaleT, (size_t)2 * kMaxFilters, "per-call scales")) ||
-        (st = dalloc(&p->dVec, (size_t)4 * kMaxCoefficients + 64, "vector scratch")) ||
-        (st = dalloc(&p->dStatus, (size_t)4, "status word")) ||
-        (st = dalloc(&p->dGrad, (size_t)p->H * p->W, "loss gradient")) ||
-        (st = dalloc(&p->dRed, (size_t)2048, "reduction scratch")) ||
-        (st = dalloc(&p->dQpart, adjoint_scratch_doubles(p->H, p->W, p->k, p->M), "adjoint scratch"))) {
-        free_plan(p);
-        return st;
-    }
-    st = hip_status(hipMemcpy(p->dF32, F32.data(), F32.size() * 4, hipMemcpyHostToDevice), "upload");
-    if (!st) st = hip_status(hipMemcpy(p->dF64, F64.data(), F64.size() * 8, hipMemcpyHostToDevice), "upload");
-    if (!st) st = hip_status(hipMemcpy(p->dBeta, beta.data(), beta.size() * 8, hipMemcpyHostToDevice), "upload");
-    if (!st) st = build_f32_fragments(p->dF32, p->N, k, p->dFragF32, nullptr);
-    if (!st) st = build_lowp_fragments(p->dF32, p->N, k, 0, p->dScaleB, p->dFragLoB, nullptr);
-    if (!st) st = build_lowp_fragments(p->dF32, p->N, k, 1, p->dScaleH, p->dFragLoH, nullptr);
-    if (!st) st = hip_status(hipDeviceSynchronize(), "plan table build");
-    if (st) { free_plan(p); return st; }
-    *out = p;
-    return SVCONV_OK;
+// Dirac delta basis (Sec. 2: one basis function per kernel pixel): basis n =
+// (v + h) k + (u + h) is 1 at (u, v) and 0 elsewhere, so K(x,y)[u,v] =
+// sum_m a[n(u,v)][m] P_m(x,y).
+int svconv_plan_create_dfb(svconv_plan** out, int height, int width, int half_width,
+                           int spatial_degree, int precision) {
+    g_last_error.clear();
+    if (!out) return fail(SVCONV_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (height <= 0 || width <= 0) return fail(SVCONV_EINVAL, "image size must be positive");
+    if (half_width < 0) return fail(SVCONV_EINVAL, "half_width < 0");
+    if (spatial_degree < 0) return fail(SVCONV_EINVAL, "spatial_degree < 0");
+    if (precision < SVCONV_FP32 || precision > SVCONV_FP16X3)
+        return fail(SVCONV_EINVAL, "unknown precision");
+    if (half_width > kMaxHalfWidth) return fail(SVCONV_EUNSUPPORTED, "half_width > 31");
+    if (spatial_degree > kMaxSpatialDegree) return fail(SVCONV_EUNSUPPORTED, "spatial_degree > 6");
+    const int M = (spatial_degree + 1) * (spatial_degree + 2) / 2;
+    const long k = 2L * half_width + 1;
+    const long N = k * k;
+    if (N * M > kMaxCoefficients) return fail(SVCONV_EUNSUPPORTED, "N * M > 1024");
+    svconv_plan* p = new (std::nothrow) svconv_plan();
+    if (!p) return fail(SVCONV_ENOMEM, "host allocation of the plan");
+    p->H = height;
+    p->W = width;
+    p->h = half_width;
+    p->k = (int)k;
+    p->N = (int)N;
+    p->d_s = spatial_degree;
+    p->M = M;
+    p->precision = precision;
+    p->dfb = true;
+    p->form = SVCONV_FORM_REGROUPED;
+    p->basis.assign((size_t)N * N, 0.0);
+    for (long n = 0; n < N; ++n) p->basis[(size_t)n * N + n] = 1.0;
+    return finish_plan(p, out);
 }
 
 int svconv_plan_set_frame(svconv_plan* p, int x0, int y0, int frame_width, int frame_height) {
@@ -255,6 +301,8 @@ int svconv_plan_set_form(svconv_plan* p, int form) {
     if (!p) return fail(SVCONV_EINVAL, "plan is NULL");
     if (form != SVCONV_FORM_BASIS && form != SVCONV_FORM_REGROUPED)
         return fail(SVCONV_EINVAL, "unknown form");
+    if (form == SVCONV_FORM_BASIS && p->N > kMaxFilters)
+        return fail(SVCONV_EUNSUPPORTED, "basis form needs N <= 64");
     p->form = form;
     return SVCONV_OK;
 }
@@ -303,6 +351,7 @@ static int run_forward(svconv_plan* p, const float* R, const float* I, const flo
     coords(p, c);
     const bool lowp = is_lowp(p->precision);
     if (p->form == SVCONV_FORM_BASIS) {
+        if (p->N > kMaxFilters) return fail(SVCONV_EUNSUPPORTED, "basis form needs N <= 64");
         c.NF = p->N;
         c.coef = a;
         c.beta = p->dBeta;

@@ -40,16 +40,25 @@ class Plan:
 
     def __init__(self, height, width, half_width, sigmas, degrees, spatial_degree,
                  precision="fp32", form="basis", frame=None, pedestal=0.0):
+        """Gaussian-basis plan; sigmas=None, degrees=None gives the Dirac delta
+        basis (one basis per kernel pixel, see ``Plan.dfb``)."""
         self._lib = _lib.load()
         self._p = ctypes.c_void_p()
-        sig = (ctypes.c_double * len(sigmas))(*[float(s) for s in sigmas])
-        deg = (ctypes.c_int * len(degrees))(*[int(d) for d in degrees])
-        if len(sigmas) != len(degrees):
-            raise ValueError("sigmas and degrees differ in length")
-        check(self._lib.svconv_plan_create(ctypes.byref(self._p), int(height), int(width),
-                                           int(half_width), len(sigmas), sig, deg,
-                                           int(spatial_degree), PRECISIONS[precision]),
-              "svconv_plan_create")
+        if sigmas is None:
+            check(self._lib.svconv_plan_create_dfb(ctypes.byref(self._p), int(height), int(width),
+                                                   int(half_width), int(spatial_degree),
+                                                   PRECISIONS[precision]),
+                  "svconv_plan_create_dfb")
+            sigmas, degrees = (), ()
+        else:
+            sig = (ctypes.c_double * len(sigmas))(*[float(s) for s in sigmas])
+            deg = (ctypes.c_int * len(degrees))(*[int(d) for d in degrees])
+            if len(sigmas) != len(degrees):
+                raise ValueError("sigmas and degrees differ in length")
+            check(self._lib.svconv_plan_create(ctypes.byref(self._p), int(height), int(width),
+                                               int(half_width), len(sigmas), sig, deg,
+                                               int(spatial_degree), PRECISIONS[precision]),
+                  "svconv_plan_create")
         self.height, self.width, self.half_width = int(height), int(width), int(half_width)
         self.k = 2 * self.half_width + 1
         self.sigmas, self.degrees = tuple(sigmas), tuple(degrees)
@@ -63,6 +72,13 @@ class Plan:
             self.set_frame(*frame)
         if pedestal:
             self.set_pedestal(pedestal)
+
+    @classmethod
+    def dfb(cls, height, width, half_width, spatial_degree, precision="fp32", form="regrouped",
+            frame=None, pedestal=0.0):
+        """Dirac delta basis plan (svconv_plan_create_dfb): a is [k*k][M]."""
+        return cls(height, width, half_width, None, None, spatial_degree, precision=precision,
+                   form=form, frame=frame, pedestal=pedestal)
 
     # ---------------------------------------------------------- settings --
     def set_frame(self, x0, y0, frame_width, frame_height):

@@ -67,6 +67,7 @@ def test_plan_create_rejects_before_any_device_call(lib, kw, status):
 def test_null_plan_and_null_pointers(lib):
     E = _lib.EINVAL
     assert lib.svconv_plan_create(None, 8, 8, 1, 1, None, None, 0, 0) == E
+    assert lib.svconv_plan_create_dfb(None, 8, 8, 1, 0, 0) == E
     assert lib.svconv_plan_set_frame(None, 0, 0, 8, 8) == E
     assert lib.svconv_plan_set_stream(None, None) == E
     assert lib.svconv_plan_set_precision(None, 0) == E
@@ -83,6 +84,20 @@ def test_null_plan_and_null_pointers(lib):
     assert lib.svconv_cholesky_solve(None, None, None, None, 4) == E
     assert lib.svconv_gn_step(None, None, None, None, None, None, None, None, None) == E
     assert lib.svconv_plan_destroy(None) == _lib.OK
+
+
+@pytest.mark.parametrize("args,status", [
+    ((0, 8, 1, 0, 0), _lib.EINVAL),
+    ((8, 8, -1, 0, 0), _lib.EINVAL),
+    ((8, 8, 1, -1, 0), _lib.EINVAL),
+    ((8, 8, 1, 0, 7), _lib.EINVAL),
+    ((8, 8, 32, 0, 0), _lib.EUNSUPPORTED),
+    ((8, 8, 7, 2, 0), _lib.EUNSUPPORTED),      # 225 delta bases x 6 terms > 1024
+])
+def test_dfb_plan_rejects_before_any_device_call(lib, args, status):
+    p = ctypes.c_void_p()
+    assert lib.svconv_plan_create_dfb(ctypes.byref(p), *args) == status
+    assert not p.value
 
 
 def test_strerror(lib):

@@ -330,3 +330,44 @@ def test_normal_equations_recover_noiseless_coefficients(orc):
     ga = orc.grad_a(R, h, B, d_s, G)
     assert np.allclose(ga.ravel(), 2.0 * (JtJ @ a0.ravel() - rhs), rtol=1e-9,
                        atol=1e-9 * np.abs(ga).max())
+
+
+# ------------------------------------------------ Dirac delta basis ----
+
+def test_dfb_basis_is_one_impulse_per_kernel_pixel(orc):
+    # the delta basis has one basis function per kernel pixel (Sec. 2)
+    for h in (0, 1, 3):
+        B = orc.basis_dfb(h)
+        k = 2 * h + 1
+        assert B.shape == (k * k, k, k)
+        assert np.array_equal(B.reshape(k * k, k * k), np.eye(k * k))
+
+
+def test_dfb_impulse_response_is_the_coefficient_polynomial(orc):
+    # R = unit impulse at (xc, yc): C(x, y) = K(x,y)[x - xc, y - yc]
+    #   = sum_m a[n][m] P_m(x, y) with n the kernel pixel (x - xc, y - yc);
+    # degree-1 terms written out: a0 + a1 xh + a2 yh
+    H, W, h = 21, 23, 3
+    xc, yc = 11, 9
+    k = 2 * h + 1
+    r = np.random.default_rng(12)
+    a = r.normal(size=(k * k, 3))
+    R = np.zeros((H, W)); R[yc, xc] = 1.0
+    C = orc.convolve(R, h, orc.basis_dfb(h), 1, a)
+    for (x, y) in [(xc, yc), (xc + 3, yc - 2), (xc - 1, yc + 3), (xc - 3, yc - 3)]:
+        u, v = x - xc, y - yc
+        n = (v + h) * k + (u + h)
+        xh, yh = 2.0 * x / (W - 1) - 1.0, 2.0 * y / (H - 1) - 1.0
+        assert abs(C[y, x] - (a[n, 0] + a[n, 1] * xh + a[n, 2] * yh)) < 1e-14
+    assert C[yc, xc + h + 1] == 0.0
+
+
+def test_dfb_regrouped_fft_identity(orc):
+    # the paper's own case: 7 x 7 delta basis, second-order polynomial
+    r = np.random.default_rng(13)
+    R = synth.star_field(90, 130, 40, seed=13)
+    a = r.uniform(-0.05, 0.05, size=(49, 6)); a[24, 0] = 1.0
+    B = orc.basis_dfb(3)
+    Cd = orc.convolve(R, 3, B, 2, a, frame=(100, 200, 4868, 4846))
+    Cf = orc.convolve_fft(R, 3, B, 2, a, frame=(100, 200, 4868, 4846))
+    assert np.max(np.abs(Cd - Cf)) < 1e-12 * np.max(np.abs(Cd))
