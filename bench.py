@@ -68,6 +68,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the forward + adjoint timing on the 4096 x 4096 workload")
+    ap.add_argument("--no-dfb", action="store_true",
+                    help="skip the Dirac delta basis size sweep")
+    ap.add_argument("--no-pipeline", action="store_true",
+                    help="skip the streamed host-tile pipeline measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (steps times), the "
                          "reference for scaling HBM byte counters")
@@ -165,6 +169,9 @@ def main():
                 px3 / ((adjoint["forward_bf16x3_ms"] + adjoint["backward_ms"]) * 1e-3) / 1e6, 2)
             plan3.close()
         log("  adjoint: %s" % adjoint)
+
+    dfb = None if args.no_dfb else dfb_sweep(args, stream)
+    pipeline = None if args.no_pipeline else pipeline_bench(args)
 
     # CPU baseline: the FP64 oracle on a bounded random sample of pixels; its
     # values also give the error of every form on that sample.
@@ -269,9 +276,127 @@ def main():
                             "max_err_sigma": results[rg].get("max_err_sigma")}
     if adjoint is not None:
         out["adjoint"] = adjoint
+    if dfb is not None:
+        out["dfb"] = dfb
+    if pipeline is not None:
+        out["pipeline"] = pipeline
     out["forms"] = {"%s/%s" % k_: {kk: (round(v, 6) if isinstance(v, float) else v)
                                    for kk, v in r.items()} for k_, r in results.items()}
     print(json.dumps(out), flush=True)
+
+
+DFB_SIZES = ((256, 256), (512, 512), (1024, 1024), (2048, 2048), (4096, 4096), (4846, 4868))
+DFB_FORMS = (("regrouped", "fp32"), ("regrouped", "bf16x3"), ("regrouped", "fp16x3"),
+             ("basis", "fp16x3"))
+
+
+def dfb_sweep(args, stream):
+    """The paper's own benchmark case (Sec. 3): 7 x 7 Dirac delta basis
+    (49 bases, one per kernel pixel), second-order spatial polynomial, image
+    sizes from 256 x 256 up to one 4846 x 4868 camera tile.  Smaller sizes are
+    top-left crops of the tile.  Reports, per size, each form's time and
+    Mpix/s, the rate in the paper's DFB FLOP model (20 L^2 + 1 per pixel) and
+    the error of each form on sampled pixels of the full tile."""
+    import numpy as np
+    import torch
+
+    import synth
+    from oracle import oracle
+    from paper_1209_5823_amd import svconv, flops
+
+    h, d_s = 3, 2
+    k = 2 * h + 1
+    Ht, Wt = DFB_SIZES[-1]
+    log("inputs: dfb %dx%d tile, %dx%d kernel" % (Ht, Wt, k, k))
+    tile = synth.star_field(Ht, Wt, 20000, seed=11)
+    a_h = synth.coefficients(k * k, synth.n_spatial(d_s), (k * k) // 2, seed=11)
+    sweep = []
+    errs = {}
+    with torch.cuda.stream(stream):
+        a = torch.from_numpy(a_h).cuda()
+        for (H, W) in DFB_SIZES:
+            R = torch.from_numpy(np.ascontiguousarray(tile[:H, :W])).cuda()
+            I = R.clone()
+            D = torch.empty_like(R)
+            row = {"height": H, "width": W}
+            best = None
+            with svconv.Plan.dfb(H, W, h, d_s, pedestal=synth.SKY_LEVEL) as plan:
+                for form, prec in DFB_FORMS:
+                    ms = time_form(plan, args, R, I, a, D, prec, form)
+                    if ms is None:
+                        continue
+                    mpix = H * W / (ms * 1e-3) / 1e6
+                    row["%s/%s" % (form, prec)] = {"ms": round(ms, 4), "mpix": round(mpix, 1)}
+                    if best is None or mpix > best[0]:
+                        best = (mpix, form, prec)
+                    if (H, W) == (Ht, Wt):
+                        torch.cuda.synchronize()
+                        errs[(form, prec)] = D.cpu().numpy()
+            row["best"] = "%s/%s" % best[1:]
+            row["best_mpix"] = round(best[0], 1)
+            row["paper_model_gflops"] = round(flops.paper_flops_dfb(k) * best[0] * 1e6 / 1e9, 1)
+            log("  dfb %5dx%-5d best %-16s %9.1f Mpix/s" % (H, W, row["best"], best[0]))
+            sweep.append(row)
+    # error of every form on 4000 random pixels + the 64 brightest of the tile
+    rng = np.random.default_rng(99)
+    xs = rng.integers(0, Wt, 4000).astype(np.int32)
+    ys = rng.integers(0, Ht, 4000).astype(np.int32)
+    flat = np.argsort(tile.ravel())[-64:]
+    xs = np.concatenate([xs, (flat % Wt).astype(np.int32)])
+    ys = np.concatenate([ys, (flat // Wt).astype(np.int32)])
+    ref = oracle.convolve_at(tile, h, oracle.basis_dfb(h), d_s, a_h, xs, ys) - tile[ys, xs]
+    sig = synth.sky_sigma()
+    err = {"%s/%s" % key: round(float(np.max(np.abs(Dg[ys, xs] - ref)) / sig), 6)
+           for key, Dg in errs.items()}
+    return {"kernel": k, "n_basis": k * k, "spatial_degree": d_s,
+            "paper_flop_per_pixel": flops.paper_flops_dfb(k),
+            "max_err_sigma_tile": err, "sizes": sweep}
+
+
+def pipeline_bench(args):
+    """End-to-end rate with the images in host memory (Sec. 3: a 60-tile
+    mosaic camera of 4846 x 4868 tiles; Sec. 4: asynchronous copies between
+    page-locked host memory and the device).  Each tile's R and I are copied
+    in and D copied back while other tiles are differenced.  The mosaic cycles
+    through 4 distinct page-locked tiles.  Reported beside the HBM-resident
+    headline, never instead of it: the host link, not the kernel, bounds it."""
+    import numpy as np
+
+    import synth
+    from paper_1209_5823_amd import svconv
+
+    H, W, n_tiles, n_distinct = 4846, 4868, 60, 4
+    res = {"tiles": n_tiles, "tile": [H, W], "distinct_tiles": n_distinct, "depth": 3}
+    host = []
+    for t in range(n_distinct):
+        R = svconv.pinned_empty((H, W))
+        R.numpy()[:] = synth.star_field(H, W, 20000, seed=200 + t)
+        I = svconv.pinned_empty((H, W))
+        I.numpy()[:] = R.numpy()
+        host.append((R, I, svconv.pinned_empty((H, W))))
+    cases = [("dfb7_regrouped_fp16x3", dict(half_width=3, sigmas=None, degrees=None,
+                                            spatial_degree=2, precision="fp16x3",
+                                            form="regrouped")),
+             ("gauss21_basis_fp16x3", dict(half_width=10, sigmas=(0.7, 1.5, 2.0),
+                                           degrees=(6, 4, 2), spatial_degree=2,
+                                           precision="fp16x3", form="basis"))]
+    for name, kw in cases:
+        with svconv.Plan(H, W, pedestal=synth.SKY_LEVEL, **kw) as plan:
+            a = synth.coefficients(plan.n_basis, plan.n_spatial, 0, seed=5)
+            Rs = [host[t % n_distinct][0] for t in range(n_tiles)]
+            Is = [host[t % n_distinct][1] for t in range(n_tiles)]
+            Ds = [host[t % n_distinct][2] for t in range(n_tiles)]
+            As = [a] * n_tiles
+            with svconv.Pipeline(plan, depth=res["depth"]) as pipe:
+                pipe.run(Rs[:n_distinct], Is[:n_distinct], As[:n_distinct], Ds[:n_distinct])
+                t0 = time.perf_counter()
+                pipe.run(Rs, Is, As, Ds)
+                dt = time.perf_counter() - t0
+        mpix = n_tiles * H * W / dt / 1e6
+        gbs = n_tiles * 3 * H * W * 4 / dt / 1e9
+        res[name] = {"s": round(dt, 4), "mpix": round(mpix, 1), "host_link_gbs": round(gbs, 2)}
+        log("  pipeline %-24s %8.1f Mpix/s  %6.2f GB/s over the host link" % (name, mpix, gbs))
+    return res
 
 
 def recorded_traffic(precision, form):

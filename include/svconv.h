@@ -44,6 +44,8 @@
 #ifndef SVCONV_H
 #define SVCONV_H
 
+#include <stddef.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -180,6 +182,45 @@ int svconv_cholesky_solve(svconv_plan* plan, const double* L, const double* rhs,
  * synchronises the plan's stream. */
 int svconv_gn_step(svconv_plan* plan, const float* R, const float* I, const unsigned char* mask,
                    const double* L, double* a64, float* a32, float* D, double* host_stats);
+
+/*
+ * Streamed tiles (Sec. 4: asynchronous transfers between page-locked host
+ * memory and the device on streams; Sec. 3: a mosaic camera of many equal
+ * tiles).  A pipeline runs svconv_difference on many tiles of the plan's
+ * size whose images live in HOST memory: tile t is copied in, differenced
+ * and copied back while the neighbouring tiles are in transfer.  It uses the
+ * plan's tables, precision, form, frame and pedestal, but its own three
+ * streams (copies in, compute, copies out); the plan's stream is unchanged.
+ * A plan must not be used elsewhere while one of its pipelines runs.
+ */
+typedef struct svconv_pipeline svconv_pipeline;
+
+/* Page-locked host memory for tile buffers (the copies overlap compute only
+ * from such memory; pageable buffers work but serialise).  *out is a HOST
+ * pointer owned by the caller, released with svconv_host_free.  EINVAL for
+ * bytes == 0, ENOMEM if the allocation fails. */
+int svconv_host_alloc(size_t bytes, void** out);
+
+/* Release memory from svconv_host_alloc (NULL is accepted). */
+int svconv_host_free(void* host_ptr);
+
+/* Create a pipeline over `plan` with `depth` (1..8) slots of device buffers:
+ * depth * (2 H W + N M) floats, allocated here.  The plan must outlive the
+ * pipeline. */
+int svconv_pipeline_create(svconv_plan* plan, int depth, svconv_pipeline** out);
+
+/* For t = 0 .. n_tiles-1: D_host[t] = R_host[t] (x) K(a_host[t]) - I_host[t]
+ * (Eq. 1).  All four arrays hold n_tiles HOST pointers: images float32
+ * [H][W], coefficients float32 [N][M].  D_host[t] may alias I_host[t].
+ * Blocking: returns when every D is in host memory.  EINVAL (before any HIP
+ * call) for a NULL array or tile pointer or n_tiles < 0; n_tiles == 0 does
+ * nothing. */
+int svconv_pipeline_run(svconv_pipeline* pipeline, int n_tiles, const float* const* R_host,
+                        const float* const* I_host, const float* const* a_host,
+                        float* const* D_host);
+
+/* Free the pipeline's buffers, events and streams (NULL is accepted). */
+int svconv_pipeline_destroy(svconv_pipeline* pipeline);
 
 /* Static description of a status code. */
 const char* svconv_strerror(int status);

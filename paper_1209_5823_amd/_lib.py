@@ -42,6 +42,12 @@ SIGNATURES = {
     "svconv_cholesky_factor": (_i, [_vp, _vp, _i]),
     "svconv_cholesky_solve": (_i, [_vp, _vp, _vp, _vp, _i]),
     "svconv_gn_step": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
+    "svconv_host_alloc": (_i, [ctypes.c_size_t, ctypes.POINTER(_vp)]),
+    "svconv_host_free": (_i, [_vp]),
+    "svconv_pipeline_create": (_i, [_vp, _i, ctypes.POINTER(_vp)]),
+    "svconv_pipeline_run": (_i, [_vp, _i, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                 ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
+    "svconv_pipeline_destroy": (_i, [_vp]),
     "svconv_strerror": (ctypes.c_char_p, [_i]),
     "svconv_last_error": (ctypes.c_char_p, []),
 }

@@ -129,6 +129,9 @@ int launch_contract_f32(const ContractArgs& a, const float* frag, int nb, hipStr
 int launch_contract_lowp(const ContractArgs& a, const uint16_t* frag, int nb, int precision,
                          hipStream_t s);
 
+// plan.hip
+int run_forward(svconv_plan* p, const float* R, const float* I, const float* a, float* out);
+
 // backward.hip
 size_t adjoint_scratch_doubles(int H, int W, int k, int M);
 int launch_adjoint_a(svconv_plan* p, const float* R, const float* gD, double* ga);

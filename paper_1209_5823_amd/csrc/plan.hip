@@ -175,6 +175,59 @@ static int finish_plan(svconv_plan* p, svconv_plan** out) {
     return SVCONV_OK;
 }
 
+namespace svc {
+
+// Shared body of svconv_forward, svconv_difference, svconv_gn_step and the
+// tile pipeline: enqueue one forward pass on the plan's stream.
+int run_forward(svconv_plan* p, const float* R, const float* I, const float* a, float* out) {
+    ContractArgs c{};
+    c.X = R;
+    c.H = p->H;
+    c.W = p->W;
+    c.h = p->h;
+    c.M = p->M;
+    c.d_s = p->d_s;
+    c.ped = p->pedestal;
+    c.I = I;
+    c.out = out;
+    c.y_begin = 0;
+    c.n_rows = p->H;
+    coords(p, c);
+    const bool lowp = is_lowp(p->precision);
+    if (p->form == SVCONV_FORM_BASIS) {
+        if (p->N > kMaxFilters) return fail(SVCONV_EUNSUPPORTED, "basis form needs N <= 64");
+        c.NF = p->N;
+        c.coef = a;
+        c.beta = p->dBeta;
+        const int nb = (p->N + 15) / 16;
+        if (!lowp) return launch_contract_f32(c, p->dFragF32, nb, p->stream);
+        c.fscale = (is_fp16(p->precision) ? p->dScaleH : p->dScaleB) + kMaxFilters;
+        return launch_contract_lowp(c, is_fp16(p->precision) ? p->dFragLoH : p->dFragLoB, nb,
+                                    p->precision, p->stream);
+    }
+    // regrouped: Kt_m built on the device for this call
+    if (p->M > 32) return fail(SVCONV_EUNSUPPORTED, "regrouped form needs M <= 32");
+    int st = regroup_filters(p->dF64, p->dBeta, a, p->N, p->M, p->k, p->dFt32, p->dBetaT, p->stream);
+    if (st) return st;
+    c.NF = p->M;
+    c.coef = nullptr;
+    c.beta = p->dBetaT;
+    const int nb = (p->M + 15) / 16;
+    if (!lowp) {
+        st = build_f32_fragments(p->dFt32, p->M, p->k, p->dFragT32, p->stream);
+        if (st) return st;
+        return launch_contract_f32(c, p->dFragT32, nb, p->stream);
+    }
+    const bool h16 = is_fp16(p->precision);
+    uint16_t* frag = h16 ? p->dFragTH : p->dFragTB;
+    st = build_lowp_fragments(p->dFt32, p->M, p->k, h16 ? 1 : 0, p->dScaleT, frag, p->stream);
+    if (st) return st;
+    c.fscale = p->dScaleT + kMaxFilters;
+    return launch_contract_lowp(c, frag, nb, p->precision, p->stream);
+}
+
+}  // namespace svc
+
 extern "C" {
 
 const char* svconv_strerror(int status) {
@@ -332,54 +385,6 @@ int svconv_plan_destroy(svconv_plan* p) {
     int st = hip_status(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
     free_plan(p);
     return st;
-}
-
-// Shared body of svconv_forward and svconv_difference.
-static int run_forward(svconv_plan* p, const float* R, const float* I, const float* a, float* out) {
-    ContractArgs c{};
-    c.X = R;
-    c.H = p->H;
-    c.W = p->W;
-    c.h = p->h;
-    c.M = p->M;
-    c.d_s = p->d_s;
-    c.ped = p->pedestal;
-    c.I = I;
-    c.out = out;
-    c.y_begin = 0;
-    c.n_rows = p->H;
-    coords(p, c);
-    const bool lowp = is_lowp(p->precision);
-    if (p->form == SVCONV_FORM_BASIS) {
-        if (p->N > kMaxFilters) return fail(SVCONV_EUNSUPPORTED, "basis form needs N <= 64");
-        c.NF = p->N;
-        c.coef = a;
-        c.beta = p->dBeta;
-        const int nb = (p->N + 15) / 16;
-        if (!lowp) return launch_contract_f32(c, p->dFragF32, nb, p->stream);
-        c.fscale = (is_fp16(p->precision) ? p->dScaleH : p->dScaleB) + kMaxFilters;
-        return launch_contract_lowp(c, is_fp16(p->precision) ? p->dFragLoH : p->dFragLoB, nb,
-                                    p->precision, p->stream);
-    }
-    // regrouped: Kt_m built on the device for this call
-    if (p->M > 32) return fail(SVCONV_EUNSUPPORTED, "regrouped form needs M <= 32");
-    int st = regroup_filters(p->dF64, p->dBeta, a, p->N, p->M, p->k, p->dFt32, p->dBetaT, p->stream);
-    if (st) return st;
-    c.NF = p->M;
-    c.coef = nullptr;
-    c.beta = p->dBetaT;
-    const int nb = (p->M + 15) / 16;
-    if (!lowp) {
-        st = build_f32_fragments(p->dFt32, p->M, p->k, p->dFragT32, p->stream);
-        if (st) return st;
-        return launch_contract_f32(c, p->dFragT32, nb, p->stream);
-    }
-    const bool h16 = is_fp16(p->precision);
-    uint16_t* frag = h16 ? p->dFragTH : p->dFragTB;
-    st = build_lowp_fragments(p->dFt32, p->M, p->k, h16 ? 1 : 0, p->dScaleT, frag, p->stream);
-    if (st) return st;
-    c.fscale = p->dScaleT + kMaxFilters;
-    return launch_contract_lowp(c, frag, nb, p->precision, p->stream);
 }
 
 int svconv_forward(svconv_plan* p, const float* R, const float* a, float* out) {

@@ -269,3 +269,73 @@ class SVConvDifference(torch.autograd.Function):
 def difference(plan, R, I, a):
     """Differentiable D = (R (x) K(a)) - I."""
     return SVConvDifference.apply(plan, R, I, a)
+
+
+def _host_ptr(t, shape, name):
+    """Address of a contiguous float32 CPU tensor or numpy array."""
+    if isinstance(t, torch.Tensor):
+        if t.device.type != "cpu":
+            raise ValueError("%s must be in host memory" % name)
+        if t.dtype != torch.float32:
+            raise TypeError("%s must be float32, got %s" % (name, t.dtype))
+        ok, addr, got = t.is_contiguous(), t.data_ptr(), tuple(t.shape)
+    else:
+        import numpy as np
+        if not isinstance(t, np.ndarray) or t.dtype != np.float32:
+            raise TypeError("%s must be a float32 tensor or array" % name)
+        ok, addr, got = t.flags.c_contiguous, t.ctypes.data, t.shape
+    if got != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), got))
+    if not ok:
+        raise ValueError("%s must be contiguous" % name)
+    return addr
+
+
+def pinned_empty(shape):
+    """Page-locked float32 host tensor (the copies of a Pipeline overlap compute
+    only from such memory)."""
+    return torch.empty(shape, dtype=torch.float32, pin_memory=True)
+
+
+class Pipeline:
+    """Streamed difference images of host-resident tiles (svconv_pipeline_*):
+    copies in, contraction and copies out of consecutive tiles overlap."""
+
+    def __init__(self, plan, depth=3):
+        self._lib = _lib.load()
+        self.plan = plan
+        self._q = ctypes.c_void_p()
+        check(self._lib.svconv_pipeline_create(plan._p, int(depth), ctypes.byref(self._q)),
+              "svconv_pipeline_create")
+
+    def run(self, R_tiles, I_tiles, a_tiles, D_tiles):
+        """D_tiles[t] = R_tiles[t] (x) K(a_tiles[t]) - I_tiles[t] for every t; all
+        host float32 (pinned for overlap).  Blocks until every D is written."""
+        n = len(R_tiles)
+        if not (len(I_tiles) == len(a_tiles) == len(D_tiles) == n):
+            raise ValueError("tile lists differ in length")
+        img = (self.plan.height, self.plan.width)
+        coef = (self.plan.n_basis, self.plan.n_spatial)
+        arr = ctypes.c_void_p * max(n, 1)
+        Rp = arr(*[_host_ptr(x, img, "R[%d]" % t) for t, x in enumerate(R_tiles)])
+        Ip = arr(*[_host_ptr(x, img, "I[%d]" % t) for t, x in enumerate(I_tiles)])
+        Ap = arr(*[_host_ptr(x, coef, "a[%d]" % t) for t, x in enumerate(a_tiles)])
+        Dp = arr(*[_host_ptr(x, img, "D[%d]" % t) for t, x in enumerate(D_tiles)])
+        check(self._lib.svconv_pipeline_run(self._q, n, Rp, Ip, Ap, Dp), "svconv_pipeline_run")
+
+    def close(self):
+        if getattr(self, "_q", None) is not None and self._q.value:
+            check(self._lib.svconv_pipeline_destroy(self._q), "svconv_pipeline_destroy")
+            self._q = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

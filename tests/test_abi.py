@@ -111,3 +111,18 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         _lib.load()
+
+
+def test_pipeline_rejects_before_any_device_call(lib):
+    E = _lib.EINVAL
+    q = ctypes.c_void_p()
+    assert lib.svconv_pipeline_create(None, 2, ctypes.byref(q)) == E
+    assert not q.value
+    assert lib.svconv_pipeline_create(None, 2, None) == E
+    assert lib.svconv_pipeline_run(None, 1, None, None, None, None) == E
+    assert lib.svconv_pipeline_destroy(None) == _lib.OK
+    assert lib.svconv_host_alloc(16, None) == E
+    p = ctypes.c_void_p()
+    assert lib.svconv_host_alloc(0, ctypes.byref(p)) == E
+    assert not p.value
+    assert lib.svconv_host_free(None) == _lib.OK
