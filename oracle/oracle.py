@@ -288,3 +288,125 @@ def convolve_fft(R, h, B, d_s, a, frame=None):
             m += 1
     assert m == M
     return C
+
+
+# ---------------------------------------------------------------------------
+# Optimal Image Subtraction on isolated-star stamps (Sec. 2: isolated stars of
+# the reference are the source the kernel is determined from), with a
+# differential background polynomial.
+#
+# Readings taken here (the paper gives no numbers for them):
+#   * a stamp centre is a pixel p whose value is strictly larger than each of
+#     its (up to 8) neighbours inside the image, with R(p) - sky > threshold,
+#     at least `margin` pixels from every edge, and with no other such local
+#     maximum q within the (2 r_iso + 1)^2 window around p (clipped to the
+#     image) for which R(q) - sky >= frac (R(p) - sky): a star is isolated
+#     when no neighbour of comparable brightness is near it.  Every decision
+#     is taken on float64 values of the float32 image.
+#   * the stamp mask is the union of the (2 s + 1)^2 boxes around the centres.
+#   * the background is bg(p) = sum_m b[m] P_m(p) with the spatial terms of
+#     Eq. 3 (same degree as the kernel's), and the model is
+#     D = (R (x) K) + bg - I.
+# ---------------------------------------------------------------------------
+
+def _strict_local_max(R64):
+    H, W = R64.shape
+    lmax = np.ones((H, W), dtype=bool)
+    pad = np.full((H + 2, W + 2), -np.inf)
+    pad[1:H + 1, 1:W + 1] = R64
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            if dx == 0 and dy == 0:
+                continue
+            lmax &= R64 > pad[1 + dy:1 + dy + H, 1 + dx:1 + dx + W]
+    return lmax
+
+
+def stamp_centres(R, sky, threshold, frac, r_iso, margin):
+    """[(x, y), ...] of isolated-star stamp centres in raster order."""
+    R64 = np.asarray(R, dtype=np.float64)
+    H, W = R64.shape
+    lmax = _strict_local_max(R64)
+    out = []
+    for y in range(margin, H - margin):
+        for x in range(margin, W - margin):
+            if not lmax[y, x] or not (R64[y, x] - sky > threshold):
+                continue
+            f = R64[y, x] - sky
+            ok = True
+            for qy in range(max(0, y - r_iso), min(H, y + r_iso + 1)):
+                for qx in range(max(0, x - r_iso), min(W, x + r_iso + 1)):
+                    if (qx, qy) != (x, y) and lmax[qy, qx] and R64[qy, qx] - sky >= frac * f:
+                        ok = False
+            if ok:
+                out.append((x, y))
+    return out
+
+
+def stamp_mask(H, W, centres, s):
+    """uint8 mask: 1 inside the (2 s + 1)^2 box of any centre."""
+    m = np.zeros((H, W), dtype=np.uint8)
+    for (x, y) in centres:
+        m[max(0, y - s):min(H, y + s + 1), max(0, x - s):min(W, x + s + 1)] = 1
+    return m
+
+
+def spatial_term_images(H, W, d_s, frame=None):
+    """P[m][y][x] at every array pixel (one orc_spatial_terms call each)."""
+    x0, y0, Wf, Hf = frame if frame is not None else (0, 0, W, H)
+    lib = _load()
+    M = n_spatial(d_s)
+    P = np.zeros((M, H, W))
+    row = np.zeros(M)
+    for y in range(H):
+        yh = 2.0 * (y + y0) / (Hf - 1) - 1.0 if Hf > 1 else 0.0
+        for x in range(W):
+            xh = 2.0 * (x + x0) / (Wf - 1) - 1.0 if Wf > 1 else 0.0
+            lib.orc_spatial_terms(xh, yh, int(d_s), _ptr(row))
+            P[:, y, x] = row
+    return P
+
+
+def background(H, W, d_s, b, frame=None):
+    """bg(p) = sum_m b[m] P_m(p)."""
+    return np.tensordot(_d(b), spatial_term_images(H, W, d_s, frame), axes=(0, 0))
+
+
+def basis_responses(R, h, B, frame=None):
+    """T_n = B_n (x) R for every basis (the convolution with a = e_(n,0), P_0 = 1)."""
+    R = _d(R); B = _d(B)
+    N = B.shape[0]
+    T = np.zeros((N,) + R.shape)
+    for n in range(N):
+        a = np.zeros((N, 1))
+        a[n, 0] = 1.0
+        T[n] = convolve(R, h, B, 0, a, frame)
+    return T
+
+
+def design_matrix_bg(R, h, B, d_s, mask=None, frame=None):
+    """Phi[p][(n,m)] = P_m(p) T_n(p) for n < N and Phi[p][N M + m] = P_m(p),
+    over the masked pixels (interior if mask is None), rows in raster order."""
+    R = _d(R)
+    H, W = R.shape
+    T = basis_responses(R, h, B, frame)
+    P = spatial_term_images(H, W, d_s, frame)
+    sel = interior_mask(H, W, h) if mask is None else np.asarray(mask, dtype=bool)
+    N, M = T.shape[0], P.shape[0]
+    cols = [P[m][sel] * T[n][sel] for n in range(N) for m in range(M)]
+    cols += [P[m][sel] for m in range(M)]
+    return np.stack(cols, axis=1), sel
+
+
+def normal_equations_bg(R, I, h, B, d_s, mask=None, frame=None):
+    """(Phi^T Phi, Phi^T I) of the model with the background polynomial."""
+    Phi, sel = design_matrix_bg(R, h, B, d_s, mask, frame)
+    return Phi.T @ Phi, Phi.T @ _d(I)[sel]
+
+
+def fit_least_squares_bg(R, I, h, B, d_s, mask=None, frame=None):
+    """(a[N][M], b[M]) minimising sum_mask (R (x) K + bg - I)^2."""
+    JtJ, rhs = normal_equations_bg(R, I, h, B, d_s, mask, frame)
+    x = cholesky_solve(JtJ, rhs)
+    N, M = _d(B).shape[0], n_spatial(d_s)
+    return x[:N * M].reshape(N, M), x[N * M:]
