@@ -158,7 +158,9 @@ int svconv_loss_grad(svconv_plan* plan, const float* D, const unsigned char* mas
 
 /* Normal matrix of the fit: JtJ[(n,m)][(n',m')] = sum_{p in mask}
  * P_m P_m' T_n T_n' with T_n = B_n (x) R, index (n,m) -> n*M + m; float64
- * [NM][NM] device.  mask as in svconv_loss_grad. */
+ * [NM][NM] device.  mask as in svconv_loss_grad.  With a background the
+ * matrix is [(N+1)M][(N+1)M] and T_N = 1.  Allocates its band scratch on
+ * the first call (and grows it when a later call needs more). */
 int svconv_normal_matrix(svconv_plan* plan, const float* R, const unsigned char* mask,
                          double* JtJ);
 
@@ -175,6 +177,8 @@ int svconv_cholesky_solve(svconv_plan* plan, const double* L, const double* rhs,
 
 /* One Gauss-Newton iteration of the fit of a to min sum_mask D^2:
  * D = R (x) K(a) - I; ga = dL/da; delta = (JtJ)^-1 ga / 2; a -= delta.
+ * With a background (svconv_plan_set_background) a64, a32 and L cover
+ * (N + 1) M coefficients and D includes bg.
  * a64: float64 [N][M] master copy (updated); a32: float32 copy written from
  * it before the forward; D: float32 [H][W] output of this iteration's
  * residual; L: Cholesky factor of JtJ.  host_stats (host, 2 doubles, may be
@@ -182,6 +186,53 @@ int svconv_cholesky_solve(svconv_plan* plan, const double* L, const double* rhs,
  * synchronises the plan's stream. */
 int svconv_gn_step(svconv_plan* plan, const float* R, const float* I, const unsigned char* mask,
                    const double* L, double* a64, float* a32, float* D, double* host_stats);
+
+/*
+ * Optimal Image Subtraction on isolated stars (Sec. 2: the least-squares
+ * kernel fit takes isolated stars of the reference as its source).
+ */
+
+/* Stamp mask of isolated stars of R.  A pixel p is a stamp centre when R(p)
+ * is strictly larger than each of its neighbours inside the image, R(p) -
+ * sky > threshold, p is at least `margin` pixels from every edge, and no
+ * other such local maximum q within |qx - px|, |qy - py| <= r_iso has
+ * R(q) - sky >= frac (R(p) - sky); every comparison is made in float64 on
+ * the float32 values.  mask (device uint8 [H][W], written) is 1 inside the
+ * (2 stamp_half + 1)^2 box of any centre, 0 elsewhere.  n_centres (HOST, may
+ * be NULL) receives the number of centres; when given, the call synchronises
+ * the plan's stream.  Limits: frac > 0, 1 <= r_iso <= 64,
+ * 0 <= stamp_half <= 64, margin >= 0.  Uses the plan's gradient scratch. */
+int svconv_stamp_mask(svconv_plan* plan, const float* R, double sky, double threshold, double frac,
+                      int r_iso, int margin, int stamp_half, unsigned char* mask, int* n_centres);
+
+/* Fit model with a differential background polynomial (enable = 1):
+ * D = (R (x) K) + bg - I, bg(x,y) = sum_m b[m] P_m(x,y) with the plan's
+ * spatial terms.  The fit entry points (svconv_normal_matrix,
+ * svconv_gn_step, svconv_pcg_fit) then work on (N + 1) M coefficients: a
+ * [N][M] followed by b [M]; the normal matrix treats the background as one
+ * more basis whose response is the constant 1.  svconv_forward,
+ * svconv_difference and svconv_backward are unchanged.  EUNSUPPORTED unless
+ * N + 1 <= 64 and (N + 1) M <= 1024. */
+int svconv_plan_set_background(svconv_plan* plan, int enable);
+
+/* D += sum_m b[m] P_m (b: float32 [M] device). */
+int svconv_add_background(svconv_plan* plan, const float* b, float* D);
+
+/* Whole-image least-squares fit by conjugate gradients on the normal
+ * equations J^T mask J a = J^T mask I, preconditioned by (L L^T)^-1 for a
+ * Cholesky factor L of any SPD matrix of the fit's size (typically the
+ * normal matrix of the stamp mask, which takes far fewer Gram products than
+ * the whole image's).  Each iteration costs one forward pass of the search
+ * direction and one adjoint in a (plus the background terms).  a64 (float64,
+ * updated) is the starting point and the result; a32 receives its float32
+ * copy; D (float32 [H][W]) is scratch and receives the residual at the
+ * result.  host_residuals (HOST, may be NULL) receives ||J^T mask (I - J a)||
+ * after each of the `iters` iterations; when given, the call synchronises
+ * the plan's stream.  D must not alias R or I.  Uses the plan's vector and
+ * gradient scratch. */
+int svconv_pcg_fit(svconv_plan* plan, const float* R, const float* I, const unsigned char* mask,
+                   const double* L, int iters, double* a64, float* a32, float* D,
+                   double* host_residuals);
 
 /*
  * Streamed tiles (Sec. 4: asynchronous transfers between page-locked host

@@ -327,19 +327,19 @@ def stamp_centres(R, sky, threshold, frac, r_iso, margin):
     R64 = np.asarray(R, dtype=np.float64)
     H, W = R64.shape
     lmax = _strict_local_max(R64)
+    cand = lmax & (R64 - sky > threshold)
     out = []
-    for y in range(margin, H - margin):
-        for x in range(margin, W - margin):
-            if not lmax[y, x] or not (R64[y, x] - sky > threshold):
-                continue
-            f = R64[y, x] - sky
-            ok = True
-            for qy in range(max(0, y - r_iso), min(H, y + r_iso + 1)):
-                for qx in range(max(0, x - r_iso), min(W, x + r_iso + 1)):
-                    if (qx, qy) != (x, y) and lmax[qy, qx] and R64[qy, qx] - sky >= frac * f:
-                        ok = False
-            if ok:
-                out.append((x, y))
+    for y, x in np.argwhere(cand):          # raster order
+        if x < margin or x > W - 1 - margin or y < margin or y > H - 1 - margin:
+            continue
+        f = R64[y, x] - sky
+        ok = True
+        for qy in range(max(0, y - r_iso), min(H, y + r_iso + 1)):
+            for qx in range(max(0, x - r_iso), min(W, x + r_iso + 1)):
+                if (qx, qy) != (x, y) and lmax[qy, qx] and R64[qy, qx] - sky >= frac * f:
+                    ok = False
+        if ok:
+            out.append((int(x), int(y)))
     return out
 
 

@@ -42,6 +42,12 @@ SIGNATURES = {
     "svconv_cholesky_factor": (_i, [_vp, _vp, _i]),
     "svconv_cholesky_solve": (_i, [_vp, _vp, _vp, _vp, _i]),
     "svconv_gn_step": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
+    "svconv_stamp_mask": (_i, [_vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _i, _i,
+                               _i, _vp, ctypes.POINTER(_i)]),
+    "svconv_plan_set_background": (_i, [_vp, _i]),
+    "svconv_add_background": (_i, [_vp, _vp, _vp]),
+    "svconv_pcg_fit": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _vp, _vp, _vp,
+                            ctypes.POINTER(ctypes.c_double)]),
     "svconv_host_alloc": (_i, [ctypes.c_size_t, ctypes.POINTER(_vp)]),
     "svconv_host_free": (_i, [_vp]),
     "svconv_pipeline_create": (_i, [_vp, _i, ctypes.POINTER(_vp)]),

@@ -176,10 +176,19 @@ __global__ void assemble_jtj(const double* __restrict__ S, int N, int M, double*
     JtJ[idx] = S[(size_t)mu * 4096 + n * 64 + n2];
 }
 
+__global__ void fill_ones_kernel(float* __restrict__ v, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) v[i] = 1.f;
+}
+
+// With a background polynomial the fit has one more "basis" whose response
+// is the constant 1 (bg = sum_m b_m P_m * 1), so the same Gram sums give the
+// background rows and columns of the normal matrix: plane N of the band is
+// filled with ones.
 int launch_normal_matrix(svconv_plan* p, const float* R, const unsigned char* mask, double* JtJ) {
-    if (p->N > 64) return fail(SVCONV_EUNSUPPORTED, "normal matrix needs N <= 64");
+    const int NF = p->N + p->bg;
+    if (NF > 64) return fail(SVCONV_EUNSUPPORTED, "normal matrix needs N (+1 with a background) <= 64");
     const int n_mu = (2 * p->d_s + 1) * (2 * p->d_s + 2) / 2;
-    const size_t row_bytes = (size_t)p->N * p->W * sizeof(float);
+    const size_t row_bytes = (size_t)NF * p->W * sizeof(float);
     int band = (int)(NM_BAND_BYTES / row_bytes);
     if (band < 8) band = 8;
     if (band > p->H) band = p->H;
@@ -187,21 +196,26 @@ int launch_normal_matrix(svconv_plan* p, const float* R, const unsigned char* ma
     const int n_chunks = (max_px + NM_PIX_CHUNK - 1) / NM_PIX_CHUNK;
     const size_t part_elems = (size_t)n_chunks * n_mu * 4096;
     const size_t s_elems = (size_t)n_mu * 4096;
-    // scratch of the normal matrix: allocated on its first call, kept by the plan
-    if (!p->dTband || p->band_rows != band) {
+    const size_t tband_bytes = (size_t)band * row_bytes;
+    const size_t nmpart_bytes = (part_elems + s_elems) * sizeof(double);
+    // scratch of the normal matrix: allocated on its first call (grown when
+    // a later call needs more), kept by the plan
+    if (p->tband_bytes < tband_bytes || p->nmpart_bytes < nmpart_bytes) {
         if (p->dTband) (void)hipFree(p->dTband);
         if (p->dNMpart) (void)hipFree(p->dNMpart);
         p->dTband = nullptr;
         p->dNMpart = nullptr;
-        if (hipMalloc((void**)&p->dTband, (size_t)band * row_bytes) != hipSuccess ||
-            hipMalloc((void**)&p->dNMpart, (part_elems + s_elems) * sizeof(double)) != hipSuccess) {
+        p->tband_bytes = p->nmpart_bytes = 0;
+        if (hipMalloc((void**)&p->dTband, tband_bytes) != hipSuccess ||
+            hipMalloc((void**)&p->dNMpart, nmpart_bytes) != hipSuccess) {
             (void)hipGetLastError();
             if (p->dTband) (void)hipFree(p->dTband);
             p->dTband = nullptr;
             p->dNMpart = nullptr;
             return fail(SVCONV_ENOMEM, "normal-matrix scratch");
         }
-        p->band_rows = band;
+        p->tband_bytes = tband_bytes;
+        p->nmpart_bytes = nmpart_bytes;
     }
     double* S = p->dNMpart + part_elems;
     hipLaunchKernelGGL(zero_kernel, dim3(256), dim3(256), 0, p->stream, S, s_elems);
@@ -236,9 +250,15 @@ int launch_normal_matrix(svconv_plan* p, const float* R, const unsigned char* ma
         st = launch_contract_f32(c, p->dFragF32, nb, p->stream);
         if (st) return st;
         const int band_px = rows * p->W;
+        if (p->bg) {
+            hipLaunchKernelGGL(fill_ones_kernel, dim3(1024), dim3(256), 0, p->stream,
+                               p->dTband + (size_t)p->N * band_px, band_px);
+            st = hip_status(hipGetLastError(), "fill_ones_kernel");
+            if (st) return st;
+        }
         const int chunks = (band_px + NM_PIX_CHUNK - 1) / NM_PIX_CHUNK;
         hipLaunchKernelGGL(gram_kernel, dim3(n_mu, chunks), dim3(256), 0, p->stream, p->dTband,
-                           p->N, band_px, y0, p->W, p->H, p->h, mask, sx, ox, sy, oy, n_mu,
+                           NF, band_px, y0, p->W, p->H, p->h, mask, sx, ox, sy, oy, n_mu,
                            p->dNMpart);
         st = hip_status(hipGetLastError(), "gram_kernel");
         if (st) return st;
@@ -247,8 +267,8 @@ int launch_normal_matrix(svconv_plan* p, const float* R, const unsigned char* ma
         st = hip_status(hipGetLastError(), "gram_reduce");
         if (st) return st;
     }
-    const int NM = p->N * p->M;
-    hipLaunchKernelGGL(assemble_jtj, dim3((NM * NM + 255) / 256), dim3(256), 0, p->stream, S, p->N,
+    const int NM = NF * p->M;
+    hipLaunchKernelGGL(assemble_jtj, dim3((NM * NM + 255) / 256), dim3(256), 0, p->stream, S, NF,
                        p->M, JtJ);
     return hip_status(hipGetLastError(), "assemble_jtj");
 }
@@ -398,7 +418,7 @@ int launch_copy_a(svconv_plan* p, const double* a64, float* a32, int n) {
 
 int launch_gn_update(svconv_plan* p, const double* delta, double* a64, float* a32, int n) {
     // the step norm lands right after the loss scalar in the plan's vector scratch
-    double* norm = p->dVec + 2 * (size_t)p->N * p->M + 1;
+    double* norm = p->dVec + 2 * (size_t)n + 1;
     hipLaunchKernelGGL(gn_update_kernel, dim3(1), dim3(1024), 0, p->stream, delta, a64, a32, n, norm);
     return hip_status(hipGetLastError(), "gn_update_kernel");
 }

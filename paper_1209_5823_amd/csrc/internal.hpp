@@ -73,6 +73,7 @@ struct svconv_plan {
     int precision = SVCONV_FP32;
     int form = SVCONV_FORM_BASIS;
     bool dfb = false;                   // Dirac delta basis (one basis per kernel pixel)
+    int bg = 0;                         // 1: the fit carries a background polynomial (M terms)
     int x0 = 0, y0 = 0, Wf = 0, Hf = 0;
     float pedestal = 0.f;
     hipStream_t stream = nullptr;
@@ -107,7 +108,7 @@ struct svconv_plan {
     int* dStatus = nullptr;             // device status word
     double* dNMpart = nullptr;          // normal-matrix partials and totals
     float* dTband = nullptr;            // basis responses of a band of rows (normal matrix)
-    int band_rows = 0;
+    size_t tband_bytes = 0, nmpart_bytes = 0;
     double* dRed = nullptr;             // reduction scratch (loss)
 };
 
@@ -145,5 +146,9 @@ int launch_cholesky_solve(svconv_plan* p, const double* L, const double* rhs, do
 int launch_gn_update(svconv_plan* p, const double* delta, double* a64, float* a32, int n);
 int launch_copy_a(svconv_plan* p, const double* a64, float* a32, int n);
 int launch_scale(svconv_plan* p, double* v, double s, int n);
+
+// ois.hip
+int launch_add_background(svconv_plan* p, const float* b, float* D);
+int launch_bg_grad(svconv_plan* p, const float* G, double* gb);
 
 }  // namespace svc

@@ -153,7 +153,7 @@ static int finish_plan(svconv_plan* p, svconv_plan** out) {
         (st = dalloc(&p->dFragTB, fraglT, "per-call bf16 fragments")) ||
         (st = dalloc(&p->dFragTH, fraglT, "per-call fp16 fragments")) ||
         (st = dalloc(&p->dScaleT, (size_t)2 * kMaxFilters, "per-call scales")) ||
-        (st = dalloc(&p->dVec, (size_t)4 * kMaxCoefficients + 64, "vector scratch")) ||
+        (st = dalloc(&p->dVec, (size_t)8 * kMaxCoefficients + 64, "vector scratch")) ||
         (st = dalloc(&p->dStatus, (size_t)4, "status word")) ||
         (st = dalloc(&p->dGrad, (size_t)p->H * p->W, "loss gradient")) ||
         (st = dalloc(&p->dRed, (size_t)2048, "reduction scratch")) ||
@@ -461,14 +461,17 @@ int svconv_gn_step(svconv_plan* p, const float* R, const float* I, const unsigne
                    const double* L, double* a64, float* a32, float* D, double* host_stats) {
     if (!p || !R || !I || !L || !a64 || !a32 || !D) return fail(SVCONV_EINVAL, "NULL argument");
     if ((const void*)D == (const void*)R) return fail(SVCONV_EINVAL, "D aliases R");
-    const int NM = p->N * p->M;
+    const int NK = p->N * p->M;          // kernel coefficients
+    const int NM = NK + p->bg * p->M;    // plus the background polynomial
     double* ga = p->dVec;            // [NM]
     double* delta = p->dVec + NM;    // [NM]
     double* loss = p->dVec + 2 * NM; // scalar
     int st = launch_copy_a(p, a64, a32, NM);
     if (!st) st = run_forward(p, R, I, a32, D);
+    if (!st && p->bg) st = launch_add_background(p, a32 + NK, D);
     if (!st) st = launch_loss_grad(p, D, mask, p->dGrad, loss);
     if (!st) st = launch_adjoint_a(p, R, p->dGrad, ga);
+    if (!st && p->bg) st = launch_bg_grad(p, p->dGrad, ga + NK);
     if (!st) st = launch_scale(p, ga, 0.5, NM);
     if (!st) st = launch_cholesky_solve(p, L, ga, delta, NM);
     if (!st) st = launch_gn_update(p, delta, a64, a32, NM);

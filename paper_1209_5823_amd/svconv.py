@@ -67,6 +67,7 @@ class Plan:
         check(self._lib.svconv_plan_sizes(self._p, ctypes.byref(n), ctypes.byref(m)), "sizes")
         self.n_basis, self.n_spatial = n.value, m.value
         self.precision, self.form = precision, "basis"
+        self.background = False
         self.set_form(form)
         if frame is not None:
             self.set_frame(*frame)
@@ -94,6 +95,13 @@ class Plan:
         check(self._lib.svconv_plan_set_form(self._p, FORMS[form]), "svconv_plan_set_form")
         self.form = form
 
+    def set_background(self, enable):
+        """Fit model D = R (x) K + bg - I with bg = sum_m b_m P_m (the fit entry
+        points then take (N + 1) x M coefficients: a, then b)."""
+        check(self._lib.svconv_plan_set_background(self._p, 1 if enable else 0),
+              "svconv_plan_set_background")
+        self.background = bool(enable)
+
     def set_pedestal(self, pedestal):
         check(self._lib.svconv_plan_set_pedestal(self._p, float(pedestal)),
               "svconv_plan_set_pedestal")
@@ -118,6 +126,12 @@ class Plan:
     @property
     def _coef(self):
         return (self.n_basis, self.n_spatial)
+
+    @property
+    def _fit_coef(self):
+        """Shape of the fit's coefficient arrays: a [N][M], plus b [M] with a
+        background."""
+        return (self.n_basis + (1 if self.background else 0), self.n_spatial)
 
     # ------------------------------------------------------------ compute --
     def forward(self, R, a, out=None):
@@ -171,7 +185,7 @@ class Plan:
 
     def normal_matrix(self, R, mask=None):
         """Phi^T Phi over the mask, Phi[p][(n,m)] = P_m(p) T_n(p); float64."""
-        nm = self.n_basis * self.n_spatial
+        nm = self._fit_coef[0] * self._fit_coef[1]
         JtJ = torch.empty((nm, nm), dtype=torch.float64, device=R.device)
         self._sync_stream()
         check(self._lib.svconv_normal_matrix(self._p, _dev_ptr(R, torch.float32, self._img, "R"),
@@ -201,18 +215,65 @@ class Plan:
 
     def gn_step(self, R, I, L, a64, a32, D, mask=None, stats=True):
         """One Gauss-Newton step; returns (loss before the step, ||delta||)."""
-        nm = self.n_basis * self.n_spatial
+        fc = self._fit_coef
+        nm = fc[0] * fc[1]
         st = (ctypes.c_double * 2)() if stats else None
         self._sync_stream()
         check(self._lib.svconv_gn_step(self._p, _dev_ptr(R, torch.float32, self._img, "R"),
                                        _dev_ptr(I, torch.float32, self._img, "I"),
                                        _opt_ptr(mask, torch.uint8, self._img, "mask"),
                                        _dev_ptr(L, torch.float64, (nm, nm), "L"),
-                                       _dev_ptr(a64, torch.float64, self._coef, "a64"),
-                                       _dev_ptr(a32, torch.float32, self._coef, "a32"),
+                                       _dev_ptr(a64, torch.float64, fc, "a64"),
+                                       _dev_ptr(a32, torch.float32, fc, "a32"),
                                        _dev_ptr(D, torch.float32, self._img, "D"), st),
               "svconv_gn_step")
         return (st[0], st[1]) if stats else None
+
+    def pcg_fit(self, R, I, L, a64, a32, D, iters, mask=None, residuals=True):
+        """Preconditioned conjugate gradients on the normal equations
+        (svconv_pcg_fit); a64 is updated in place.  Returns the residual norm
+        after each iteration (a list) when residuals=True."""
+        fc = self._fit_coef
+        nm = fc[0] * fc[1]
+        res = (ctypes.c_double * max(int(iters), 1))() if residuals else None
+        self._sync_stream()
+        check(self._lib.svconv_pcg_fit(self._p, _dev_ptr(R, torch.float32, self._img, "R"),
+                                       _dev_ptr(I, torch.float32, self._img, "I"),
+                                       _opt_ptr(mask, torch.uint8, self._img, "mask"),
+                                       _dev_ptr(L, torch.float64, (nm, nm), "L"), int(iters),
+                                       _dev_ptr(a64, torch.float64, fc, "a64"),
+                                       _dev_ptr(a32, torch.float32, fc, "a32"),
+                                       _dev_ptr(D, torch.float32, self._img, "D"), res),
+              "svconv_pcg_fit")
+        return list(res)[:int(iters)] if residuals else None
+
+    def stamp_mask(self, R, sky, threshold, frac=0.1, r_iso=None, margin=None, stamp_half=None,
+                   mask=None):
+        """Isolated-star stamp mask (svconv_stamp_mask); returns (mask, n_centres).
+        Defaults: stamp_half = r_iso = the kernel half-width, margin = 2 h."""
+        h = self.half_width
+        r_iso = max(1, h) if r_iso is None else r_iso
+        stamp_half = h if stamp_half is None else stamp_half
+        margin = 2 * h if margin is None else margin
+        if mask is None:
+            mask = torch.empty(self._img, dtype=torch.uint8, device=R.device)
+        n = ctypes.c_int(0)
+        self._sync_stream()
+        check(self._lib.svconv_stamp_mask(self._p, _dev_ptr(R, torch.float32, self._img, "R"),
+                                          float(sky), float(threshold), float(frac), int(r_iso),
+                                          int(margin), int(stamp_half),
+                                          _dev_ptr(mask, torch.uint8, self._img, "mask"),
+                                          ctypes.byref(n)), "svconv_stamp_mask")
+        return mask, n.value
+
+    def add_background(self, b, D):
+        """D += sum_m b_m P_m (in place); b float32 [M] on the GPU."""
+        self._sync_stream()
+        check(self._lib.svconv_add_background(self._p, _dev_ptr(b, torch.float32,
+                                                                (self.n_spatial,), "b"),
+                                              _dev_ptr(D, torch.float32, self._img, "D")),
+              "svconv_add_background")
+        return D
 
     # ----------------------------------------------------------- lifetime --
     def close(self):

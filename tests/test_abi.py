@@ -126,3 +126,12 @@ def test_pipeline_rejects_before_any_device_call(lib):
     assert lib.svconv_host_alloc(0, ctypes.byref(p)) == E
     assert not p.value
     assert lib.svconv_host_free(None) == _lib.OK
+
+
+def test_ois_entry_points_reject_before_any_device_call(lib):
+    E = _lib.EINVAL
+    n = ctypes.c_int()
+    assert lib.svconv_stamp_mask(None, None, 0.0, 1.0, 0.1, 3, 0, 2, None, ctypes.byref(n)) == E
+    assert lib.svconv_plan_set_background(None, 1) == E
+    assert lib.svconv_add_background(None, None, None) == E
+    assert lib.svconv_pcg_fit(None, None, None, None, None, 1, None, None, None, None) == E
