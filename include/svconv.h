@@ -76,7 +76,13 @@ enum svconv_precision {
  * D = sum_n c_n T_n - I.  REGROUPED: Kt_m = sum_n a[n][m] B_n (built on the
  * device per call), then D = sum_m P_m (Kt_m (x) R) - I, which needs M
  * instead of N filters because P_m depends only on the output pixel. */
-enum svconv_form { SVCONV_FORM_BASIS = 0, SVCONV_FORM_REGROUPED = 1 };
+enum svconv_form { SVCONV_FORM_BASIS = 0, SVCONV_FORM_REGROUPED = 1, SVCONV_FORM_SEPARABLE = 2 };
+/* SEPARABLE (Gaussian bases, 1 <= half_width <= 15): each Gaussian basis is a
+ * product f_i(u) f_j(v) of one-dimensional factors (the L1 norm of the
+ * product is the product of the norms), so T_n = f_j (x)_y (f_i (x)_x R): a
+ * row pass per factor f_i of a family, then a column pass per basis, in
+ * float64 arithmetic with the row responses held in float32; the precision
+ * setting does not apply.  EUNSUPPORTED for delta-basis plans. */
 
 /*
  * Create a plan for images of height x width with a (2 half_width + 1)^2

@@ -65,6 +65,24 @@ struct ContractArgs {
     float* tout = nullptr;      // optional T_f planes [NF][n_rows][W] (FP32 kernel only)
 };
 
+// Separable form (Gaussian bases only): one-dimensional factors per family.
+constexpr int kSepMaxFactors = 10;   // degree <= 9 (N <= 64)
+struct SepArgs {
+    const float* X;             // [H][W]
+    const float* I;             // nullable
+    float* out;                 // [H][W]
+    int H, W, h;
+    float ped;
+    int G;                      // Gaussian families
+    const int* fam;             // [2 G]: degree, index of the family's first basis
+    const double* f1d;          // [G][kSepMaxFactors][k] factors f_e(w), w = -h..h
+    const double* beta;         // [N] basis sums
+    const float* coef;          // [N][M]
+    int M, d_s;
+    double sx, ox, sy, oy;
+    int tiles_x, n_tiles;
+};
+
 }  // namespace svc
 
 struct svconv_plan {
@@ -82,6 +100,8 @@ struct svconv_plan {
     std::vector<double> sigmas;
     std::vector<int> degrees;
     std::vector<double> basis;          // host B[n][v+h][u+h], float64
+    double* dSep1d = nullptr;           // separable factors (Gaussian plans with h >= 1)
+    int* dSepFam = nullptr;             // [2 G] degree, first basis
 
     // device tables (basis form, fixed per plan)
     float* dF32 = nullptr;              // [N][k][k] correlation-oriented basis, float32
@@ -129,6 +149,9 @@ int adjoint_filters(const double* F64, const float* a, int N, int M, int d_s, in
 int launch_contract_f32(const ContractArgs& a, const float* frag, int nb, hipStream_t s);
 int launch_contract_lowp(const ContractArgs& a, const uint16_t* frag, int nb, int precision,
                          hipStream_t s);
+
+// separable.hip
+int launch_contract_sep(SepArgs a, hipStream_t s);
 
 // plan.hip
 int run_forward(svconv_plan* p, const float* R, const float* I, const float* a, float* out);

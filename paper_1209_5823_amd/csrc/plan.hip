@@ -71,7 +71,8 @@ static int dalloc(T** p, size_t count, const char* what) {
 }
 
 static void free_plan(svconv_plan* p) {
-    void* ptrs[] = {p->dF32,   p->dF64,   p->dBeta,   p->dFragF32, p->dFragLoB, p->dFragLoH,
+    void* ptrs[] = {p->dSep1d, p->dSepFam,
+                    p->dF32,   p->dF64,   p->dBeta,   p->dFragF32, p->dFragLoB, p->dFragLoH,
                     p->dScaleB, p->dScaleH, p->dFt32, p->dBetaT, p->dFragT32, p->dFragTB,  p->dFragTH,
                     p->dScaleT, p->dQpart, p->dQ,    p->dGrad,    p->dVec,     p->dStatus,
                     p->dNMpart, p->dTband, p->dRed};
@@ -164,6 +165,40 @@ static int finish_plan(svconv_plan* p, svconv_plan** out) {
     st = hip_status(hipMemcpy(p->dF32, F32.data(), F32.size() * 4, hipMemcpyHostToDevice), "upload");
     if (!st) st = hip_status(hipMemcpy(p->dF64, F64.data(), F64.size() * 8, hipMemcpyHostToDevice), "upload");
     if (!st) st = hip_status(hipMemcpy(p->dBeta, beta.data(), beta.size() * 8, hipMemcpyHostToDevice), "upload");
+    if (!st && !p->dfb && p->h >= 1) {
+        // one-dimensional factors of every Gaussian family (the separable form)
+        const int G = (int)p->sigmas.size(), h = p->h;
+        std::vector<double> f1d((size_t)G * kSepMaxFactors * k, 0.0);
+        std::vector<int> fam(2 * (size_t)G);
+        int first = 0;
+        for (int g = 0; g < G; ++g) {
+            fam[2 * g] = p->degrees[g];
+            fam[2 * g + 1] = first;
+            first += (p->degrees[g] + 1) * (p->degrees[g] + 2) / 2;
+            for (int e = 0; e <= p->degrees[g]; ++e) {
+                double* f = &f1d[((size_t)g * kSepMaxFactors + e) * k];
+                double l1 = 0.0;
+                for (int w = -h; w <= h; ++w) {
+                    double val;
+                    if (p->sigmas[g] == 0.0) {
+                        val = (w == 0) ? 1.0 : 0.0;
+                    } else {
+                        double mono = 1.0;
+                        for (int q = 0; q < e; ++q) mono *= w;
+                        val = std::exp(-(double)(w * w) / (2.0 * p->sigmas[g] * p->sigmas[g])) * mono;
+                    }
+                    f[w + h] = val;
+                    l1 += std::fabs(val);
+                }
+                if (l1 > 0.0)
+                    for (int q = 0; q < k; ++q) f[q] /= l1;
+            }
+        }
+        st = dalloc(&p->dSep1d, f1d.size(), "separable factors");
+        if (!st) st = dalloc(&p->dSepFam, fam.size(), "separable families");
+        if (!st) st = hip_status(hipMemcpy(p->dSep1d, f1d.data(), f1d.size() * 8, hipMemcpyHostToDevice), "upload");
+        if (!st) st = hip_status(hipMemcpy(p->dSepFam, fam.data(), fam.size() * 4, hipMemcpyHostToDevice), "upload");
+    }
     if (!st && p->N <= kMaxFilters) {
         st = build_f32_fragments(p->dF32, p->N, k, p->dFragF32, nullptr);
         if (!st) st = build_lowp_fragments(p->dF32, p->N, k, 0, p->dScaleB, p->dFragLoB, nullptr);
@@ -194,6 +229,25 @@ int run_forward(svconv_plan* p, const float* R, const float* I, const float* a, 
     c.n_rows = p->H;
     coords(p, c);
     const bool lowp = is_lowp(p->precision);
+    if (p->form == SVCONV_FORM_SEPARABLE) {
+        SepArgs sa{};
+        sa.X = R;
+        sa.I = I;
+        sa.out = out;
+        sa.H = p->H;
+        sa.W = p->W;
+        sa.h = p->h;
+        sa.ped = p->pedestal;
+        sa.G = (int)p->sigmas.size();
+        sa.fam = p->dSepFam;
+        sa.f1d = p->dSep1d;
+        sa.beta = p->dBeta;
+        sa.coef = a;
+        sa.M = p->M;
+        sa.d_s = p->d_s;
+        sa.sx = c.sx; sa.ox = c.ox; sa.sy = c.sy; sa.oy = c.oy;
+        return launch_contract_sep(sa, p->stream);
+    }
     if (p->form == SVCONV_FORM_BASIS) {
         if (p->N > kMaxFilters) return fail(SVCONV_EUNSUPPORTED, "basis form needs N <= 64");
         c.NF = p->N;
@@ -352,8 +406,10 @@ int svconv_plan_set_precision(svconv_plan* p, int precision) {
 
 int svconv_plan_set_form(svconv_plan* p, int form) {
     if (!p) return fail(SVCONV_EINVAL, "plan is NULL");
-    if (form != SVCONV_FORM_BASIS && form != SVCONV_FORM_REGROUPED)
+    if (form != SVCONV_FORM_BASIS && form != SVCONV_FORM_REGROUPED && form != SVCONV_FORM_SEPARABLE)
         return fail(SVCONV_EINVAL, "unknown form");
+    if (form == SVCONV_FORM_SEPARABLE && (!p->dSep1d || p->h > 15))
+        return fail(SVCONV_EUNSUPPORTED, "separable form needs Gaussian bases and 1 <= half-width <= 15");
     if (form == SVCONV_FORM_BASIS && p->N > kMaxFilters)
         return fail(SVCONV_EUNSUPPORTED, "basis form needs N <= 64");
     p->form = form;

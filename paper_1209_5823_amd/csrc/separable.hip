@@ -1,0 +1,241 @@
+// Separable form of the Gaussian-basis contraction.
+//
+// Every Gaussian basis function is a product of two one-dimensional factors
+// (Sec. 2, Eq. 2 with the Gaussian basis of Alard & Lupton):
+//   B_n(u,v) = exp(-(u^2+v^2)/(2 s^2)) u^i v^j / Z = f_i(u) f_j(v),
+//   f_e(w) = exp(-w^2/(2 s^2)) w^e / sum_w |exp(-w^2/(2 s^2)) w^e|,
+// because the L1 norm of the product is the product of the two L1 norms.  So
+//   T_n = B_n (x) R = f_j (x)_y ( f_i (x)_x R ),
+// a row pass with the (d+1) factors f_i of a Gaussian family followed by a
+// column pass with f_j on each row response: (d+1) + N one-dimensional
+// convolutions of k taps per pixel instead of N two-dimensional ones of k^2.
+// The result is D of Eq. 1 exactly, up to rounding.
+//
+// Arithmetic: float64 fused multiply-adds on the vector units (on this chip
+// the float64 vector rate equals the unpacked float32 rate); the row
+// responses are rounded to float32 once, in LDS, between the two passes.  The
+// pedestal s is subtracted from R when it is staged and restored through
+// s * beta_n, as in the matrix-core forms.
+//
+// Workgroup: SEP_NW waves, output tile 64 x 4 SEP_NW.  Phase A (row pass):
+// each task is one staged row and 4 consecutive columns, computing up to
+// SEP_CHUNK row factors from one register window.  Phase B (column pass):
+// thread (lane x, wave w) owns column x and rows 4w..4w+3; it reads the column of a row
+// response into registers once and applies every column factor of that row
+// factor, then folds T_n + s beta_n into D with c_n(x,y) = sum_m a_nm P_m.
+#include "internal.hpp"
+
+namespace svc {
+
+#ifndef SEP_WAVES
+#define SEP_WAVES 8
+#endif
+#ifndef SEP_ROWS
+#define SEP_ROWS 8
+#endif
+#ifndef SEP_AOUT
+#define SEP_AOUT 8
+#endif
+constexpr int SEP_NW = SEP_WAVES;          // waves per workgroup
+constexpr int SEP_RPT = SEP_ROWS;          // output rows per thread (phase B)
+constexpr int SEP_APT = SEP_AOUT;          // row-pass outputs per task (phase A)
+constexpr int SEP_TW = 64, SEP_TH = SEP_RPT * SEP_NW;
+constexpr int SEP_CHUNK = 4;               // row factors per phase A / phase B round
+
+// Read-only tables (factors, coefficients, sums) are read through the
+// constant address space: every lane reads the same element, so the loads
+// become scalar-cache loads into SGPRs that the FMAs take as operands.
+template <class T>
+using cptr = const __attribute__((address_space(4))) T*;
+template <class T>
+__device__ __forceinline__ cptr<T> as_const(const T* p) {
+    return (cptr<T>)(p);
+}
+
+__device__ __forceinline__ int sep_xcd_remap(int bid, int n) {
+    const int x8 = bid & 7, tt = bid >> 3, q8 = n >> 3, r8 = n & 7;
+    return x8 * q8 + (x8 < r8 ? x8 : r8) + tt;
+}
+
+template <int H>
+__global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
+    constexpr int NT = 64 * SEP_NW;
+    constexpr int K = 2 * H + 1;
+    constexpr int RA = SEP_TH + 2 * H;          // staged rows
+    constexpr int CA = SEP_TW + 2 * H;          // staged columns
+    constexpr int TP = CA;                      // tile pitch (floats)
+    constexpr int WA = SEP_APT + 2 * H;         // phase-A window
+    constexpr int WB = SEP_RPT + 2 * H;         // phase-B window
+    constexpr int NTASK = RA * (SEP_TW / SEP_APT);
+    extern __shared__ float sep_lds[];
+    float* tile = sep_lds;                      // [RA][TP]
+    float* rc = sep_lds + RA * TP;              // [SEP_CHUNK][RA][SEP_TW]
+
+    const cptr<double> f1d = as_const(a.f1d);
+    const cptr<double> beta = as_const(a.beta);
+    const cptr<float> coef = as_const(a.coef);
+    const cptr<int> fam = as_const(a.fam);
+
+    const int tid = threadIdx.x;
+    const int t = sep_xcd_remap(blockIdx.x, a.n_tiles);
+    const int X0 = (t % a.tiles_x) * SEP_TW;
+    const int Y0 = (t / a.tiles_x) * SEP_TH;
+
+    // stage R - s; outside the image R is 0, so the staged value is -s there
+    for (int q = tid; q < RA * CA; q += NT) {
+        const int r = q / CA, c = q - r * CA;
+        const int gy = Y0 - H + r, gx = X0 - H + c;
+        float v = 0.f;
+        if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) v = a.X[(size_t)gy * a.W + gx];
+        tile[r * TP + c] = v - a.ped;
+    }
+
+    const int lane = tid & 63, w = tid >> 6;
+    const int x = X0 + lane;
+    const double xh = a.sx * x + a.ox;
+    double xpow[kMaxSpatialDegree + 1];
+    xpow[0] = 1.0;
+#pragma unroll
+    for (int q = 1; q <= kMaxSpatialDegree; ++q) xpow[q] = xpow[q - 1] * xh;
+    double yh[SEP_RPT], dacc[SEP_RPT];
+#pragma unroll
+    for (int rr = 0; rr < SEP_RPT; ++rr) {
+        yh[rr] = a.sy * (Y0 + SEP_RPT * w + rr) + a.oy;
+        dacc[rr] = 0.0;
+    }
+    const int d_s = a.d_s;
+
+    for (int g = 0; g < a.G; ++g) {
+        const int deg = fam[2 * g], base = fam[2 * g + 1];
+        const cptr<double> fg = f1d + (size_t)g * kSepMaxFactors * K;
+        for (int i0 = 0; i0 <= deg; i0 += SEP_CHUNK) {
+            const int nc = min(SEP_CHUNK, deg + 1 - i0);
+            __syncthreads();   // tile staged / previous round's rc consumed
+            // phase A: rc[c][r][x'] = sum_u f_{i0+c}(u) (R - s)(x' - u, r)
+            for (int tb = 0; tb < NTASK; tb += NT) {
+                const int task = tb + tid;
+                if (task < NTASK) {
+                    const int r = task / (SEP_TW / SEP_APT);
+                    const int q4 = SEP_APT * (task - r * (SEP_TW / SEP_APT));
+                    double win[WA];
+#pragma unroll
+                    for (int s = 0; s < WA; ++s) win[s] = (double)tile[r * TP + q4 + s];
+                    for (int c = 0; c < nc; ++c) {
+                        const cptr<double> f = fg + (size_t)(i0 + c) * K;
+                        double acc[SEP_APT];
+#pragma unroll
+                        for (int o = 0; o < SEP_APT; ++o) acc[o] = 0.0;
+#pragma unroll
+                        for (int u = 0; u < K; ++u) {
+                            const double fu = f[u];
+#pragma unroll
+                            for (int o = 0; o < SEP_APT; ++o) acc[o] = fma(fu, win[o + 2 * H - u], acc[o]);
+                        }
+                        float* dst = rc + ((size_t)c * RA + r) * SEP_TW + q4;
+#pragma unroll
+                        for (int o = 0; o < SEP_APT; ++o) dst[o] = (float)acc[o];
+                    }
+                }
+            }
+            __syncthreads();
+            // phase B: T_n(x, y) = sum_v f_j(v) rc(x, y - v), D += c_n (T_n + s beta_n)
+            for (int c = 0; c < nc; ++c) {
+                const int i = i0 + c;
+                double col[WB];
+#pragma unroll
+                for (int s = 0; s < WB; ++s) col[s] = (double)rc[((size_t)c * RA + SEP_RPT * w + s) * SEP_TW + lane];
+                for (int j = 0; j + i <= deg; ++j) {
+                    const int n = base + (i + j) * (i + j + 1) / 2 + j;
+                    const cptr<double> f = fg + (size_t)j * K;
+                    double tv[SEP_RPT];
+#pragma unroll
+                    for (int o = 0; o < SEP_RPT; ++o) tv[o] = 0.0;
+#pragma unroll
+                    for (int v = 0; v < K; ++v) {
+                        const double fv = f[v];
+#pragma unroll
+                        for (int o = 0; o < SEP_RPT; ++o) tv[o] = fma(fv, col[o + 2 * H - v], tv[o]);
+                    }
+                    // c_n(x, y) = sum_jj Cy[jj] yh^jj with Cy[jj] = sum_ie a[n][m(ie, jj)] xh^ie
+                    double cy[kMaxSpatialDegree + 1];
+#pragma unroll
+                    for (int q = 0; q <= kMaxSpatialDegree; ++q) cy[q] = 0.0;
+                    const cptr<float> an = coef + (size_t)n * a.M;
+                    int m = 0;
+#pragma unroll
+                    for (int tt = 0; tt <= kMaxSpatialDegree; ++tt) {
+                        if (tt <= d_s) {
+#pragma unroll
+                            for (int ie = tt; ie >= 0; --ie) cy[tt - ie] = fma((double)an[m + tt - ie], xpow[ie], cy[tt - ie]);
+                        }
+                        m += tt + 1;
+                    }
+                    const double pb = (double)a.ped * beta[n];
+                    // Horner in yh; the terms above d_s are zero, so the
+                    // quadratic path is exact for d_s <= 2 (the uniform branch
+                    // keeps the common case short)
+                    if (d_s <= 2) {
+#pragma unroll
+                        for (int o = 0; o < SEP_RPT; ++o) {
+                            const double cn = fma(fma(cy[2], yh[o], cy[1]), yh[o], cy[0]);
+                            dacc[o] = fma(cn, tv[o] + pb, dacc[o]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int o = 0; o < SEP_RPT; ++o) {
+                            double cn = cy[kMaxSpatialDegree];
+#pragma unroll
+                            for (int q = kMaxSpatialDegree - 1; q >= 0; --q) cn = fma(cn, yh[o], cy[q]);
+                            dacc[o] = fma(cn, tv[o] + pb, dacc[o]);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (x < a.W) {
+#pragma unroll
+        for (int o = 0; o < SEP_RPT; ++o) {
+            const int y = Y0 + SEP_RPT * w + o;
+            if (y < a.H) {
+                const size_t idx = (size_t)y * a.W + x;
+                const double iv = a.I ? (double)a.I[idx] : 0.0;
+                a.out[idx] = (float)(dacc[o] - iv);
+            }
+        }
+    }
+}
+
+template <int H>
+static int launch_sep_t(const SepArgs& a, hipStream_t s) {
+    constexpr int RA = SEP_TH + 2 * H, CA = SEP_TW + 2 * H;
+    const size_t lds = ((size_t)RA * CA + (size_t)SEP_CHUNK * RA * SEP_TW) * sizeof(float);
+    hipLaunchKernelGGL(contract_sep_kernel<H>, dim3(a.n_tiles), dim3(64 * SEP_NW), lds, s, a);
+    return hip_status(hipGetLastError(), "contract_sep_kernel");
+}
+
+int launch_contract_sep(SepArgs a, hipStream_t s) {
+    a.tiles_x = (a.W + SEP_TW - 1) / SEP_TW;
+    const int tiles_y = (a.H + SEP_TH - 1) / SEP_TH;
+    a.n_tiles = a.tiles_x * tiles_y;
+    switch (a.h) {
+        case 1: return launch_sep_t<1>(a, s);
+        case 2: return launch_sep_t<2>(a, s);
+        case 3: return launch_sep_t<3>(a, s);
+        case 4: return launch_sep_t<4>(a, s);
+        case 5: return launch_sep_t<5>(a, s);
+        case 6: return launch_sep_t<6>(a, s);
+        case 7: return launch_sep_t<7>(a, s);
+        case 8: return launch_sep_t<8>(a, s);
+        case 9: return launch_sep_t<9>(a, s);
+        case 10: return launch_sep_t<10>(a, s);
+        case 11: return launch_sep_t<11>(a, s);
+        case 12: return launch_sep_t<12>(a, s);
+        case 13: return launch_sep_t<13>(a, s);
+        case 14: return launch_sep_t<14>(a, s);
+        case 15: return launch_sep_t<15>(a, s);
+        default: return fail(SVCONV_EUNSUPPORTED, "separable form needs 1 <= half-width <= 15");
+    }
+}
+
+}  // namespace svc

@@ -45,3 +45,12 @@ def executed_flops_per_pixel(n_filters_padded, taps_padded, passes=1):
 
 BYTES_PER_PIXEL = 12          # R in, I in, D out (float32)
 BYTES_PER_PIXEL_FORWARD = 8   # R in, C out
+
+
+def separable_flops_per_pixel(degrees, M, k):
+    """FLOP per pixel of the separable Gaussian-basis form: a row pass with the
+    (d_g + 1) one-dimensional factors of each family, a column pass per basis,
+    then the coefficients, the dot with c and the subtraction."""
+    n_factors = sum(d + 1 for d in degrees)
+    N = sum((d + 1) * (d + 2) // 2 for d in degrees)
+    return 2 * n_factors * k + 2 * N * k + 2 * N * M + 2 * N + 1

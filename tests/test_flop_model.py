@@ -33,3 +33,12 @@ def test_algorithmic_counts_at_workloads():
     assert flops.flops_per_pixel(49, 6, 21) == 43905
     assert flops.flops_per_pixel(49, 15, 31) == 95747
     assert flops.flops_per_pixel(22, 6, 15) == 10209
+
+
+def test_separable_count_at_the_chip_workload():
+    # 15 row factors (degrees 6, 4, 2) and 49 column passes of 21 taps, then
+    # 2 N M + 2 N + 1 for the coefficients, the dot and the subtraction
+    assert flops.separable_flops_per_pixel((6, 4, 2), 6, 21) == 2 * 15 * 21 + 2 * 49 * 21 + 2 * 49 * 6 + 2 * 49 + 1
+    assert flops.separable_flops_per_pixel((6, 4, 2), 6, 21) == 3375
+    # a single delta family: one factor, one basis
+    assert flops.separable_flops_per_pixel((0,), 1, 3) == 2 * 3 + 2 * 3 + 2 + 2 + 1
