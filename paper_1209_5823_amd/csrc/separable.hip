@@ -63,13 +63,14 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
     constexpr int K = 2 * H + 1;
     constexpr int RA = SEP_TH + 2 * H;          // staged rows
     constexpr int CA = SEP_TW + 2 * H;          // staged columns
-    constexpr int TP = CA;                      // tile pitch (floats)
+    constexpr int TP = CA | 1;                  // tile pitch (floats), odd: rows hit distinct banks
+    constexpr int RP = SEP_TW + 1;              // row-response pitch, odd for the same reason
     constexpr int WA = SEP_APT + 2 * H;         // phase-A window
     constexpr int WB = SEP_RPT + 2 * H;         // phase-B window
     constexpr int NTASK = RA * (SEP_TW / SEP_APT);
     extern __shared__ float sep_lds[];
     float* tile = sep_lds;                      // [RA][TP]
-    float* rc = sep_lds + RA * TP;              // [SEP_CHUNK][RA][SEP_TW]
+    float* rc = sep_lds + RA * TP;              // [SEP_CHUNK][RA][RP]
 
     const cptr<double> f1d = as_const(a.f1d);
     const cptr<double> beta = as_const(a.beta);
@@ -115,8 +116,9 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
             for (int tb = 0; tb < NTASK; tb += NT) {
                 const int task = tb + tid;
                 if (task < NTASK) {
-                    const int r = task / (SEP_TW / SEP_APT);
-                    const int q4 = SEP_APT * (task - r * (SEP_TW / SEP_APT));
+                    // consecutive lanes take consecutive rows (odd pitches: no bank conflicts)
+                    const int qi = task / RA, r = task - qi * RA;
+                    const int q4 = SEP_APT * qi;
                     double win[WA];
 #pragma unroll
                     for (int s = 0; s < WA; ++s) win[s] = (double)tile[r * TP + q4 + s];
@@ -131,7 +133,7 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
 #pragma unroll
                             for (int o = 0; o < SEP_APT; ++o) acc[o] = fma(fu, win[o + 2 * H - u], acc[o]);
                         }
-                        float* dst = rc + ((size_t)c * RA + r) * SEP_TW + q4;
+                        float* dst = rc + ((size_t)c * RA + r) * RP + q4;
 #pragma unroll
                         for (int o = 0; o < SEP_APT; ++o) dst[o] = (float)acc[o];
                     }
@@ -143,7 +145,7 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
                 const int i = i0 + c;
                 double col[WB];
 #pragma unroll
-                for (int s = 0; s < WB; ++s) col[s] = (double)rc[((size_t)c * RA + SEP_RPT * w + s) * SEP_TW + lane];
+                for (int s = 0; s < WB; ++s) col[s] = (double)rc[((size_t)c * RA + SEP_RPT * w + s) * RP + lane];
                 for (int j = 0; j + i <= deg; ++j) {
                     const int n = base + (i + j) * (i + j + 1) / 2 + j;
                     const cptr<double> f = fg + (size_t)j * K;
@@ -209,7 +211,7 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
 template <int H>
 static int launch_sep_t(const SepArgs& a, hipStream_t s) {
     constexpr int RA = SEP_TH + 2 * H, CA = SEP_TW + 2 * H;
-    const size_t lds = ((size_t)RA * CA + (size_t)SEP_CHUNK * RA * SEP_TW) * sizeof(float);
+    const size_t lds = ((size_t)RA * (CA | 1) + (size_t)SEP_CHUNK * RA * (SEP_TW + 1)) * sizeof(float);
     hipLaunchKernelGGL(contract_sep_kernel<H>, dim3(a.n_tiles), dim3(64 * SEP_NW), lds, s, a);
     return hip_status(hipGetLastError(), "contract_sep_kernel");
 }
