@@ -150,8 +150,9 @@ int launch_contract_f32(const ContractArgs& a, const float* frag, int nb, hipStr
 int launch_contract_lowp(const ContractArgs& a, const uint16_t* frag, int nb, int precision,
                          hipStream_t s);
 
-// separable.hip
+// separable.hip, separable_adjoint.hip
 int launch_contract_sep(SepArgs a, hipStream_t s);
+int launch_adjoint_a_sep(svconv_plan* p, const float* R, const float* G, double* ga);
 
 // plan.hip
 int run_forward(svconv_plan* p, const float* R, const float* I, const float* a, float* out);

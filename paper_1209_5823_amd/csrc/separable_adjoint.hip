@@ -1,0 +1,292 @@
+// Adjoint in the coefficients through the separable Gaussian factors.
+//
+//   dL/da[n][m] = sum_p G(p) P_m(p) T_n(p),   T_n = f_j (x)_y (f_i (x)_x R)
+//
+// (the factorisation of the separable forward form).  With the pedestal s,
+// T_n(R) = T_n(R - s) + s beta_n, so
+//   dL/da[n][m] = sum_p G P_m T_n(R - s) + s beta_n sum_p G P_m.
+// The first sum is computed here; the second (gP[m] = sum_p G P_m, the
+// background-gradient reduction) is added by the final kernel.
+//
+// A workgroup walks a 64-column strip of the image (a run of 32-row tiles).
+// Rounds of SA_CHUNK row factors: the strip is walked once per round.
+// Because P_m(x, y) = xh^ie yh^je and every lane keeps its column x over the
+// whole walk, each lane accumulates, for the bases of one round of row
+// factors, the moments V[n][je][lane] = sum_y G T_n yh^je (float64 LDS
+// atomic adds from the 8 waves that share a column); the weighting by xh^ie
+// and the sum over the 64 columns happen once per round at the end of the
+// walk.  Per-workgroup results go to a partial array that a second kernel
+// sums in a fixed order.
+#include "internal.hpp"
+
+namespace svc {
+
+#ifndef SA_ROWS
+#define SA_ROWS 4
+#endif
+#ifndef SA_ROUND
+#define SA_ROUND 4
+#endif
+constexpr int SA_NW = 8, SA_RPT = SA_ROWS, SA_TW = 64, SA_TH = SA_NW * SA_RPT, SA_APT = 8;
+constexpr int SA_CHUNK = SA_ROUND;         // row factors per round
+
+struct SepAdjArgs {
+    const float* R;
+    const float* G;
+    int H, W;
+    float ped;
+    int G_fam;                  // Gaussian families
+    const int* fam;             // [2 G]: degree, first basis
+    const double* f1d;          // [G][kSepMaxFactors][k]
+    int N, M, d_s;
+    double sx, ox, sy, oy;
+    int strips, tiles_y, tiles_per_seg;
+    int vmax;                   // bases per round, at most
+    double* part;               // [n_wg][N M]
+};
+
+template <class T>
+using acptr = const __attribute__((address_space(4))) T*;
+
+template <int H>
+__global__ __launch_bounds__(64 * SA_NW) void adjoint_a_sep_kernel(SepAdjArgs a) {
+    constexpr int NT = 64 * SA_NW;
+    constexpr int K = 2 * H + 1;
+    constexpr int RA = SA_TH + 2 * H, CA = SA_TW + 2 * H;
+    constexpr int TP = CA | 1, RP = SA_TW + 1;
+    constexpr int WA = SA_APT + 2 * H, WB = SA_RPT + 2 * H;
+    constexpr int NTASK = RA * (SA_TW / SA_APT);
+    const int DS1 = a.d_s + 1;
+    extern __shared__ double sa_lds[];
+    double* V = sa_lds;                                  // [vmax][DS1][64]
+    double* xpt = V + (size_t)a.vmax * DS1 * 64;         // [DS1][64] powers of xh
+    float* tile = reinterpret_cast<float*>(xpt + (size_t)DS1 * 64);   // [RA][TP]
+    float* rc = tile + RA * TP;                          // [SA_CHUNK][RA][RP]
+
+    const acptr<double> f1d = (acptr<double>)a.f1d;
+    const acptr<int> fam = (acptr<int>)a.fam;
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int sxi = blockIdx.x % a.strips, seg = blockIdx.x / a.strips;
+    const int X0 = sxi * SA_TW;
+    const int ty0 = seg * a.tiles_per_seg;
+    const int ty1 = min(a.tiles_y, ty0 + a.tiles_per_seg);
+    const int x = X0 + lane;
+    const int NM = a.N * a.M;
+    double* part = a.part + (size_t)blockIdx.x * NM;
+
+    if (w == 0) {
+        const double xh = a.sx * x + a.ox;
+        double pw = 1.0;
+        for (int q = 0; q < DS1; ++q) {
+            xpt[q * 64 + lane] = pw;
+            pw *= xh;
+        }
+    }
+
+    for (int g = 0; g < a.G_fam; ++g) {
+        const int deg = fam[2 * g], base = fam[2 * g + 1];
+        const acptr<double> fg = f1d + (size_t)g * kSepMaxFactors * K;
+        for (int i0 = 0; i0 <= deg; i0 += SA_CHUNK) {
+            const int nc = min(SA_CHUNK, deg + 1 - i0);
+            int nn = 0;
+            for (int c = 0; c < nc; ++c) nn += deg - (i0 + c) + 1;
+            __syncthreads();   // previous round's reduction has read V
+            for (int q = tid; q < nn * DS1 * 64; q += NT) V[q] = 0.0;
+            for (int ty = ty0; ty < ty1; ++ty) {
+                const int Y0 = ty * SA_TH;
+                __syncthreads();   // V cleared / previous tile's rc consumed
+                for (int q = tid; q < RA * CA; q += NT) {
+                    const int r = q / CA, c = q - r * CA;
+                    const int gy = Y0 - H + r, gx = X0 - H + c;
+                    float v = 0.f;
+                    if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) v = a.R[(size_t)gy * a.W + gx];
+                    tile[r * TP + c] = v - a.ped;
+                }
+                __syncthreads();
+                // row pass (as in the forward)
+                for (int tb = 0; tb < NTASK; tb += NT) {
+                    const int task = tb + tid;
+                    if (task < NTASK) {
+                        const int qi = task / RA, r = task - qi * RA;
+                        const int q0 = SA_APT * qi;
+                        double win[WA];
+#pragma unroll
+                        for (int s = 0; s < WA; ++s) win[s] = (double)tile[r * TP + q0 + s];
+                        for (int c = 0; c < nc; ++c) {
+                            const acptr<double> f = fg + (size_t)(i0 + c) * K;
+                            double acc[SA_APT];
+#pragma unroll
+                            for (int o = 0; o < SA_APT; ++o) acc[o] = 0.0;
+#pragma unroll
+                            for (int u = 0; u < K; ++u) {
+                                const double fu = f[u];
+#pragma unroll
+                                for (int o = 0; o < SA_APT; ++o) acc[o] = fma(fu, win[o + 2 * H - u], acc[o]);
+                            }
+                            float* dst = rc + ((size_t)c * RA + r) * RP + q0;
+#pragma unroll
+                            for (int o = 0; o < SA_APT; ++o) dst[o] = (float)acc[o];
+                        }
+                    }
+                }
+                __syncthreads();
+                // column pass per basis, moments of G T_n over this thread's rows
+                double gv[SA_RPT], yv[SA_RPT];
+#pragma unroll
+                for (int o = 0; o < SA_RPT; ++o) {
+                    const int y = Y0 + SA_RPT * w + o;
+                    gv[o] = (x < a.W && y < a.H) ? (double)a.G[(size_t)y * a.W + x] : 0.0;
+                    yv[o] = a.sy * y + a.oy;
+                }
+                int nl = 0;
+                for (int c = 0; c < nc; ++c) {
+                    const int i = i0 + c;
+                    double col[WB];
+#pragma unroll
+                    for (int s = 0; s < WB; ++s) col[s] = (double)rc[((size_t)c * RA + SA_RPT * w + s) * RP + lane];
+                    for (int j = 0; j + i <= deg; ++j, ++nl) {
+                        const acptr<double> f = fg + (size_t)j * K;
+                        double tv[SA_RPT];
+#pragma unroll
+                        for (int o = 0; o < SA_RPT; ++o) tv[o] = 0.0;
+#pragma unroll
+                        for (int v = 0; v < K; ++v) {
+                            const double fv = f[v];
+#pragma unroll
+                            for (int o = 0; o < SA_RPT; ++o) tv[o] = fma(fv, col[o + 2 * H - v], tv[o]);
+                        }
+                        double mom[kMaxSpatialDegree + 1];
+#pragma unroll
+                        for (int q = 0; q <= kMaxSpatialDegree; ++q) mom[q] = 0.0;
+#pragma unroll
+                        for (int o = 0; o < SA_RPT; ++o) {
+                            double pw = gv[o] * tv[o];
+#pragma unroll
+                            for (int q = 0; q <= kMaxSpatialDegree; ++q) {
+                                if (q <= a.d_s) {
+                                    mom[q] += pw;
+                                    pw *= yv[o];
+                                }
+                            }
+                        }
+                        double* vrow = V + (size_t)nl * DS1 * 64 + lane;
+#pragma unroll
+                        for (int q = 0; q <= kMaxSpatialDegree; ++q)
+                            if (q <= a.d_s) atomicAdd(vrow + q * 64, mom[q]);
+                    }
+                }
+            }
+            __syncthreads();
+            // dL/da[n][m] (this strip) = sum_lanes xh^ie V[n][je][lane]
+            for (int q = tid; q < nn * a.M; q += NT) {
+                int l = q / a.M;
+                const int m = q - l * a.M;
+                int t = 0;
+                while ((t + 1) * (t + 2) / 2 <= m) ++t;
+                const int je = m - t * (t + 1) / 2, ie = t - je;
+                int n = -1;
+                for (int c = 0; c < nc && n < 0; ++c) {
+                    const int cnt = deg - (i0 + c) + 1;
+                    if (l < cnt) n = base + (i0 + c + l) * (i0 + c + l + 1) / 2 + l;
+                    else l -= cnt;
+                }
+                const int vl = q / a.M;
+                double s = 0.0;
+                for (int ln = 0; ln < 64; ++ln)
+                    s = fma(xpt[ie * 64 + ln], V[((size_t)vl * DS1 + je) * 64 + ln], s);
+                part[(size_t)n * a.M + m] = s;
+            }
+        }
+    }
+}
+
+// ga[n][m] = sum over workgroups (fixed order) + s beta_n gP[m]
+__global__ void adjoint_a_sep_final(const double* __restrict__ part, int n_wg, int N, int M,
+                                    const double* __restrict__ beta, const double* __restrict__ gP,
+                                    float ped, double* __restrict__ ga) {
+    const int nm = blockIdx.x * blockDim.x + threadIdx.x;
+    if (nm >= N * M) return;
+    double s = 0.0;
+    for (int b = 0; b < n_wg; ++b) s += part[(size_t)b * N * M + nm];
+    const int n = nm / M, m = nm - n * M;
+    ga[nm] = s + (double)ped * beta[n] * gP[m];
+}
+
+template <int H>
+static int launch_asep_t(const SepAdjArgs& a, int n_wg, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL(adjoint_a_sep_kernel<H>, dim3(n_wg), dim3(64 * SA_NW), lds, s, a);
+    return hip_status(hipGetLastError(), "adjoint_a_sep_kernel");
+}
+
+int launch_adjoint_a_sep(svconv_plan* p, const float* R, const float* G, double* ga) {
+    if (!p->dSep1d || p->h < 1 || p->h > 15)
+        return fail(SVCONV_EUNSUPPORTED, "separable adjoint needs Gaussian bases and 1 <= half-width <= 15");
+    const int h = p->h, NM = p->N * p->M;
+    SepAdjArgs a{};
+    a.R = R;
+    a.G = G;
+    a.H = p->H;
+    a.W = p->W;
+    a.ped = p->pedestal;
+    a.G_fam = (int)p->sigmas.size();
+    a.fam = p->dSepFam;
+    a.f1d = p->dSep1d;
+    a.N = p->N;
+    a.M = p->M;
+    a.d_s = p->d_s;
+    if (p->Wf > 1) { a.sx = 2.0 / (p->Wf - 1); a.ox = a.sx * p->x0 - 1.0; }
+    if (p->Hf > 1) { a.sy = 2.0 / (p->Hf - 1); a.oy = a.sy * p->y0 - 1.0; }
+    a.vmax = 0;                                // bases in one round of row factors, at most
+    for (int d : p->degrees)
+        for (int i0 = 0; i0 <= d; i0 += SA_CHUNK) {
+            int nn = 0;
+            for (int c = 0; c < SA_CHUNK && i0 + c <= d; ++c) nn += d - (i0 + c) + 1;
+            a.vmax = nn > a.vmax ? nn : a.vmax;
+        }
+    a.strips = (p->W + SA_TW - 1) / SA_TW;
+    a.tiles_y = (p->H + SA_TH - 1) / SA_TH;
+    // about two workgroups per CU, within the partial-sum scratch
+    const size_t cap = adjoint_scratch_doubles(p->H, p->W, p->k, p->M) / (size_t)NM - 1;
+    int segs = (512 + a.strips - 1) / a.strips;
+    if (segs > a.tiles_y) segs = a.tiles_y;
+    a.tiles_per_seg = (a.tiles_y + segs - 1) / segs;
+    segs = (a.tiles_y + a.tiles_per_seg - 1) / a.tiles_per_seg;
+    while ((size_t)a.strips * segs > cap && a.tiles_per_seg < a.tiles_y) {
+        a.tiles_per_seg *= 2;
+        segs = (a.tiles_y + a.tiles_per_seg - 1) / a.tiles_per_seg;
+    }
+    const int n_wg = a.strips * segs;
+    if ((size_t)n_wg > cap) return fail(SVCONV_EUNSUPPORTED, "image too wide for the adjoint scratch");
+    a.part = p->dQpart;
+    double* gP = p->dVec + 6 * (size_t)kMaxCoefficients;
+    int st = launch_bg_grad(p, G, gP);
+    if (st) return st;
+    const int RA = SA_TH + 2 * h, CA = SA_TW + 2 * h;
+    const size_t lds = ((size_t)a.vmax * (a.d_s + 1) * 64 + (size_t)(a.d_s + 1) * 64) * sizeof(double) +
+                       ((size_t)RA * (CA | 1) + (size_t)SA_CHUNK * RA * (SA_TW + 1)) * sizeof(float);
+    if (lds > 160 * 1024) return fail(SVCONV_EUNSUPPORTED, "separable adjoint: LDS budget exceeded");
+    switch (h) {
+        case 1: st = launch_asep_t<1>(a, n_wg, lds, p->stream); break;
+        case 2: st = launch_asep_t<2>(a, n_wg, lds, p->stream); break;
+        case 3: st = launch_asep_t<3>(a, n_wg, lds, p->stream); break;
+        case 4: st = launch_asep_t<4>(a, n_wg, lds, p->stream); break;
+        case 5: st = launch_asep_t<5>(a, n_wg, lds, p->stream); break;
+        case 6: st = launch_asep_t<6>(a, n_wg, lds, p->stream); break;
+        case 7: st = launch_asep_t<7>(a, n_wg, lds, p->stream); break;
+        case 8: st = launch_asep_t<8>(a, n_wg, lds, p->stream); break;
+        case 9: st = launch_asep_t<9>(a, n_wg, lds, p->stream); break;
+        case 10: st = launch_asep_t<10>(a, n_wg, lds, p->stream); break;
+        case 11: st = launch_asep_t<11>(a, n_wg, lds, p->stream); break;
+        case 12: st = launch_asep_t<12>(a, n_wg, lds, p->stream); break;
+        case 13: st = launch_asep_t<13>(a, n_wg, lds, p->stream); break;
+        case 14: st = launch_asep_t<14>(a, n_wg, lds, p->stream); break;
+        default: st = launch_asep_t<15>(a, n_wg, lds, p->stream); break;
+    }
+    if (st) return st;
+    hipLaunchKernelGGL(adjoint_a_sep_final, dim3((NM + 255) / 256), dim3(256), 0, p->stream, p->dQpart,
+                       n_wg, p->N, p->M, p->dBeta, gP, p->pedestal, ga);
+    return hip_status(hipGetLastError(), "adjoint_a_sep_final");
+}
+
+}  // namespace svc

@@ -71,3 +71,70 @@ def test_separable_rejects_delta_basis_plans(svc):
         with pytest.raises(SvconvError) as ei:
             plan.set_form("separable")
         assert ei.value.status == EUNSUPPORTED
+
+
+# ----------------------------------------------- adjoint in a, separable ----
+
+@pytest.mark.parametrize("pedestal", [0.0, 1000.0])
+def test_separable_adjoint_a_vs_oracle_c3_crop(svc, orc, pedestal):
+    # the c3 crop of the adjoint tests (256 x 256 at frame offset (2100,
+    # 1900), 31 x 31 kernel, 49 bases, spatial degree 3) with the same
+    # rounding bound: 2e-5 of the magnitude sums sum_p |G| |P_m| |T_n|
+    from tests.test_gpu_backward import crop_case, REL, C3
+    R, I, a, B, frame = crop_case(orc, C3)
+    h, d_s = C3.half_width, C3.spatial_degree
+    D = orc.difference(R, I, h, B, d_s, a, frame=frame)
+    G = (2.0 * D * orc.interior_mask(*R.shape, h)).astype(np.float32)
+    ga_ref = orc.grad_a(R, h, B, d_s, G, frame=frame)
+    sa = orc.grad_a(np.abs(R), h, np.abs(B), 0, np.abs(G), frame=frame)[:, :1]
+    say("separable adjoint in a, c3 crop, pedestal", pedestal)
+    with svc.Plan(R.shape[0], R.shape[1], h, C3.sigmas, C3.degrees, d_s, form="separable",
+                  frame=frame, pedestal=pedestal) as plan:
+        _, ga = plan.backward(to_dev(R), to_dev(a), to_dev(G), want_gR=False)
+        ga = to_host(ga)
+    e = np.abs(ga - ga_ref)
+    say("  max err %.3e (scale %.3e)" % (e.max(), sa.max()))
+    assert np.all(e <= REL * sa + 1e-9)
+
+
+@pytest.mark.parametrize("name", ["h1_ragged", "nb3_degree3", "max_filters_64",
+                                  "max_spatial_degree_6", "single_column", "single_row",
+                                  "all_border_8x8"])
+def test_separable_adjoint_a_edge_cases(svc, orc, name):
+    case = EDGE_CASES[name]
+    H, W, h, sig, deg, d_s, frame = case
+    R, I, a = _edge_inputs(name, case)
+    G = synth.uniform_image(H, W, seed=17, lo=-40.0, hi=40.0)
+    B = orc.basis(h, sig, deg)
+    ga_ref = orc.grad_a(R, h, B, d_s, G, frame=frame)
+    sa = orc.grad_a(np.abs(R), h, np.abs(B), 0, np.abs(G), frame=frame)[:, :1]
+    say("separable adjoint edge", name)
+    with svc.Plan(H, W, h, sig, deg, d_s, form="separable", frame=frame,
+                  pedestal=synth.SKY_LEVEL) as plan:
+        _, ga = plan.backward(to_dev(R), to_dev(a), to_dev(G), want_gR=False)
+        ga = to_host(ga)
+    e = np.abs(ga - ga_ref)
+    say("  max err %.3e" % e.max())
+    assert np.all(e <= 2e-5 * sa + 1e-9)
+
+
+def test_separable_gauss_newton_recovers_noiseless_coefficients(svc, orc):
+    import torch
+    from tests.test_gpu_fit import small_case
+    R, C, a_star, B, (H, W, h, sig, deg, d_s) = small_case(orc, H=96, W=112)
+    I = C.astype(np.float32)
+    r = np.random.default_rng(1)
+    a0 = a_star.astype(np.float64) + r.uniform(-0.02, 0.02, a_star.shape)
+    say("gauss-newton, separable form")
+    with svc.Plan(H, W, h, sig, deg, d_s, form="separable", pedestal=1000.0) as plan:
+        Rd, Id = to_dev(R), to_dev(I)
+        JtJ = plan.cholesky_factor(plan.normal_matrix(Rd))
+        a64 = torch.from_numpy(a0).cuda()
+        a32 = torch.empty(a_star.shape, dtype=torch.float32, device="cuda")
+        D = torch.empty_like(Rd)
+        hist = [plan.gn_step(Rd, Id, JtJ, a64, a32, D) for _ in range(4)]
+        a_fit = to_host(a64)
+    err = np.abs(a_fit - a_star).max()
+    say("  max |a - a*| = %.3e" % err)
+    assert err <= 2e-5
+    assert hist[-1][0] < 1e-3 * hist[0][0]
