@@ -1,7 +1,8 @@
 """The fit at survey scale: 8192 x 8192 star field, 31 x 31 kernel, 49
 bases, spatial degree 4 (735 coefficients).  I = float32(Poisson(C(R;
 a_hidden))) with C from the oracle's FFT regrouping; the coefficients are
-fitted by Gauss-Newton with the bf16x3 and FP32 forwards.  Reports the
+fitted by Gauss-Newton with the bf16x3 and FP32 matrix-core forwards and with
+the separable form (forward and adjoint through the Gaussian factors).  Reports the
 recovered-coefficient error, the final D RMS in sigma_sky and the Mpix/s of
 one iteration."""
 
@@ -27,13 +28,14 @@ def c4_case(orc):
     return wl, R, I, a_hidden, a0
 
 
-@pytest.mark.parametrize("precision", ["bf16x3", "fp32"])
-def test_fit_survey_scale(svc, c4_case, precision):
+@pytest.mark.parametrize("precision,form", [("bf16x3", "basis"), ("fp32", "basis"),
+                                            ("fp32", "separable")])
+def test_fit_survey_scale(svc, c4_case, precision, form):
     import torch
     from paper_1209_5823_amd.fit import gauss_newton_fit
     wl, R, I, a_hidden, a0 = c4_case
-    say("c4 fit", precision)
-    with svc.plan_for(wl, precision=precision, pedestal=synth.SKY_LEVEL) as plan:
+    say("c4 fit", precision, form)
+    with svc.plan_for(wl, precision=precision, form=form, pedestal=synth.SKY_LEVEL) as plan:
         Rd, Id = to_dev(R), to_dev(I)
         a64, D, hist, t_setup = gauss_newton_fit(plan, Rd, Id, to_dev(a0), iters=3, timings=True)
         a_fit = to_host(a64)
