@@ -192,7 +192,9 @@ __global__ void adjoint_a_final(const double* __restrict__ F64, const double* __
 
 int launch_adjoint_a(svconv_plan* p, const float* R, const float* gD, double* ga) {
     // a plan in the separable form takes the adjoint through the same factors
-    if (p->form == SVCONV_FORM_SEPARABLE) return launch_adjoint_a_sep(p, R, gD, ga);
+    // (when its per-round moments fit in LDS; otherwise the product below)
+    if (p->form == SVCONV_FORM_SEPARABLE && sep_adjoint_supported(p))
+        return launch_adjoint_a_sep(p, R, gD, ga);
     const AdjointQGeometry g = aq_geometry(p->H, p->W, p->k, p->M);
     if (!p->dQpart) return fail(SVCONV_ENOMEM, "adjoint scratch missing");
     double sx = 0, ox = 0, sy = 0, oy = 0;

@@ -10,9 +10,14 @@
 // 2 d_s.  So JtJ is assembled from
 //   S[mu][n][n'] = sum_p mask(p) Q_mu(p) T_n(p) T_n'(p)
 // over the (d_s + 1)(2 d_s + 1) monomials Q_mu of degree <= 2 d_s, which needs
-// N^2 per monomial instead of (N M)^2 products per pixel.  The T_n of a band
-// of rows are produced by the forward contraction (written out instead of
-// being contracted with c_n), then S is accumulated on the float64 matrix
+// N^2 per monomial instead of (N M)^2 products per pixel.  Within one image
+// row yh is constant, so with Q_mu = xh^a yh^b the Gram sums of a row segment
+// are taken for the 2 d_s + 1 powers of xh only,
+//   G_a[n][n'] = sum_{x in segment} mask xh^a T_n T_n',
+// and S[(a, b)] = sum_segments yh^b G_a is formed by the reduction: 2 d_s + 1
+// instead of (d_s + 1)(2 d_s + 1) weighted products per pixel.  The T_n of a
+// band of rows are produced by the forward contraction (written out instead
+// of being contracted with c_n), then G is accumulated on the float64 matrix
 // cores (v_mfma_f64_16x16x4_f64).
 #include <cmath>
 
@@ -88,64 +93,70 @@ __device__ __forceinline__ double ipow_f(double x, int e) {
     return r;
 }
 
-// S_part[chunk][mu][n][n'] for 64 x 64 (n, n') and one monomial mu per
-// workgroup: wave w owns rows n = 16 w .. 16 w + 15, all 64 columns.
-// A operand: T_n(p_k); B operand: T_n'(p_k) Q_mu(p_k) mask(p_k).
+// G_part[seg][a][n][n'] for 64 x 64 (n, n') and one power a of xh per
+// workgroup; a segment is up to NM_PIX_CHUNK pixels of one row of the band.
+// Wave w owns rows n = 16 w .. 16 w + 15; blocks whose rows or columns are
+// all padding are skipped.  A operand: T_n(p_k); B operand: T_n'(p_k) xh^a mask.
 __global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ T, int N, int band_px,
-                                                   int y_begin, int W, int H, int h,
+                                                   int y_begin, int W, int H, int h, int cpr,
                                                    const unsigned char* __restrict__ mask,
-                                                   double sx, double ox, double sy, double oy,
-                                                   int n_mu, double* __restrict__ part) {
-    const int mu = blockIdx.x;
-    const int chunk = blockIdx.y;
+                                                   double sx, double ox, int n_a,
+                                                   double* __restrict__ part) {
+    const int ea = blockIdx.x;
+    const int seg = blockIdx.y;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int kq = lane >> 4, j = lane & 15;
-    int tt = 0;
-    while ((tt + 1) * (tt + 2) / 2 <= mu) ++tt;
-    const int ej = mu - tt * (tt + 1) / 2;
-    const int ei = tt - ej;
+    const int row = seg / cpr, x_begin = (seg - row * cpr) * NM_PIX_CHUNK;
+    const int x_end = min(W, x_begin + NM_PIX_CHUNK);
+    const int y = y_begin + row;
 
     d4 acc[4];
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
     const int na = 16 * w + j;                         // A row of this lane
-    const int p_begin = chunk * NM_PIX_CHUNK;
-    const int p_end = min(band_px, p_begin + NM_PIX_CHUNK);
-    for (int p0 = p_begin; p0 < p_end; p0 += 4) {
-        const int pp = p0 + kq;
-        double wq = 0.0;
-        if (pp < p_end) {
-            const int y = y_begin + pp / W, x = pp % W;
-            if (in_mask(mask, H, W, h, x, y))
-                wq = ipow_f(sx * x + ox, ei) * ipow_f(sy * y + oy, ej);
-        }
-        const bool ok = pp < p_end;
-        const double av = (ok && na < N) ? (double)T[(size_t)na * band_px + pp] : 0.0;
+    if (16 * w < N) {
+        for (int x0 = x_begin; x0 < x_end; x0 += 4) {
+            const int x = x0 + kq;
+            const bool ok = x < x_end;
+            const size_t pp = (size_t)row * W + x;
+            double wq = 0.0;
+            if (ok && in_mask(mask, H, W, h, x, y)) wq = ipow_f(sx * x + ox, ea);
+            const double av = (ok && na < N) ? (double)T[(size_t)na * band_px + pp] : 0.0;
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-            const int nb = 16 * cb + j;
-            const double bv = (ok && nb < N) ? (double)T[(size_t)nb * band_px + pp] * wq : 0.0;
-            acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[cb], 0, 0, 0);
+            for (int cb = 0; cb < 4; ++cb) {
+                if (16 * cb < N) {   // uniform
+                    const int nb = 16 * cb + j;
+                    const double bv = (ok && nb < N) ? (double)T[(size_t)nb * band_px + pp] * wq : 0.0;
+                    acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[cb], 0, 0, 0);
+                }
+            }
         }
     }
     // the float64 16x16x4 instruction stores row 4 e + kq of the 16 x 16
     // block in register e of lane (kq, j) (groups of one row, unlike the
     // float32 form's groups of four): lane (kq, j) holds
-    // S[n = 16 w + 4 e + kq][n' = 16 cb + j]
-    double* dst = part + ((size_t)chunk * n_mu + mu) * 64 * 64;
+    // G[n = 16 w + 4 e + kq][n' = 16 cb + j]
+    double* dst = part + ((size_t)seg * n_a + ea) * 64 * 64;
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
         for (int e = 0; e < 4; ++e) dst[(16 * w + 4 * e + kq) * 64 + 16 * cb + j] = acc[cb][e];
 }
 
-// S[mu][.][.] += sum over chunks (fixed order)
-__global__ void gram_reduce(const double* __restrict__ part, int n_chunks, int n_mu,
-                            double* __restrict__ S) {
+// S[(a, b)][.][.] += sum over segments (fixed order) of yh(segment row)^b G_a
+__global__ void gram_reduce(const double* __restrict__ part, int n_seg, int cpr, int n_a, int n_mu,
+                            int y_begin, double sy, double oy, double* __restrict__ S) {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n_mu * 4096) return;
+    const int mu = idx >> 12, e = idx & 4095;
+    int tt = 0;
+    while ((tt + 1) * (tt + 2) / 2 <= mu) ++tt;
+    const int eb = mu - tt * (tt + 1) / 2, ea = tt - eb;
     double s = 0.0;
-    for (int c = 0; c < n_chunks; ++c) s += part[(size_t)c * n_mu * 4096 + idx];
+    for (int c = 0; c < n_seg; ++c) {
+        const double yh = sy * (y_begin + c / cpr) + oy;
+        s += ipow_f(yh, eb) * part[((size_t)c * n_a + ea) * 4096 + e];
+    }
     S[idx] += s;
 }
 
@@ -188,13 +199,13 @@ int launch_normal_matrix(svconv_plan* p, const float* R, const unsigned char* ma
     const int NF = p->N + p->bg;
     if (NF > 64) return fail(SVCONV_EUNSUPPORTED, "normal matrix needs N (+1 with a background) <= 64");
     const int n_mu = (2 * p->d_s + 1) * (2 * p->d_s + 2) / 2;
+    const int n_a = 2 * p->d_s + 1;                       // powers of xh
+    const int cpr = (p->W + NM_PIX_CHUNK - 1) / NM_PIX_CHUNK;   // segments per row
     const size_t row_bytes = (size_t)NF * p->W * sizeof(float);
     int band = (int)(NM_BAND_BYTES / row_bytes);
     if (band < 8) band = 8;
     if (band > p->H) band = p->H;
-    const int max_px = band * p->W;
-    const int n_chunks = (max_px + NM_PIX_CHUNK - 1) / NM_PIX_CHUNK;
-    const size_t part_elems = (size_t)n_chunks * n_mu * 4096;
+    const size_t part_elems = (size_t)band * cpr * n_a * 4096;
     const size_t s_elems = (size_t)n_mu * 4096;
     const size_t tband_bytes = (size_t)band * row_bytes;
     const size_t nmpart_bytes = (part_elems + s_elems) * sizeof(double);
@@ -247,7 +258,31 @@ int launch_normal_matrix(svconv_plan* p, const float* R, const unsigned char* ma
         const int rows = (y0 + band <= p->H) ? band : p->H - y0;
         c.y_begin = y0;
         c.n_rows = rows;
-        st = launch_contract_f32(c, p->dFragF32, nb, p->stream);
+        if (p->form == SVCONV_FORM_SEPARABLE) {
+            // basis responses through the separable factors
+            SepArgs sa{};
+            sa.X = R;
+            sa.I = nullptr;
+            sa.out = nullptr;
+            sa.H = p->H;
+            sa.W = p->W;
+            sa.h = p->h;
+            sa.ped = p->pedestal;
+            sa.G = (int)p->sigmas.size();
+            sa.fam = p->dSepFam;
+            sa.f1d = p->dSep1d;
+            sa.beta = p->dBeta;
+            sa.coef = reinterpret_cast<const float*>(p->dF32);   // not read in this mode
+            sa.M = p->M;
+            sa.d_s = p->d_s;
+            sa.sx = sx; sa.ox = ox; sa.sy = sy; sa.oy = oy;
+            sa.y_begin = y0;
+            sa.n_rows = rows;
+            sa.tout = p->dTband;
+            st = launch_contract_sep(sa, p->stream);
+        } else {
+            st = launch_contract_f32(c, p->dFragF32, nb, p->stream);
+        }
         if (st) return st;
         const int band_px = rows * p->W;
         if (p->bg) {
@@ -256,14 +291,13 @@ int launch_normal_matrix(svconv_plan* p, const float* R, const unsigned char* ma
             st = hip_status(hipGetLastError(), "fill_ones_kernel");
             if (st) return st;
         }
-        const int chunks = (band_px + NM_PIX_CHUNK - 1) / NM_PIX_CHUNK;
-        hipLaunchKernelGGL(gram_kernel, dim3(n_mu, chunks), dim3(256), 0, p->stream, p->dTband,
-                           NF, band_px, y0, p->W, p->H, p->h, mask, sx, ox, sy, oy, n_mu,
-                           p->dNMpart);
+        const int segs = rows * cpr;
+        hipLaunchKernelGGL(gram_kernel, dim3(n_a, segs), dim3(256), 0, p->stream, p->dTband, NF,
+                           band_px, y0, p->W, p->H, p->h, cpr, mask, sx, ox, n_a, p->dNMpart);
         st = hip_status(hipGetLastError(), "gram_kernel");
         if (st) return st;
         hipLaunchKernelGGL(gram_reduce, dim3((n_mu * 4096 + 255) / 256), dim3(256), 0, p->stream,
-                           p->dNMpart, chunks, n_mu, S);
+                           p->dNMpart, segs, cpr, n_a, n_mu, y0, sy, oy, S);
         st = hip_status(hipGetLastError(), "gram_reduce");
         if (st) return st;
     }

@@ -81,6 +81,8 @@ struct SepArgs {
     int M, d_s;
     double sx, ox, sy, oy;
     int tiles_x, n_tiles;
+    int y_begin, n_rows;        // output rows [y_begin, y_begin + n_rows)
+    float* tout;                // nullable: T_n + s beta_n planes [N][n_rows][W] instead of D
 };
 
 }  // namespace svc
@@ -153,6 +155,7 @@ int launch_contract_lowp(const ContractArgs& a, const uint16_t* frag, int nb, in
 // separable.hip, separable_adjoint.hip
 int launch_contract_sep(SepArgs a, hipStream_t s);
 int launch_adjoint_a_sep(svconv_plan* p, const float* R, const float* G, double* ga);
+bool sep_adjoint_supported(const svconv_plan* p);
 
 // plan.hip
 int run_forward(svconv_plan* p, const float* R, const float* I, const float* a, float* out);

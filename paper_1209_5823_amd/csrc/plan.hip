@@ -246,6 +246,9 @@ int run_forward(svconv_plan* p, const float* R, const float* I, const float* a, 
         sa.M = p->M;
         sa.d_s = p->d_s;
         sa.sx = c.sx; sa.ox = c.ox; sa.sy = c.sy; sa.oy = c.oy;
+        sa.y_begin = 0;
+        sa.n_rows = p->H;
+        sa.tout = nullptr;
         return launch_contract_sep(sa, p->stream);
     }
     if (p->form == SVCONV_FORM_BASIS) {

@@ -80,7 +80,9 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
     const int tid = threadIdx.x;
     const int t = sep_xcd_remap(blockIdx.x, a.n_tiles);
     const int X0 = (t % a.tiles_x) * SEP_TW;
-    const int Y0 = (t / a.tiles_x) * SEP_TH;
+    const int Y0 = a.y_begin + (t / a.tiles_x) * SEP_TH;
+    const int y_end = min(a.H, a.y_begin + a.n_rows);
+    const bool t_only = a.tout != nullptr;   // write the basis responses instead of D
 
     // stage R - s; outside the image R is 0, so the staged value is -s there
     for (int q = tid; q < RA * CA; q += NT) {
@@ -158,6 +160,18 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
 #pragma unroll
                         for (int o = 0; o < SEP_RPT; ++o) tv[o] = fma(fv, col[o + 2 * H - v], tv[o]);
                     }
+                    if (t_only) {
+                        const double pbt = (double)a.ped * beta[n];
+                        if (x < a.W) {
+#pragma unroll
+                            for (int o = 0; o < SEP_RPT; ++o) {
+                                const int y = Y0 + SEP_RPT * w + o;
+                                if (y < y_end)
+                                    a.tout[((size_t)n * a.n_rows + (y - a.y_begin)) * a.W + x] = (float)(tv[o] + pbt);
+                            }
+                        }
+                        continue;
+                    }
                     // c_n(x, y) = sum_jj Cy[jj] yh^jj with Cy[jj] = sum_ie a[n][m(ie, jj)] xh^ie
                     double cy[kMaxSpatialDegree + 1];
 #pragma unroll
@@ -195,11 +209,11 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
             }
         }
     }
-    if (x < a.W) {
+    if (!t_only && x < a.W) {
 #pragma unroll
         for (int o = 0; o < SEP_RPT; ++o) {
             const int y = Y0 + SEP_RPT * w + o;
-            if (y < a.H) {
+            if (y < y_end) {
                 const size_t idx = (size_t)y * a.W + x;
                 const double iv = a.I ? (double)a.I[idx] : 0.0;
                 a.out[idx] = (float)(dacc[o] - iv);
@@ -218,7 +232,7 @@ static int launch_sep_t(const SepArgs& a, hipStream_t s) {
 
 int launch_contract_sep(SepArgs a, hipStream_t s) {
     a.tiles_x = (a.W + SEP_TW - 1) / SEP_TW;
-    const int tiles_y = (a.H + SEP_TH - 1) / SEP_TH;
+    const int tiles_y = (a.n_rows + SEP_TH - 1) / SEP_TH;
     a.n_tiles = a.tiles_x * tiles_y;
     switch (a.h) {
         case 1: return launch_sep_t<1>(a, s);

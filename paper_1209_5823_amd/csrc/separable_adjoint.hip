@@ -5,8 +5,9 @@
 // (the factorisation of the separable forward form).  With the pedestal s,
 // T_n(R) = T_n(R - s) + s beta_n, so
 //   dL/da[n][m] = sum_p G P_m T_n(R - s) + s beta_n sum_p G P_m.
-// The first sum is computed here; the second (gP[m] = sum_p G P_m, the
-// background-gradient reduction) is added by the final kernel.
+// Both sums are computed here: gP[m] = sum_p G P_m is the same moment sum
+// with a response of 1, accumulated once (in the first round) in one extra
+// slot, and the final kernel adds s beta_n gP[m].
 //
 // A workgroup walks a 64-column strip of the image (a run of 32-row tiles).
 // Rounds of SA_CHUNK row factors: the strip is walked once per round.
@@ -58,8 +59,8 @@ __global__ __launch_bounds__(64 * SA_NW) void adjoint_a_sep_kernel(SepAdjArgs a)
     constexpr int NTASK = RA * (SA_TW / SA_APT);
     const int DS1 = a.d_s + 1;
     extern __shared__ double sa_lds[];
-    double* V = sa_lds;                                  // [vmax][DS1][64]
-    double* xpt = V + (size_t)a.vmax * DS1 * 64;         // [DS1][64] powers of xh
+    double* V = sa_lds;                                  // [vmax + 1][DS1][64]
+    double* xpt = V + (size_t)(a.vmax + 1) * DS1 * 64;   // [DS1][64] powers of xh
     float* tile = reinterpret_cast<float*>(xpt + (size_t)DS1 * 64);   // [RA][TP]
     float* rc = tile + RA * TP;                          // [SA_CHUNK][RA][RP]
 
@@ -73,7 +74,7 @@ __global__ __launch_bounds__(64 * SA_NW) void adjoint_a_sep_kernel(SepAdjArgs a)
     const int ty1 = min(a.tiles_y, ty0 + a.tiles_per_seg);
     const int x = X0 + lane;
     const int NM = a.N * a.M;
-    double* part = a.part + (size_t)blockIdx.x * NM;
+    double* part = a.part + (size_t)blockIdx.x * (NM + a.M);   // [N][M] then gP[M]
 
     if (w == 0) {
         const double xh = a.sx * x + a.ox;
@@ -91,8 +92,10 @@ __global__ __launch_bounds__(64 * SA_NW) void adjoint_a_sep_kernel(SepAdjArgs a)
             const int nc = min(SA_CHUNK, deg + 1 - i0);
             int nn = 0;
             for (int c = 0; c < nc; ++c) nn += deg - (i0 + c) + 1;
+            const bool first = (g == 0 && i0 == 0);   // this round also sums G P_m (slot nn)
+            const int slots = nn + (first ? 1 : 0);
             __syncthreads();   // previous round's reduction has read V
-            for (int q = tid; q < nn * DS1 * 64; q += NT) V[q] = 0.0;
+            for (int q = tid; q < slots * DS1 * 64; q += NT) V[q] = 0.0;
             for (int ty = ty0; ty < ty1; ++ty) {
                 const int Y0 = ty * SA_TH;
                 __syncthreads();   // V cleared / previous tile's rc consumed
@@ -139,6 +142,26 @@ __global__ __launch_bounds__(64 * SA_NW) void adjoint_a_sep_kernel(SepAdjArgs a)
                     gv[o] = (x < a.W && y < a.H) ? (double)a.G[(size_t)y * a.W + x] : 0.0;
                     yv[o] = a.sy * y + a.oy;
                 }
+                if (first) {
+                    double mom[kMaxSpatialDegree + 1];
+#pragma unroll
+                    for (int q = 0; q <= kMaxSpatialDegree; ++q) mom[q] = 0.0;
+#pragma unroll
+                    for (int o = 0; o < SA_RPT; ++o) {
+                        double pw = gv[o];
+#pragma unroll
+                        for (int q = 0; q <= kMaxSpatialDegree; ++q) {
+                            if (q <= a.d_s) {
+                                mom[q] += pw;
+                                pw *= yv[o];
+                            }
+                        }
+                    }
+                    double* vrow = V + (size_t)nn * DS1 * 64 + lane;
+#pragma unroll
+                    for (int q = 0; q <= kMaxSpatialDegree; ++q)
+                        if (q <= a.d_s) atomicAdd(vrow + q * 64, mom[q]);
+                }
                 int nl = 0;
                 for (int c = 0; c < nc; ++c) {
                     const int i = i0 + c;
@@ -179,14 +202,14 @@ __global__ __launch_bounds__(64 * SA_NW) void adjoint_a_sep_kernel(SepAdjArgs a)
             }
             __syncthreads();
             // dL/da[n][m] (this strip) = sum_lanes xh^ie V[n][je][lane]
-            for (int q = tid; q < nn * a.M; q += NT) {
+            for (int q = tid; q < slots * a.M; q += NT) {
                 int l = q / a.M;
                 const int m = q - l * a.M;
                 int t = 0;
                 while ((t + 1) * (t + 2) / 2 <= m) ++t;
                 const int je = m - t * (t + 1) / 2, ie = t - je;
-                int n = -1;
-                for (int c = 0; c < nc && n < 0; ++c) {
+                int n = a.N;                     // slot nn: the G P_m sums
+                for (int c = 0; c < nc && n == a.N && l < nn; ++c) {
                     const int cnt = deg - (i0 + c) + 1;
                     if (l < cnt) n = base + (i0 + c + l) * (i0 + c + l + 1) / 2 + l;
                     else l -= cnt;
@@ -203,14 +226,18 @@ __global__ __launch_bounds__(64 * SA_NW) void adjoint_a_sep_kernel(SepAdjArgs a)
 
 // ga[n][m] = sum over workgroups (fixed order) + s beta_n gP[m]
 __global__ void adjoint_a_sep_final(const double* __restrict__ part, int n_wg, int N, int M,
-                                    const double* __restrict__ beta, const double* __restrict__ gP,
-                                    float ped, double* __restrict__ ga) {
+                                    const double* __restrict__ beta, float ped,
+                                    double* __restrict__ ga) {
     const int nm = blockIdx.x * blockDim.x + threadIdx.x;
     if (nm >= N * M) return;
-    double s = 0.0;
-    for (int b = 0; b < n_wg; ++b) s += part[(size_t)b * N * M + nm];
     const int n = nm / M, m = nm - n * M;
-    ga[nm] = s + (double)ped * beta[n] * gP[m];
+    const size_t stride = (size_t)(N + 1) * M;
+    double s = 0.0, gp = 0.0;
+    for (int b = 0; b < n_wg; ++b) {
+        s += part[b * stride + nm];
+        gp += part[b * stride + (size_t)N * M + m];
+    }
+    ga[nm] = s + (double)ped * beta[n] * gp;
 }
 
 template <int H>
@@ -219,9 +246,31 @@ static int launch_asep_t(const SepAdjArgs& a, int n_wg, size_t lds, hipStream_t 
     return hip_status(hipGetLastError(), "adjoint_a_sep_kernel");
 }
 
+static int sep_round_bases(const svconv_plan* p) {
+    int vmax = 0;                              // bases in one round of row factors, at most
+    for (int d : p->degrees)
+        for (int i0 = 0; i0 <= d; i0 += SA_CHUNK) {
+            int nn = 0;
+            for (int c = 0; c < SA_CHUNK && i0 + c <= d; ++c) nn += d - (i0 + c) + 1;
+            vmax = nn > vmax ? nn : vmax;
+        }
+    return vmax;
+}
+
+static size_t sep_adjoint_lds(const svconv_plan* p) {
+    const int RA = SA_TH + 2 * p->h, CA = SA_TW + 2 * p->h;
+    return ((size_t)(sep_round_bases(p) + 1) * (p->d_s + 1) * 64 + (size_t)(p->d_s + 1) * 64) *
+               sizeof(double) +
+           ((size_t)RA * (CA | 1) + (size_t)SA_CHUNK * RA * (SA_TW + 1)) * sizeof(float);
+}
+
+bool sep_adjoint_supported(const svconv_plan* p) {
+    return p->dSep1d && p->h >= 1 && p->h <= 15 && sep_adjoint_lds(p) <= 160 * 1024;
+}
+
 int launch_adjoint_a_sep(svconv_plan* p, const float* R, const float* G, double* ga) {
-    if (!p->dSep1d || p->h < 1 || p->h > 15)
-        return fail(SVCONV_EUNSUPPORTED, "separable adjoint needs Gaussian bases and 1 <= half-width <= 15");
+    if (!sep_adjoint_supported(p))
+        return fail(SVCONV_EUNSUPPORTED, "separable adjoint: Gaussian bases, 1 <= half-width <= 15 and its LDS budget");
     const int h = p->h, NM = p->N * p->M;
     SepAdjArgs a{};
     a.R = R;
@@ -237,17 +286,11 @@ int launch_adjoint_a_sep(svconv_plan* p, const float* R, const float* G, double*
     a.d_s = p->d_s;
     if (p->Wf > 1) { a.sx = 2.0 / (p->Wf - 1); a.ox = a.sx * p->x0 - 1.0; }
     if (p->Hf > 1) { a.sy = 2.0 / (p->Hf - 1); a.oy = a.sy * p->y0 - 1.0; }
-    a.vmax = 0;                                // bases in one round of row factors, at most
-    for (int d : p->degrees)
-        for (int i0 = 0; i0 <= d; i0 += SA_CHUNK) {
-            int nn = 0;
-            for (int c = 0; c < SA_CHUNK && i0 + c <= d; ++c) nn += d - (i0 + c) + 1;
-            a.vmax = nn > a.vmax ? nn : a.vmax;
-        }
+    a.vmax = sep_round_bases(p);
     a.strips = (p->W + SA_TW - 1) / SA_TW;
     a.tiles_y = (p->H + SA_TH - 1) / SA_TH;
     // about two workgroups per CU, within the partial-sum scratch
-    const size_t cap = adjoint_scratch_doubles(p->H, p->W, p->k, p->M) / (size_t)NM - 1;
+    const size_t cap = adjoint_scratch_doubles(p->H, p->W, p->k, p->M) / (size_t)(NM + p->M) - 1;
     int segs = (512 + a.strips - 1) / a.strips;
     if (segs > a.tiles_y) segs = a.tiles_y;
     a.tiles_per_seg = (a.tiles_y + segs - 1) / segs;
@@ -259,13 +302,8 @@ int launch_adjoint_a_sep(svconv_plan* p, const float* R, const float* G, double*
     const int n_wg = a.strips * segs;
     if ((size_t)n_wg > cap) return fail(SVCONV_EUNSUPPORTED, "image too wide for the adjoint scratch");
     a.part = p->dQpart;
-    double* gP = p->dVec + 6 * (size_t)kMaxCoefficients;
-    int st = launch_bg_grad(p, G, gP);
-    if (st) return st;
-    const int RA = SA_TH + 2 * h, CA = SA_TW + 2 * h;
-    const size_t lds = ((size_t)a.vmax * (a.d_s + 1) * 64 + (size_t)(a.d_s + 1) * 64) * sizeof(double) +
-                       ((size_t)RA * (CA | 1) + (size_t)SA_CHUNK * RA * (SA_TW + 1)) * sizeof(float);
-    if (lds > 160 * 1024) return fail(SVCONV_EUNSUPPORTED, "separable adjoint: LDS budget exceeded");
+    int st = SVCONV_OK;
+    const size_t lds = sep_adjoint_lds(p);
     switch (h) {
         case 1: st = launch_asep_t<1>(a, n_wg, lds, p->stream); break;
         case 2: st = launch_asep_t<2>(a, n_wg, lds, p->stream); break;
@@ -285,7 +323,7 @@ int launch_adjoint_a_sep(svconv_plan* p, const float* R, const float* G, double*
     }
     if (st) return st;
     hipLaunchKernelGGL(adjoint_a_sep_final, dim3((NM + 255) / 256), dim3(256), 0, p->stream, p->dQpart,
-                       n_wg, p->N, p->M, p->dBeta, gP, p->pedestal, ga);
+                       n_wg, p->N, p->M, p->dBeta, p->pedestal, ga);
     return hip_status(hipGetLastError(), "adjoint_a_sep_final");
 }
 

@@ -138,3 +138,22 @@ def test_separable_gauss_newton_recovers_noiseless_coefficients(svc, orc):
     say("  max |a - a*| = %.3e" % err)
     assert err <= 2e-5
     assert hist[-1][0] < 1e-3 * hist[0][0]
+
+
+@pytest.mark.parametrize("with_mask,background", [(False, False), (True, False), (False, True)])
+def test_separable_normal_matrix_vs_oracle(svc, orc, with_mask, background):
+    # basis responses from the separable row and column passes (T-only mode)
+    from tests.test_gpu_fit import small_case
+    R, C, a_star, B, (H, W, h, sig, deg, d_s) = small_case(orc)
+    mask = (synth.uniform_image(H, W, seed=11) > -0.5).astype(np.uint8) if with_mask else None
+    if background:
+        JtJ_ref, _ = orc.normal_equations_bg(R, C, h, B, d_s, mask=mask)
+    else:
+        JtJ_ref, _ = orc.normal_equations(R, None, h, B, d_s, mask=mask)
+    say("separable normal matrix", with_mask, background)
+    with svc.Plan(H, W, h, sig, deg, d_s, form="separable", pedestal=1000.0) as plan:
+        plan.set_background(background)
+        JtJ = to_host(plan.normal_matrix(to_dev(R), None if mask is None else to_dev(mask)))
+    err = np.abs(JtJ - JtJ_ref).max() / np.abs(JtJ_ref).max()
+    say("  rel err %.3e" % err)
+    assert err <= 2e-6
