@@ -404,9 +404,9 @@ def pipeline_bench(args):
     cases = [("dfb7_regrouped_fp16x3", dict(half_width=3, sigmas=None, degrees=None,
                                             spatial_degree=2, precision="fp16x3",
                                             form="regrouped")),
-             ("gauss21_basis_fp16x3", dict(half_width=10, sigmas=(0.7, 1.5, 2.0),
-                                           degrees=(6, 4, 2), spatial_degree=2,
-                                           precision="fp16x3", form="basis"))]
+             ("gauss21_separable", dict(half_width=10, sigmas=(0.7, 1.5, 2.0),
+                                        degrees=(6, 4, 2), spatial_degree=2,
+                                        precision="fp32", form="separable"))]
     for name, kw in cases:
         with svconv.Plan(H, W, pedestal=synth.SKY_LEVEL, **kw) as plan:
             a = synth.coefficients(plan.n_basis, plan.n_spatial, 0, seed=5)
@@ -427,8 +427,8 @@ def pipeline_bench(args):
 
 
 def recorded_traffic(precision, form):
-    """HBM bytes per launch of the contraction kernel from the committed
-    rocprofv3 counter summary, or None if the kernel source changed since."""
+    """HBM bytes per launch of the form's dominant kernel from the committed
+    rocprofv3 counter summary, or None if the kernel's sources changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
@@ -439,10 +439,10 @@ def recorded_traffic(precision, form):
     if not ent:
         return None
     h = hashlib.sha256()
-    for src in rec.get("sources", []):
+    for src in ent.get("sources", []):
         with open(os.path.join(ROOT, src), "rb") as f:
             h.update(f.read())
-    if h.hexdigest() != rec.get("sources_sha256"):
+    if h.hexdigest() != ent.get("sources_sha256"):
         return None
     return ent.get("traffic_bytes")
 

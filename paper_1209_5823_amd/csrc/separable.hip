@@ -40,7 +40,10 @@ constexpr int SEP_NW = SEP_WAVES;          // waves per workgroup
 constexpr int SEP_RPT = SEP_ROWS;          // output rows per thread (phase B)
 constexpr int SEP_APT = SEP_AOUT;          // row-pass outputs per task (phase A)
 constexpr int SEP_TW = 64, SEP_TH = SEP_RPT * SEP_NW;
-constexpr int SEP_CHUNK = 4;               // row factors per phase A / phase B round
+#ifndef SEP_ROUND
+#define SEP_ROUND 4
+#endif
+constexpr int SEP_CHUNK = SEP_ROUND;       // row factors per phase A / phase B round
 
 // Read-only tables (factors, coefficients, sums) are read through the
 // constant address space: every lane reads the same element, so the loads

@@ -26,14 +26,15 @@ def device_differences(plan, R, I, a):
     return [to_host(plan.difference(to_dev(r), to_dev(i), to_dev(c))) for r, i, c in zip(R, I, a)]
 
 
-@pytest.mark.parametrize("depth,pinned", [(2, True), (3, False), (1, True)])
-def test_pipeline_gaussian_basis(svc, orc, depth, pinned):
+@pytest.mark.parametrize("depth,pinned,form", [(2, True, "basis"), (3, False, "basis"),
+                                              (1, True, "basis"), (2, True, "separable")])
+def test_pipeline_gaussian_basis(svc, orc, depth, pinned, form):
     H, W = 200, 232
     n = 5
     R, I, a = tiles(n, H, W, C0.n_basis, C0.n_spatial, C0.const_basis, seed=40)
-    say("pipeline gaussian depth", depth, "pinned", pinned)
+    say("pipeline gaussian depth", depth, "pinned", pinned, form)
     with svc.Plan(H, W, C0.half_width, C0.sigmas, C0.degrees, C0.spatial_degree,
-                  pedestal=synth.SKY_LEVEL) as plan:
+                  pedestal=synth.SKY_LEVEL, form=form) as plan:
         want = device_differences(plan, R, I, a)
         if pinned:
             Rh = [svc.pinned_empty((H, W)) for _ in range(n)]

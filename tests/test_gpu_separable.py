@@ -157,3 +157,28 @@ def test_separable_normal_matrix_vs_oracle(svc, orc, with_mask, background):
     err = np.abs(JtJ - JtJ_ref).max() / np.abs(JtJ_ref).max()
     say("  rel err %.3e" % err)
     assert err <= 2e-6
+
+
+def test_separable_pcg_with_stamp_preconditioner(svc, orc):
+    # the stamp-preconditioned conjugate gradients of the OIS fit, every
+    # forward and adjoint in the separable form
+    import torch
+    from paper_1209_5823_amd.fit import stamp_preconditioned_fit
+    wl = synth.WORKLOADS["c0"]
+    R, a_star = synth.workload_inputs(wl)
+    B = orc.basis(wl.half_width, wl.sigmas, wl.degrees)
+    H, W, h, d_s = wl.height, wl.width, wl.half_width, wl.spatial_degree
+    I = synth.poisson_noise(orc.convolve(R, h, B, d_s, a_star), seed=4)
+    x_ref = orc.fit_least_squares(R, I, h, B, d_s)
+    say("separable pcg")
+    with svc.plan_for(wl, form="separable", pedestal=synth.SKY_LEVEL) as plan:
+        a0 = torch.zeros(plan._fit_coef, dtype=torch.float64).cuda()
+        a0[wl.const_basis, 0] = 1.0
+        a64, D, info = stamp_preconditioned_fit(plan, to_dev(R), to_dev(I), a0, synth.SKY_LEVEL,
+                                                500.0, iters=12, rounds=2)
+        x = to_host(a64)
+    res = info["residuals"]
+    say("  residuals " + " ".join("%.2e" % v for v in res))
+    err = np.abs(x - x_ref).max() / np.abs(x_ref).max()
+    say("  max |x - x_ref| / max |x_ref| = %.3e" % err)
+    assert err <= 1e-3
