@@ -114,20 +114,51 @@ __global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ T, 
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
     const int na = 16 * w + j;                         // A row of this lane
+    // 16 pixels per step: lane group kq takes pixels x0 + 4 kq .. x0 + 4 kq + 3
+    // (the k slot of instruction s is pixel x0 + 4 kq + s in both operands),
+    // so each lane reads 4 consecutive floats of a filter row
+    const bool vec = (W & 3) == 0;
     if (16 * w < N) {
-        for (int x0 = x_begin; x0 < x_end; x0 += 4) {
-            const int x = x0 + kq;
-            const bool ok = x < x_end;
-            const size_t pp = (size_t)row * W + x;
-            double wq = 0.0;
-            if (ok && in_mask(mask, H, W, h, x, y)) wq = ipow_f(sx * x + ox, ea);
-            const double av = (ok && na < N) ? (double)T[(size_t)na * band_px + pp] : 0.0;
+        for (int x0 = x_begin; x0 < x_end; x0 += 16) {
+            const int xb = x0 + 4 * kq;
+            const size_t pb = (size_t)row * W + xb;
+            double wq[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int x = xb + s;
+                wq[s] = (x < x_end && in_mask(mask, H, W, h, x, y)) ? ipow_f(sx * x + ox, ea) : 0.0;
+            }
+            const bool full = vec && xb + 3 < x_end;
+            float av[4] = {0.f, 0.f, 0.f, 0.f};
+            if (na < N) {
+                const float* src = T + (size_t)na * band_px + pb;
+                if (full) {
+                    const float4 v = *reinterpret_cast<const float4*>(src);
+                    av[0] = v.x; av[1] = v.y; av[2] = v.z; av[3] = v.w;
+                } else {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) av[s] = (xb + s < x_end) ? src[s] : 0.f;
+                }
+            }
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb) {
                 if (16 * cb < N) {   // uniform
                     const int nb = 16 * cb + j;
-                    const double bv = (ok && nb < N) ? (double)T[(size_t)nb * band_px + pp] * wq : 0.0;
-                    acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[cb], 0, 0, 0);
+                    float bv[4] = {0.f, 0.f, 0.f, 0.f};
+                    if (nb < N) {
+                        const float* src = T + (size_t)nb * band_px + pb;
+                        if (full) {
+                            const float4 v = *reinterpret_cast<const float4*>(src);
+                            bv[0] = v.x; bv[1] = v.y; bv[2] = v.z; bv[3] = v.w;
+                        } else {
+#pragma unroll
+                            for (int s = 0; s < 4; ++s) bv[s] = (xb + s < x_end) ? src[s] : 0.f;
+                        }
+                    }
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)av[s], (double)bv[s] * wq[s],
+                                                                        acc[cb], 0, 0, 0);
                 }
             }
         }
