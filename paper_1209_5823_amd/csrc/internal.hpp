@@ -78,6 +78,8 @@ struct SepArgs {
     const double* f1d;          // [G][kSepMaxFactors][k] factors f_e(w), w = -h..h
     const double* beta;         // [N] basis sums
     const float* coef;          // [N][M]
+    const double* coefd;        // [N][M] float64 copy of coef (written by sep_prep)
+    const double* gamma;        // [M] sum_n coef[n][m] beta[n] (written by sep_prep)
     int M, d_s;
     double sx, ox, sy, oy;
     int tiles_x, n_tiles;
@@ -154,6 +156,8 @@ int launch_contract_lowp(const ContractArgs& a, const uint16_t* frag, int nb, in
 
 // separable.hip, separable_adjoint.hip
 int launch_contract_sep(SepArgs a, hipStream_t s);
+int launch_sep_prep(const float* coef, const double* beta, int N, int M, double* coefd,
+                    double* gamma, hipStream_t s);
 int launch_adjoint_a_sep(svconv_plan* p, const float* R, const float* G, double* ga);
 bool sep_adjoint_supported(const svconv_plan* p);
 

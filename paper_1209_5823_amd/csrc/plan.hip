@@ -249,6 +249,13 @@ int run_forward(svconv_plan* p, const float* R, const float* I, const float* a, 
         sa.y_begin = 0;
         sa.n_rows = p->H;
         sa.tout = nullptr;
+        // per-call tables in the plan's vector scratch, past what the fit uses
+        double* coefd = p->dVec + 7 * (size_t)kMaxCoefficients;
+        double* gamma = p->dVec + 8 * (size_t)kMaxCoefficients;
+        int st = launch_sep_prep(a, p->dBeta, p->N, p->M, coefd, gamma, p->stream);
+        if (st) return st;
+        sa.coefd = coefd;
+        sa.gamma = gamma;
         return launch_contract_sep(sa, p->stream);
     }
     if (p->form == SVCONV_FORM_BASIS) {

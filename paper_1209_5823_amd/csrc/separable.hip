@@ -77,7 +77,7 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
 
     const cptr<double> f1d = as_const(a.f1d);
     const cptr<double> beta = as_const(a.beta);
-    const cptr<float> coef = as_const(a.coef);
+    const cptr<double> coefd = as_const(a.coefd);
     const cptr<int> fam = as_const(a.fam);
 
     const int tid = threadIdx.x;
@@ -179,25 +179,25 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
                     double cy[kMaxSpatialDegree + 1];
 #pragma unroll
                     for (int q = 0; q <= kMaxSpatialDegree; ++q) cy[q] = 0.0;
-                    const cptr<float> an = coef + (size_t)n * a.M;
+                    const cptr<double> an = coefd + (size_t)n * a.M;
                     int m = 0;
 #pragma unroll
                     for (int tt = 0; tt <= kMaxSpatialDegree; ++tt) {
                         if (tt <= d_s) {
 #pragma unroll
-                            for (int ie = tt; ie >= 0; --ie) cy[tt - ie] = fma((double)an[m + tt - ie], xpow[ie], cy[tt - ie]);
+                            for (int ie = tt; ie >= 0; --ie) cy[tt - ie] = fma(an[m + tt - ie], xpow[ie], cy[tt - ie]);
                         }
                         m += tt + 1;
                     }
-                    const double pb = (double)a.ped * beta[n];
                     // Horner in yh; the terms above d_s are zero, so the
                     // quadratic path is exact for d_s <= 2 (the uniform branch
-                    // keeps the common case short)
+                    // keeps the common case short).  The pedestal term
+                    // s beta_n c_n is summed once per pixel at the end.
                     if (d_s <= 2) {
 #pragma unroll
                         for (int o = 0; o < SEP_RPT; ++o) {
                             const double cn = fma(fma(cy[2], yh[o], cy[1]), yh[o], cy[0]);
-                            dacc[o] = fma(cn, tv[o] + pb, dacc[o]);
+                            dacc[o] = fma(cn, tv[o], dacc[o]);
                         }
                     } else {
 #pragma unroll
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
                             double cn = cy[kMaxSpatialDegree];
 #pragma unroll
                             for (int q = kMaxSpatialDegree - 1; q >= 0; --q) cn = fma(cn, yh[o], cy[q]);
-                            dacc[o] = fma(cn, tv[o] + pb, dacc[o]);
+                            dacc[o] = fma(cn, tv[o], dacc[o]);
                         }
                     }
                 }
@@ -213,16 +213,53 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
         }
     }
     if (!t_only && x < a.W) {
+        // pedestal restore: s sum_n beta_n c_n = s sum_m gamma_m P_m
+        const cptr<double> gam = as_const(a.gamma);
+        double cy[kMaxSpatialDegree + 1];
+#pragma unroll
+        for (int q = 0; q <= kMaxSpatialDegree; ++q) cy[q] = 0.0;
+        int m = 0;
+#pragma unroll
+        for (int tt = 0; tt <= kMaxSpatialDegree; ++tt) {
+            if (tt <= d_s) {
+#pragma unroll
+                for (int ie = tt; ie >= 0; --ie) cy[tt - ie] = fma(gam[m + tt - ie], xpow[ie], cy[tt - ie]);
+            }
+            m += tt + 1;
+        }
 #pragma unroll
         for (int o = 0; o < SEP_RPT; ++o) {
             const int y = Y0 + SEP_RPT * w + o;
             if (y < y_end) {
+                double pg = cy[kMaxSpatialDegree];
+#pragma unroll
+                for (int q = kMaxSpatialDegree - 1; q >= 0; --q) pg = fma(pg, yh[o], cy[q]);
                 const size_t idx = (size_t)y * a.W + x;
                 const double iv = a.I ? (double)a.I[idx] : 0.0;
-                a.out[idx] = (float)(dacc[o] - iv);
+                a.out[idx] = (float)(fma((double)a.ped, pg, dacc[o]) - iv);
             }
         }
     }
+}
+
+// Per-call tables of the separable epilogue: coef in float64 (read by scalar
+// loads without conversions) and gamma_m = sum_n coef[n][m] beta_n.
+__global__ __launch_bounds__(1024) void sep_prep_kernel(const float* __restrict__ coef,
+                                                        const double* __restrict__ beta, int N,
+                                                        int M, double* __restrict__ coefd,
+                                                        double* __restrict__ gamma) {
+    for (int i = threadIdx.x; i < N * M; i += 1024) coefd[i] = (double)coef[i];
+    if ((int)threadIdx.x < M) {
+        double g = 0.0;
+        for (int n = 0; n < N; ++n) g = fma((double)coef[n * M + threadIdx.x], beta[n], g);
+        gamma[threadIdx.x] = g;
+    }
+}
+
+int launch_sep_prep(const float* coef, const double* beta, int N, int M, double* coefd,
+                    double* gamma, hipStream_t s) {
+    hipLaunchKernelGGL(sep_prep_kernel, dim3(1), dim3(1024), 0, s, coef, beta, N, M, coefd, gamma);
+    return hip_status(hipGetLastError(), "sep_prep_kernel");
 }
 
 template <int H>
