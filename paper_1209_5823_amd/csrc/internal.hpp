@@ -160,6 +160,7 @@ int launch_sep_prep(const float* coef, const double* beta, int N, int M, double*
                     double* gamma, hipStream_t s);
 int launch_adjoint_a_sep(svconv_plan* p, const float* R, const float* G, double* ga);
 bool sep_adjoint_supported(const svconv_plan* p);
+int launch_adjoint_r_sep(svconv_plan* p, const float* a32, const float* G, float* gR);
 
 // plan.hip
 int run_forward(svconv_plan* p, const float* R, const float* I, const float* a, float* out);

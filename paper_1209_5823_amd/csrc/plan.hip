@@ -472,7 +472,11 @@ int svconv_backward(svconv_plan* p, const float* R, const float* a, const float*
         return fail(SVCONV_EINVAL, "gR aliases R or gD");
     if (p->M > 32) return fail(SVCONV_EUNSUPPORTED, "adjoint in R needs M <= 32");
     int st = SVCONV_OK;
-    if (gR) {
+    if (gR && p->form == SVCONV_FORM_SEPARABLE) {
+        // through the separable factors (E_n = c_n gD correlated with B_n)
+        st = launch_adjoint_r_sep(p, a, gD, gR);
+        if (st) return st;
+    } else if (gR) {
         ContractArgs c{};
         c.X = gD;
         c.H = p->H;

@@ -49,6 +49,11 @@ struct SepAdjArgs {
 template <class T>
 using acptr = const __attribute__((address_space(4))) T*;
 
+__device__ __forceinline__ int sep_xcd_remap_r(int bid, int n) {
+    const int x8 = bid & 7, tt = bid >> 3, q8 = n >> 3, r8 = n & 7;
+    return x8 * q8 + (x8 < r8 ? x8 : r8) + tt;
+}
+
 template <int H>
 __global__ __launch_bounds__(64 * SA_NW) void adjoint_a_sep_kernel(SepAdjArgs a) {
     constexpr int NT = 64 * SA_NW;
@@ -325,6 +330,212 @@ int launch_adjoint_a_sep(svconv_plan* p, const float* R, const float* G, double*
     hipLaunchKernelGGL(adjoint_a_sep_final, dim3((NM + 255) / 256), dim3(256), 0, p->stream, p->dQpart,
                        n_wg, p->N, p->M, p->dBeta, p->pedestal, ga);
     return hip_status(hipGetLastError(), "adjoint_a_sep_final");
+}
+
+}  // namespace svc
+
+// ------------------------------------------------------- adjoint in R ----
+//
+//   dL/dR(q) = sum_n sum_{u,v} B_n[u,v] E_n(q + (u,v)),   E_n = c_n G,
+//
+// and with B_n = f_i(u) f_j(v) the inner sums group by row factor:
+//   CE_i(x', y) = sum_j sum_v f_j(v) E_{ij}(x', y + v)       (column pass per basis)
+//   dL/dR(x, y) += sum_u f_i(u) CE_i(x + u, y)              (row pass per factor).
+// A workgroup owns a 64 x 64 output tile.  For every basis it forms E_n on the
+// tile and its halo in LDS (c_n from per-column coefficients in xh and Horner
+// in yh), then column tasks (one staged column, 8 output rows) accumulate
+// CE_i in registers over the bases of the row factor; CE_i goes to LDS and
+// each thread adds the row pass to its 8 output pixels.  E and CE are held
+// in float32 between passes, every sum in float64.
+
+namespace svc {
+
+constexpr int SR_NT = 512, SR_TW = 64, SR_TH = 64, SR_RPT = 8;
+
+struct SepRArgs {
+    const float* G;
+    float* gR;
+    int H, W;
+    int G_fam;
+    const int* fam;
+    const double* f1d;
+    const double* coefd;        // [N][M] float64 coefficients
+    int M, d_s;
+    double sx, ox, sy, oy;
+    int tiles_x, n_tiles;
+};
+
+template <int H>
+__global__ __launch_bounds__(SR_NT) void adjoint_r_sep_kernel(SepRArgs a) {
+    constexpr int K = 2 * H + 1;
+    constexpr int RA = SR_TH + 2 * H, CA = SR_TW + 2 * H, CP = CA | 1;
+    constexpr int WB = SR_RPT + 2 * H;                  // window of a column task / row task
+    constexpr int NTASK = CA * (SR_TH / SR_RPT);        // column tasks
+    constexpr int TPT = (NTASK + SR_NT - 1) / SR_NT;    // column tasks per thread
+    constexpr int DSM = kMaxSpatialDegree + 1;
+    extern __shared__ double sr_lds[];
+    double* cyt = sr_lds;                               // [CA][DSM] coefficients in yh per column
+    float* gt = reinterpret_cast<float*>(cyt + CA * DSM);   // [RA][CP] G tile
+    float* en = gt + RA * CP;                           // [RA][CP] E_n tile
+    float* ce = en + RA * CP;                           // [SR_TH][CP] CE_i
+
+    const acptr<double> f1d = (acptr<double>)a.f1d;
+    const acptr<int> fam = (acptr<int>)a.fam;
+    const acptr<double> coefd = (acptr<double>)a.coefd;
+    const int tid = threadIdx.x;
+    const int t = sep_xcd_remap_r(blockIdx.x, a.n_tiles);
+    const int X0 = (t % a.tiles_x) * SR_TW, Y0 = (t / a.tiles_x) * SR_TH;
+    const int DS1 = a.d_s + 1;
+
+    for (int q = tid; q < RA * CA; q += SR_NT) {
+        const int r = q / CA, c = q - r * CA;
+        const int gy = Y0 - H + r, gx = X0 - H + c;
+        gt[r * CP + c] = (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) ? a.G[(size_t)gy * a.W + gx] : 0.f;
+    }
+    // row-pass role: output row rr, columns q8 .. q8 + 7
+    const int rr = tid >> 3, q8 = (tid & 7) * SR_RPT;
+    double gacc[SR_RPT];
+#pragma unroll
+    for (int o = 0; o < SR_RPT; ++o) gacc[o] = 0.0;
+
+    for (int g = 0; g < a.G_fam; ++g) {
+        const int deg = fam[2 * g], base = fam[2 * g + 1];
+        const acptr<double> fg = f1d + (size_t)g * kSepMaxFactors * K;
+        for (int i = 0; i <= deg; ++i) {
+            double cacc[TPT][SR_RPT];
+#pragma unroll
+            for (int tk = 0; tk < TPT; ++tk)
+#pragma unroll
+                for (int o = 0; o < SR_RPT; ++o) cacc[tk][o] = 0.0;
+            for (int j = 0; j + i <= deg; ++j) {
+                const int n = base + (i + j) * (i + j + 1) / 2 + j;
+                const acptr<double> an = coefd + (size_t)n * a.M;
+                __syncthreads();   // previous E_n / cyt consumed (and G staged)
+                // coefficients of c_n in yh for every staged column
+                for (int e = tid; e < CA * DS1; e += SR_NT) {
+                    const int c = e / DS1, jj = e - c * DS1;
+                    const double xh = a.sx * (X0 - H + c) + a.ox;
+                    double s = 0.0, xp = 1.0;
+                    for (int ie = 0; ie + jj <= a.d_s; ++ie) {
+                        const int tt = ie + jj;
+                        s = fma(an[tt * (tt + 1) / 2 + jj], xp, s);
+                        xp *= xh;
+                    }
+                    cyt[c * DSM + jj] = s;
+                }
+                __syncthreads();
+                // E_n = c_n G on the staged region
+                for (int q = tid; q < RA * CA; q += SR_NT) {
+                    const int r = q / CA, c = q - r * CA;
+                    const double yh = a.sy * (Y0 - H + r) + a.oy;
+                    double cn = 0.0;
+                    for (int jj = a.d_s; jj >= 0; --jj) cn = fma(cn, yh, cyt[c * DSM + jj]);
+                    en[r * CP + c] = (float)(cn * (double)gt[r * CP + c]);
+                }
+                __syncthreads();
+                // column correlation with f_j, accumulated over j
+                const acptr<double> f = fg + (size_t)j * K;
+#pragma unroll
+                for (int tk = 0; tk < TPT; ++tk) {
+                    const int task = tid + tk * SR_NT;
+                    if (task < NTASK) {
+                        const int c = task % CA, r0 = (task / CA) * SR_RPT;
+                        double win[WB];
+#pragma unroll
+                        for (int s = 0; s < WB; ++s) win[s] = (double)en[(r0 + s) * CP + c];
+#pragma unroll
+                        for (int v = 0; v < K; ++v) {
+                            const double fv = f[v];
+#pragma unroll
+                            for (int o = 0; o < SR_RPT; ++o) cacc[tk][o] = fma(fv, win[o + v], cacc[tk][o]);
+                        }
+                    }
+                }
+            }
+            // CE_i to LDS, then the row correlation with f_i
+#pragma unroll
+            for (int tk = 0; tk < TPT; ++tk) {
+                const int task = tid + tk * SR_NT;
+                if (task < NTASK) {
+                    const int c = task % CA, r0 = (task / CA) * SR_RPT;
+#pragma unroll
+                    for (int o = 0; o < SR_RPT; ++o) ce[(r0 + o) * CP + c] = (float)cacc[tk][o];
+                }
+            }
+            __syncthreads();
+            {
+                const acptr<double> f = fg + (size_t)i * K;
+                double win[WB];
+#pragma unroll
+                for (int s = 0; s < WB; ++s) win[s] = (double)ce[rr * CP + q8 + s];
+#pragma unroll
+                for (int u = 0; u < K; ++u) {
+                    const double fu = f[u];
+#pragma unroll
+                    for (int o = 0; o < SR_RPT; ++o) gacc[o] = fma(fu, win[o + u], gacc[o]);
+                }
+            }
+        }
+    }
+    const int y = Y0 + rr;
+    if (y < a.H) {
+#pragma unroll
+        for (int o = 0; o < SR_RPT; ++o) {
+            const int x = X0 + q8 + o;
+            if (x < a.W) a.gR[(size_t)y * a.W + x] = (float)gacc[o];
+        }
+    }
+}
+
+template <int H>
+static int launch_rsep_t(const SepRArgs& a, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL(adjoint_r_sep_kernel<H>, dim3(a.n_tiles), dim3(SR_NT), lds, s, a);
+    return hip_status(hipGetLastError(), "adjoint_r_sep_kernel");
+}
+
+int launch_adjoint_r_sep(svconv_plan* p, const float* a32, const float* G, float* gR) {
+    if (!p->dSep1d || p->h < 1 || p->h > 15)
+        return fail(SVCONV_EUNSUPPORTED, "separable adjoint needs Gaussian bases and 1 <= half-width <= 15");
+    const int h = p->h;
+    double* coefd = p->dVec + 7 * (size_t)kMaxCoefficients;
+    double* gamma = p->dVec + 8 * (size_t)kMaxCoefficients;
+    int st = launch_sep_prep(a32, p->dBeta, p->N, p->M, coefd, gamma, p->stream);
+    if (st) return st;
+    SepRArgs a{};
+    a.G = G;
+    a.gR = gR;
+    a.H = p->H;
+    a.W = p->W;
+    a.G_fam = (int)p->sigmas.size();
+    a.fam = p->dSepFam;
+    a.f1d = p->dSep1d;
+    a.coefd = coefd;
+    a.M = p->M;
+    a.d_s = p->d_s;
+    if (p->Wf > 1) { a.sx = 2.0 / (p->Wf - 1); a.ox = a.sx * p->x0 - 1.0; }
+    if (p->Hf > 1) { a.sy = 2.0 / (p->Hf - 1); a.oy = a.sy * p->y0 - 1.0; }
+    a.tiles_x = (p->W + SR_TW - 1) / SR_TW;
+    a.n_tiles = a.tiles_x * ((p->H + SR_TH - 1) / SR_TH);
+    const int RA = SR_TH + 2 * h, CA = SR_TW + 2 * h, CP = CA | 1;
+    const size_t lds = (size_t)CA * (kMaxSpatialDegree + 1) * sizeof(double) +
+                       ((size_t)2 * RA * CP + (size_t)SR_TH * CP) * sizeof(float);
+    switch (h) {
+        case 1: return launch_rsep_t<1>(a, lds, p->stream);
+        case 2: return launch_rsep_t<2>(a, lds, p->stream);
+        case 3: return launch_rsep_t<3>(a, lds, p->stream);
+        case 4: return launch_rsep_t<4>(a, lds, p->stream);
+        case 5: return launch_rsep_t<5>(a, lds, p->stream);
+        case 6: return launch_rsep_t<6>(a, lds, p->stream);
+        case 7: return launch_rsep_t<7>(a, lds, p->stream);
+        case 8: return launch_rsep_t<8>(a, lds, p->stream);
+        case 9: return launch_rsep_t<9>(a, lds, p->stream);
+        case 10: return launch_rsep_t<10>(a, lds, p->stream);
+        case 11: return launch_rsep_t<11>(a, lds, p->stream);
+        case 12: return launch_rsep_t<12>(a, lds, p->stream);
+        case 13: return launch_rsep_t<13>(a, lds, p->stream);
+        case 14: return launch_rsep_t<14>(a, lds, p->stream);
+        default: return launch_rsep_t<15>(a, lds, p->stream);
+    }
 }
 
 }  // namespace svc

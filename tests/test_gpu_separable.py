@@ -182,3 +182,66 @@ def test_separable_pcg_with_stamp_preconditioner(svc, orc):
     err = np.abs(x - x_ref).max() / np.abs(x_ref).max()
     say("  max |x - x_ref| / max |x_ref| = %.3e" % err)
     assert err <= 1e-3
+
+
+# ----------------------------------------------- adjoint in R, separable ----
+
+@pytest.mark.parametrize("pedestal", [0.0, 1000.0])
+def test_separable_adjoint_R_vs_oracle_c3_crop(svc, orc, pedestal):
+    from tests.test_gpu_backward import crop_case, REL, C3
+    R, I, a, B, frame = crop_case(orc, C3)
+    h, d_s = C3.half_width, C3.spatial_degree
+    D = orc.difference(R, I, h, B, d_s, a, frame=frame)
+    G = (2.0 * D * orc.interior_mask(*R.shape, h)).astype(np.float32)
+    gR_ref = orc.grad_R(R.shape, h, B, d_s, a, G, frame=frame)
+    sR = orc.grad_R(R.shape, h, np.abs(B), 0, np.abs(a).sum(axis=1, keepdims=True), np.abs(G),
+                    frame=frame)
+    say("separable adjoint in R, c3 crop, pedestal", pedestal)
+    with svc.Plan(R.shape[0], R.shape[1], h, C3.sigmas, C3.degrees, d_s, form="separable",
+                  frame=frame, pedestal=pedestal) as plan:
+        gR, ga = plan.backward(to_dev(R), to_dev(a), to_dev(G))
+        gR = to_host(gR)
+    e = np.abs(gR - gR_ref)
+    say("  max err %.3e (scale %.3e)" % (e.max(), sR.max()))
+    assert np.all(e <= REL * sR + 1e-6)
+
+
+@pytest.mark.parametrize("name", ["h1_ragged", "nb3_degree3", "max_filters_64",
+                                  "max_spatial_degree_6", "single_column", "single_row",
+                                  "all_border_8x8", "c1_kernel_ragged_crop"])
+def test_separable_adjoint_R_edge_cases(svc, orc, name):
+    case = EDGE_CASES[name]
+    H, W, h, sig, deg, d_s, frame = case
+    R, I, a = _edge_inputs(name, case)
+    G = synth.uniform_image(H, W, seed=19, lo=-40.0, hi=40.0)
+    B = orc.basis(h, sig, deg)
+    gR_ref = orc.grad_R((H, W), h, B, d_s, a, G, frame=frame)
+    sR = orc.grad_R((H, W), h, np.abs(B), 0, np.abs(a).sum(axis=1, keepdims=True), np.abs(G),
+                    frame=frame)
+    say("separable adjoint in R, edge", name)
+    with svc.Plan(H, W, h, sig, deg, d_s, form="separable", frame=frame) as plan:
+        gR, _ = plan.backward(to_dev(R), to_dev(a), to_dev(G), want_ga=False)
+        gR = to_host(gR)
+    e = np.abs(gR - gR_ref)
+    say("  max err %.3e" % e.max())
+    assert np.all(e <= 2e-5 * sR + 1e-6)
+
+
+def test_separable_autograd_matches_dense_form(svc, orc):
+    # the torch.autograd.Function on a separable plan gives the same
+    # gradients as on the dense matrix-core plan, to float32 rounding
+    import torch
+    from tests.test_gpu_backward import crop_case, C3
+    R, I, a, B, frame = crop_case(orc, C3, size=128)
+    grads = {}
+    for form in ("basis", "separable"):
+        with svc.Plan(128, 128, C3.half_width, C3.sigmas, C3.degrees, C3.spatial_degree,
+                      form=form, frame=frame) as plan:
+            Rt = to_dev(R).requires_grad_(True)
+            at = to_dev(a).requires_grad_(True)
+            D = svc.difference(plan, Rt, to_dev(I), at)
+            (D.double() ** 2).sum().backward()
+            grads[form] = (to_host(Rt.grad), to_host(at.grad))
+    for k in range(2):
+        g0, g1 = grads["basis"][k], grads["separable"][k]
+        assert np.abs(g1 - g0).max() <= 1e-4 * np.abs(g0).max()
