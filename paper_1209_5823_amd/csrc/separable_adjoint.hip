@@ -343,7 +343,7 @@ int launch_adjoint_a_sep(svconv_plan* p, const float* R, const float* G, double*
 //   dL/dR(x, y) += sum_u f_i(u) CE_i(x + u, y)              (row pass per factor).
 // A workgroup owns a 64 x 64 output tile.  For every basis it forms E_n on the
 // tile and its halo in LDS (c_n from per-column coefficients in xh and Horner
-// in yh), then column tasks (one staged column, 8 output rows) accumulate
+// in yh, G read from global memory), then column tasks (one staged column, 8 output rows) accumulate
 // CE_i in registers over the bases of the row factor; CE_i goes to LDS and
 // each thread adds the row pass to its 8 output pixels.  E and CE are held
 // in float32 between passes, every sum in float64.
@@ -365,8 +365,18 @@ struct SepRArgs {
     int tiles_x, n_tiles;
 };
 
+// G is read from global memory (L2) while E_n is formed, not staged in LDS:
+// the LDS left then holds two workgroups per CU, and the register budget is
+// held to 4 waves per SIMD; this was faster than an LDS copy of G at one
+// workgroup per CU.
+#ifndef SR_GLOBAL_G
+#define SR_GLOBAL_G 1
+#endif
+#ifndef SR_WG_PER_CU
+#define SR_WG_PER_CU 4          // minimum waves per SIMD (launch bounds)
+#endif
 template <int H>
-__global__ __launch_bounds__(SR_NT) void adjoint_r_sep_kernel(SepRArgs a) {
+__global__ __launch_bounds__(SR_NT, SR_WG_PER_CU) void adjoint_r_sep_kernel(SepRArgs a) {
     constexpr int K = 2 * H + 1;
     constexpr int RA = SR_TH + 2 * H, CA = SR_TW + 2 * H, CP = CA | 1;
     constexpr int WB = SR_RPT + 2 * H;                  // window of a column task / row task
@@ -376,7 +386,7 @@ __global__ __launch_bounds__(SR_NT) void adjoint_r_sep_kernel(SepRArgs a) {
     extern __shared__ double sr_lds[];
     double* cyt = sr_lds;                               // [CA][DSM] coefficients in yh per column
     float* gt = reinterpret_cast<float*>(cyt + CA * DSM);   // [RA][CP] G tile
-    float* en = gt + RA * CP;                           // [RA][CP] E_n tile
+    float* en = gt + (SR_GLOBAL_G ? 0 : RA * CP);       // [RA][CP] E_n tile
     float* ce = en + RA * CP;                           // [SR_TH][CP] CE_i
 
     const acptr<double> f1d = (acptr<double>)a.f1d;
@@ -387,11 +397,12 @@ __global__ __launch_bounds__(SR_NT) void adjoint_r_sep_kernel(SepRArgs a) {
     const int X0 = (t % a.tiles_x) * SR_TW, Y0 = (t / a.tiles_x) * SR_TH;
     const int DS1 = a.d_s + 1;
 
-    for (int q = tid; q < RA * CA; q += SR_NT) {
-        const int r = q / CA, c = q - r * CA;
-        const int gy = Y0 - H + r, gx = X0 - H + c;
-        gt[r * CP + c] = (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) ? a.G[(size_t)gy * a.W + gx] : 0.f;
-    }
+    if (!SR_GLOBAL_G)
+        for (int q = tid; q < RA * CA; q += SR_NT) {
+            const int r = q / CA, c = q - r * CA;
+            const int gy = Y0 - H + r, gx = X0 - H + c;
+            gt[r * CP + c] = (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) ? a.G[(size_t)gy * a.W + gx] : 0.f;
+        }
     // row-pass role: output row rr, columns q8 .. q8 + 7
     const int rr = tid >> 3, q8 = (tid & 7) * SR_RPT;
     double gacc[SR_RPT];
@@ -430,7 +441,14 @@ __global__ __launch_bounds__(SR_NT) void adjoint_r_sep_kernel(SepRArgs a) {
                     const double yh = a.sy * (Y0 - H + r) + a.oy;
                     double cn = 0.0;
                     for (int jj = a.d_s; jj >= 0; --jj) cn = fma(cn, yh, cyt[c * DSM + jj]);
-                    en[r * CP + c] = (float)(cn * (double)gt[r * CP + c]);
+                    float gv;
+                    if (SR_GLOBAL_G) {
+                        const int gy = Y0 - H + r, gx = X0 - H + c;
+                        gv = (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) ? a.G[(size_t)gy * a.W + gx] : 0.f;
+                    } else {
+                        gv = gt[r * CP + c];
+                    }
+                    en[r * CP + c] = (float)(cn * (double)gv);
                 }
                 __syncthreads();
                 // column correlation with f_j, accumulated over j
@@ -518,7 +536,7 @@ int launch_adjoint_r_sep(svconv_plan* p, const float* a32, const float* G, float
     a.n_tiles = a.tiles_x * ((p->H + SR_TH - 1) / SR_TH);
     const int RA = SR_TH + 2 * h, CA = SR_TW + 2 * h, CP = CA | 1;
     const size_t lds = (size_t)CA * (kMaxSpatialDegree + 1) * sizeof(double) +
-                       ((size_t)2 * RA * CP + (size_t)SR_TH * CP) * sizeof(float);
+                       ((size_t)(SR_GLOBAL_G ? 1 : 2) * RA * CP + (size_t)SR_TH * CP) * sizeof(float);
     switch (h) {
         case 1: return launch_rsep_t<1>(a, lds, p->stream);
         case 2: return launch_rsep_t<2>(a, lds, p->stream);
