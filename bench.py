@@ -48,15 +48,15 @@ def time_form(plan, args, R, I, a, D, precision, form):
         log("  %s/%s: %s" % (form, precision, e))
         return None
     torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    start.record()
-    for _ in range(args.steps):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev[0].record()
+    for k in range(args.steps):
         plan.difference(R, I, a, out=D)
-    end.record()
+        ev[k + 1].record()
     torch.cuda.synchronize()
-    ms = start.elapsed_time(end) / args.steps
-    return ms
+    per = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps))
+    time_form.last = {"median_ms": per[len(per) // 2], "min_ms": per[0]}
+    return ev[0].elapsed_time(ev[-1]) / args.steps
 
 
 def main():
@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the forward + adjoint timing on the 4096 x 4096 workload")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the size sweep of the chip workload's kernel and basis")
     ap.add_argument("--no-dfb", action="store_true",
                     help="skip the Dirac delta basis size sweep")
     ap.add_argument("--no-pipeline", action="store_true",
@@ -127,7 +129,7 @@ def main():
                 torch.cuda.synchronize()
                 outputs[(form, prec)] = D.cpu().numpy()
                 mpix = wl.height * wl.width / (ms * 1e-3) / 1e6
-                results[(form, prec)] = dict(ms=ms, mpix=mpix)
+                results[(form, prec)] = dict(ms=ms, mpix=mpix, **time_form.last)
                 log("  %-9s %-7s %8.3f ms  %10.1f Mpix/s" % (form, prec, ms, mpix))
         plan.close()
 
@@ -187,11 +189,12 @@ def main():
         log("  adjoint: %s" % adjoint)
 
     dfb = None if args.no_dfb else dfb_sweep(args, stream)
+    sweep = None if args.no_sweep else gauss_sweep(args, stream, wl)
     pipeline = None if args.no_pipeline else pipeline_bench(args)
 
     # CPU baseline: the FP64 oracle on a bounded random sample of pixels; its
     # values also give the error of every form on that sample.
-    cpu = None
+    cpu = cpu1 = None
     if not args.no_cpu:
         from oracle import oracle
         B = oracle.basis(wl.half_width, wl.sigmas, wl.degrees)
@@ -224,6 +227,15 @@ def main():
                "sample": "%d random pixels + 256 brightest of the %dx%d frame, per-pixel "
                          "kernel and direct convolution in float64 (%.1f s)"
                          % (len(xs) - 256, wl.height, wl.width, dt)}
+        # one thread: the analogue of the paper's single-thread ANSI-C baseline
+        n1 = max(2000, len(xs) // (4 * max(1, oracle.max_threads())))
+        t0 = time.perf_counter()
+        oracle.convolve_at(R_h, wl.half_width, B, wl.spatial_degree, a_h, xs[:n1], ys[:n1], nthreads=1)
+        dt1 = time.perf_counter() - t0
+        cpu1 = {"value": n1 / dt1 / 1e6, "unit": "Mpix/s", "cores": 1, "kind": "oracle",
+                "sample": "%d of the same pixels, one thread (%.1f s)" % (n1, dt1)}
+        log("cpu baseline: %.2f Mpix/s on %d threads, %.3f Mpix/s on one"
+            % (cpu["value"], cpu["cores"], cpu1["value"]))
 
     # headline: the fastest form within 1e-2 sigma_sky (every form computes D
     # of Eq. 1 exactly up to rounding); the fastest form within the FP32
@@ -289,9 +301,23 @@ def main():
         "roofline": {"bound": "alu" if form == "separable" else "mfma",
                      "achieved": round(achieved, 3), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
-                     "flop_per_pixel": per_px, "pixels_per_launch": px},
+                     "flop_per_pixel": per_px, "pixels_per_launch": px,
+                     "traffic_gbs": (round(traffic / (hr["ms"] * 1e-3) / 1e9, 1)
+                                     if traffic else None),
+                     "hbm_peak_gbs": 8000.0,
+                     "paper_flop_per_pixel": flops.paper_flops_gfb(N, k),
+                     "paper_model_tflops": round(flops.paper_flops_gfb(N, k) * px
+                                                 / (hr["ms"] * 1e-3) / 1e12, 3)},
         "cpu_baseline": cpu,
+        "timing": {"mean_ms": round(hr["ms"], 4), "median_ms": round(hr["median_ms"], 4),
+                   "min_ms": round(hr["min_ms"], 4)},
     }
+    if cpu is not None:
+        out["cpu_single_core"] = cpu1
+        out["speedup"] = {"vs_oracle_all_threads": round(hr["mpix"] / cpu["value"], 1),
+                          "vs_oracle_one_thread": round(hr["mpix"] / cpu1["value"], 1),
+                          "paper": "about 50x over single-thread ANSI-C (GTX465 against "
+                                   "Athlon II X3, delta basis; context only)"}
     fp = best(1e-4)
     if fp is not None:
         out["fp32_path"] = summary(fp)
@@ -305,6 +331,8 @@ def main():
         out["regrouped"] = summary(rg)
     if adjoint is not None:
         out["adjoint"] = adjoint
+    if sweep is not None:
+        out["size_sweep"] = sweep
     if dfb is not None:
         out["dfb"] = dfb
     if pipeline is not None:
@@ -312,6 +340,48 @@ def main():
     out["forms"] = {"%s/%s" % k_: {kk: (round(v, 6) if isinstance(v, float) else v)
                                    for kk, v in r.items()} for k_, r in results.items()}
     print(json.dumps(out), flush=True)
+
+
+SWEEP_FORMS = (("separable", "fp32"), ("basis", "fp16x3"), ("regrouped", "fp16x3"))
+
+
+def gauss_sweep(args, stream, wl):
+    """Mpix/s against image size with the chip workload's kernel and basis
+    (21 x 21, 49 Gaussian bases, spatial degree 2), sizes from 256 x 256 to
+    one 4846 x 4868 camera tile (the x-axis of the paper's size study,
+    Sec. 5): top-left crops of one tile-sized star field with the chip's star
+    density and FWHM ramp."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1209_5823_amd import svconv
+
+    Ht, Wt = DFB_SIZES[-1]
+    n_stars = int(round(wl.n_stars * Ht * Wt / (wl.height * wl.width)))
+    log("inputs: size sweep %dx%d, %d stars" % (Ht, Wt, n_stars))
+    tile = synth.star_field(Ht, Wt, n_stars, wl.fwhm, seed=12)
+    _, a_h = synth.workload_inputs(wl)
+    rows = []
+    with torch.cuda.stream(stream):
+        a = torch.from_numpy(a_h).cuda()
+        for (H, W) in DFB_SIZES:
+            R = torch.from_numpy(np.ascontiguousarray(tile[:H, :W])).cuda()
+            I = R.clone()
+            D = torch.empty_like(R)
+            row = {"height": H, "width": W}
+            with svconv.Plan(H, W, wl.half_width, wl.sigmas, wl.degrees, wl.spatial_degree,
+                             pedestal=synth.SKY_LEVEL) as plan:
+                for form, prec in SWEEP_FORMS:
+                    ms = time_form(plan, args, R, I, a, D, prec, form)
+                    if ms is None:
+                        continue
+                    label = "%s/%s" % (form, "f64" if form == "separable" else prec)
+                    row[label] = {"ms": round(ms, 4), "mpix": round(H * W / (ms * 1e-3) / 1e6, 1)}
+            log("  sweep %5dx%-5d %s" % (H, W, "  ".join("%s %.0f" % (k, v["mpix"]) for k, v in row.items()
+                                                      if isinstance(v, dict))))
+            rows.append(row)
+    return {"kernel": wl.k, "n_basis": wl.n_basis, "spatial_degree": wl.spatial_degree, "sizes": rows}
 
 
 DFB_SIZES = ((256, 256), (512, 512), (1024, 1024), (2048, 2048), (4096, 4096), (4846, 4868))
