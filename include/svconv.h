@@ -82,7 +82,12 @@ enum svconv_form { SVCONV_FORM_BASIS = 0, SVCONV_FORM_REGROUPED = 1, SVCONV_FORM
  * product is the product of the norms), so T_n = f_j (x)_y (f_i (x)_x R): a
  * row pass per factor f_i of a family, then a column pass per basis, in
  * float64 arithmetic with the row responses held in float32; the precision
- * setting does not apply.  EUNSUPPORTED for delta-basis plans. */
+ * setting does not apply.  In this form svconv_backward, svconv_normal_matrix,
+ * svconv_gn_step and svconv_pcg_fit also go through the factors (the adjoint
+ * in a falls back to the matrix-core product when its per-round moments do
+ * not fit in LDS).  The adjoint in a sums with LDS atomics, so repeated calls
+ * agree to float64 rounding rather than bit for bit.  EUNSUPPORTED for
+ * delta-basis plans. */
 
 /*
  * Create a plan for images of height x width with a (2 half_width + 1)^2
