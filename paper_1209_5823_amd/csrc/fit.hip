@@ -390,9 +390,133 @@ __global__ __launch_bounds__(1024) void cholesky_kernel(double* __restrict__ A, 
     if (tid == 0) status[0] = bad;
 }
 
+// Blocked right-looking factorisation for larger matrices: for each block
+// column k0 of width CH_NB, one workgroup factors the diagonal block in LDS
+// and solves the panel below it (L21 = A21 L11^-T), then one workgroup per
+// 32 x 32 tile of the trailing lower triangle applies A22 -= L21 L21^T.
+constexpr int CH_NB = 32;
+
+__global__ __launch_bounds__(256) void chol_panel_kernel(double* __restrict__ A, int n, int k0,
+                                                         int* __restrict__ status) {
+    __shared__ double L[CH_NB][CH_NB + 1];
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    const int nb = min(CH_NB, n - k0);
+    for (int q = tid; q < nb * nb; q += 256) {
+        const int r = q / nb, c = q - r * nb;
+        L[r][c] = A[(size_t)(k0 + r) * n + k0 + c];
+    }
+    if (tid == 0) bad = status[0];
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+        if (tid == 0) {
+            double d = L[j][j];
+            if (!(d > 0.0) || !isfinite(d)) {
+                if (!bad) bad = k0 + j + 1;
+                d = 1.0;
+            }
+            L[j][j] = sqrt(d);
+        }
+        __syncthreads();
+        const double inv = 1.0 / L[j][j];
+        for (int i = j + 1 + tid; i < nb; i += 256) L[i][j] *= inv;
+        __syncthreads();
+        const int m = nb - j - 1;
+        for (int q = tid; q < m * m; q += 256) {
+            const int i = j + 1 + q / m, c = j + 1 + q % m;
+            if (c <= i) L[i][c] -= L[i][j] * L[c][j];
+        }
+        __syncthreads();
+    }
+    for (int q = tid; q < nb * nb; q += 256) {
+        const int r = q / nb, c = q - r * nb;
+        A[(size_t)(k0 + r) * n + k0 + c] = (c <= r) ? L[r][c] : 0.0;
+    }
+    // panel rows below: x L11^T = a, forward substitution over the block's columns
+    for (int i = k0 + nb + tid; i < n; i += 256) {
+        double x[CH_NB];
+        double* row = A + (size_t)i * n + k0;
+#pragma unroll
+        for (int c = 0; c < CH_NB; ++c) {
+            if (c < nb) {
+                double s = row[c];
+#pragma unroll
+                for (int t = 0; t < c; ++t) s -= x[t] * L[c][t];
+                x[c] = s / L[c][c];
+                row[c] = x[c];
+            }
+        }
+    }
+    if (tid == 0) status[0] = bad;
+}
+
+// A22 -= L21 L21^T on the lower triangle; block b is tile (ti, tj), tj <= ti
+__global__ __launch_bounds__(256) void chol_update_kernel(double* __restrict__ A, int n, int k0,
+                                                          int nb) {
+    __shared__ double Li[CH_NB][CH_NB + 1], Lj[CH_NB][CH_NB + 1];
+    const int b = blockIdx.x;
+    int ti = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+    while (ti * (ti + 1) / 2 > b) --ti;
+    while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
+    const int tj = b - ti * (ti + 1) / 2;
+    const int k1 = k0 + nb;
+    const int r0 = k1 + 32 * ti, c0 = k1 + 32 * tj;
+    const int tid = threadIdx.x;
+    for (int q = tid; q < 32 * nb; q += 256) {
+        const int r = q / nb, c = q - r * nb;
+        Li[r][c] = (r0 + r < n) ? A[(size_t)(r0 + r) * n + k0 + c] : 0.0;
+        Lj[r][c] = (c0 + r < n) ? A[(size_t)(c0 + r) * n + k0 + c] : 0.0;
+    }
+    __syncthreads();
+    const int cc = tid & 31, rb = tid >> 5;     // column, first of 4 rows (stride 8)
+    for (int rr = rb; rr < 32; rr += 8) {
+        const int gi = r0 + rr, gj = c0 + cc;
+        if (gi < n && gj < n && gj <= gi) {
+            double s = 0.0;
+            for (int t = 0; t < nb; ++t) s = fma(Li[rr][t], Lj[cc][t], s);
+            A[(size_t)gi * n + gj] -= s;
+        }
+    }
+}
+
+__global__ void chol_zero_upper(double* __restrict__ A, int n) {
+    const size_t total = (size_t)n * n;
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+         q += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(q / n), c = (int)(q % n);
+        if (c > i) A[q] = 0.0;
+    }
+}
+
+__global__ void chol_status_clear(int* status) {
+    if (threadIdx.x == 0) status[0] = 0;
+}
+
 int launch_cholesky(svconv_plan* p, double* A, int n) {
-    hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(1024), 0, p->stream, A, n, p->dStatus);
-    int st = hip_status(hipGetLastError(), "cholesky_kernel");
+    int st = SVCONV_OK;
+    if (n <= 64) {
+        hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(1024), 0, p->stream, A, n, p->dStatus);
+        st = hip_status(hipGetLastError(), "cholesky_kernel");
+    } else {
+        hipLaunchKernelGGL(chol_status_clear, dim3(1), dim3(64), 0, p->stream, p->dStatus);
+        st = hip_status(hipGetLastError(), "chol_status_clear");
+        for (int k0 = 0; k0 < n && !st; k0 += CH_NB) {
+            const int nb = (n - k0) < CH_NB ? (n - k0) : CH_NB;
+            hipLaunchKernelGGL(chol_panel_kernel, dim3(1), dim3(256), 0, p->stream, A, n, k0, p->dStatus);
+            st = hip_status(hipGetLastError(), "chol_panel_kernel");
+            const int rest = n - k0 - nb;
+            if (!st && rest > 0) {
+                const int nt = (rest + 31) / 32;
+                hipLaunchKernelGGL(chol_update_kernel, dim3(nt * (nt + 1) / 2), dim3(256), 0, p->stream,
+                                   A, n, k0, nb);
+                st = hip_status(hipGetLastError(), "chol_update_kernel");
+            }
+        }
+        if (!st) {
+            hipLaunchKernelGGL(chol_zero_upper, dim3(256), dim3(256), 0, p->stream, A, n);
+            st = hip_status(hipGetLastError(), "chol_zero_upper");
+        }
+    }
     if (st) return st;
     int bad = 0;
     st = hip_status(hipMemcpyAsync(&bad, p->dStatus, sizeof(int), hipMemcpyDeviceToHost, p->stream),
