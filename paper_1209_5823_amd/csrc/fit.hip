@@ -95,8 +95,9 @@ __device__ __forceinline__ double ipow_f(double x, int e) {
 
 // G_part[seg][a][n][n'] for 64 x 64 (n, n') and one power a of xh per
 // workgroup; a segment is up to NM_PIX_CHUNK pixels of one row of the band.
-// Wave w owns rows n = 16 w .. 16 w + 15; blocks whose rows or columns are
-// all padding are skipped.  A operand: T_n(p_k); B operand: T_n'(p_k) xh^a mask.
+// The 16 x 16 blocks with row block <= column block are formed (the waves
+// share them out); blocks whose rows or columns are all padding are skipped.
+// A operand: T_n(p_k); B operand: T_n'(p_k) xh^a mask.
 __global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ T, int N, int band_px,
                                                    int y_begin, int W, int H, int h, int cpr,
                                                    const unsigned char* __restrict__ mask,
@@ -110,55 +111,54 @@ __global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ T, 
     const int x_end = min(W, x_begin + NM_PIX_CHUNK);
     const int y = y_begin + row;
 
-    d4 acc[4];
+    // G is symmetric: only the 10 blocks (rb, cb) with rb <= cb of the 4 x 4
+    // block grid are formed, 3, 3, 2 and 2 of them by waves 0..3
+    constexpr int PAIRS[10][2] = {{0, 0}, {0, 1}, {0, 2}, {0, 3}, {1, 1},
+                                  {1, 2}, {1, 3}, {2, 2}, {2, 3}, {3, 3}};
+    const int p_begin = (w == 0) ? 0 : (w == 1) ? 3 : (w == 2) ? 6 : 8;
+    const int p_count = (w < 2) ? 3 : 2;
+    d4 acc[3];
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
-    const int na = 16 * w + j;                         // A row of this lane
+    for (int q = 0; q < 3; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
     // 16 pixels per step: lane group kq takes pixels x0 + 4 kq .. x0 + 4 kq + 3
     // (the k slot of instruction s is pixel x0 + 4 kq + s in both operands),
     // so each lane reads 4 consecutive floats of a filter row
     const bool vec = (W & 3) == 0;
-    if (16 * w < N) {
-        for (int x0 = x_begin; x0 < x_end; x0 += 16) {
-            const int xb = x0 + 4 * kq;
-            const size_t pb = (size_t)row * W + xb;
-            double wq[4];
+    for (int x0 = x_begin; x0 < x_end; x0 += 16) {
+        const int xb = x0 + 4 * kq;
+        const size_t pb = (size_t)row * W + xb;
+        double wq[4];
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int x = xb + s;
-                wq[s] = (x < x_end && in_mask(mask, H, W, h, x, y)) ? ipow_f(sx * x + ox, ea) : 0.0;
-            }
-            const bool full = vec && xb + 3 < x_end;
-            float av[4] = {0.f, 0.f, 0.f, 0.f};
-            if (na < N) {
-                const float* src = T + (size_t)na * band_px + pb;
+        for (int s = 0; s < 4; ++s) {
+            const int x = xb + s;
+            wq[s] = (x < x_end && in_mask(mask, H, W, h, x, y)) ? ipow_f(sx * x + ox, ea) : 0.0;
+        }
+        const bool full = vec && xb + 3 < x_end;
+        auto load4 = [&](int nrow, float* v) {
+            v[0] = v[1] = v[2] = v[3] = 0.f;
+            if (nrow < N) {
+                const float* src = T + (size_t)nrow * band_px + pb;
                 if (full) {
-                    const float4 v = *reinterpret_cast<const float4*>(src);
-                    av[0] = v.x; av[1] = v.y; av[2] = v.z; av[3] = v.w;
+                    const float4 t4 = *reinterpret_cast<const float4*>(src);
+                    v[0] = t4.x; v[1] = t4.y; v[2] = t4.z; v[3] = t4.w;
                 } else {
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) av[s] = (xb + s < x_end) ? src[s] : 0.f;
+                    for (int s = 0; s < 4; ++s) v[s] = (xb + s < x_end) ? src[s] : 0.f;
                 }
             }
+        };
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) {
-                if (16 * cb < N) {   // uniform
-                    const int nb = 16 * cb + j;
-                    float bv[4] = {0.f, 0.f, 0.f, 0.f};
-                    if (nb < N) {
-                        const float* src = T + (size_t)nb * band_px + pb;
-                        if (full) {
-                            const float4 v = *reinterpret_cast<const float4*>(src);
-                            bv[0] = v.x; bv[1] = v.y; bv[2] = v.z; bv[3] = v.w;
-                        } else {
-#pragma unroll
-                            for (int s = 0; s < 4; ++s) bv[s] = (xb + s < x_end) ? src[s] : 0.f;
-                        }
-                    }
+        for (int q = 0; q < 3; ++q) {
+            if (q < p_count) {   // uniform
+                const int rb = PAIRS[p_begin + q][0], cb = PAIRS[p_begin + q][1];
+                if (16 * rb < N && 16 * cb < N) {   // uniform
+                    float av[4], bv[4];
+                    load4(16 * rb + j, av);
+                    load4(16 * cb + j, bv);
 #pragma unroll
                     for (int s = 0; s < 4; ++s)
-                        acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)av[s], (double)bv[s] * wq[s],
-                                                                        acc[cb], 0, 0, 0);
+                        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)av[s], (double)bv[s] * wq[s],
+                                                                       acc[q], 0, 0, 0);
                 }
             }
         }
@@ -166,12 +166,16 @@ __global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ T, 
     // the float64 16x16x4 instruction stores row 4 e + kq of the 16 x 16
     // block in register e of lane (kq, j) (groups of one row, unlike the
     // float32 form's groups of four): lane (kq, j) holds
-    // G[n = 16 w + 4 e + kq][n' = 16 cb + j]
+    // G[n = 16 rb + 4 e + kq][n' = 16 cb + j]
     double* dst = part + ((size_t)seg * n_a + ea) * 64 * 64;
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
+    for (int q = 0; q < 3; ++q) {
+        if (q < p_count) {
+            const int rb = PAIRS[p_begin + q][0], cb = PAIRS[p_begin + q][1];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) dst[(16 * w + 4 * e + kq) * 64 + 16 * cb + j] = acc[cb][e];
+            for (int e = 0; e < 4; ++e) dst[(16 * rb + 4 * e + kq) * 64 + 16 * cb + j] = acc[q][e];
+        }
+    }
 }
 
 // S[(a, b)][.][.] += sum over segments (fixed order) of yh(segment row)^b G_a
@@ -180,6 +184,7 @@ __global__ void gram_reduce(const double* __restrict__ part, int n_seg, int cpr,
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n_mu * 4096) return;
     const int mu = idx >> 12, e = idx & 4095;
+    if (((e >> 6) >> 4) > ((e & 63) >> 4)) return;   // lower blocks are not formed (S symmetric)
     int tt = 0;
     while ((tt + 1) * (tt + 2) / 2 <= mu) ++tt;
     const int eb = mu - tt * (tt + 1) / 2, ea = tt - eb;
@@ -215,7 +220,9 @@ __global__ void assemble_jtj(const double* __restrict__ S, int N, int M, double*
     expo(m2, i2, j2);
     const int a = i1 + i2, b = j1 + j2, t = a + b;
     const int mu = t * (t + 1) / 2 + b;
-    JtJ[idx] = S[(size_t)mu * 4096 + n * 64 + n2];
+    // only blocks with row block <= column block are formed (S is symmetric)
+    const int lo = ((n >> 4) <= (n2 >> 4)) ? n : n2, hi = ((n >> 4) <= (n2 >> 4)) ? n2 : n;
+    JtJ[idx] = S[(size_t)mu * 4096 + lo * 64 + hi];
 }
 
 __global__ void fill_ones_kernel(float* __restrict__ v, int n) {
