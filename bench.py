@@ -94,8 +94,8 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the method shards into independent row slabs; see the design notes)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the method shards into independent row slabs of the image)",
               file=sys.stderr)
         sys.exit(2)
 

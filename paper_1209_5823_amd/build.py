@@ -3,8 +3,8 @@
     python -m paper_1209_5823_amd.build        # or build() from Python
 
 Every csrc/*.hip is compiled to an object under _build/ (in parallel), then
-linked into paper_1209_5823_amd/libsvconv.so.  The GPU machine loads the library
-built here; nothing is compiled at import time.
+linked into paper_1209_5823_amd/libsvconv.so.  Importing the package loads
+that library; nothing is compiled at import time.
 """
 
 import concurrent.futures
