@@ -305,6 +305,8 @@ def main():
                      "traffic_gbs": (round(traffic / (hr["ms"] * 1e-3) / 1e9, 1)
                                      if traffic else None),
                      "hbm_peak_gbs": 8000.0,
+                     "tap_by_tap_flop_per_pixel": (flops.separable_unfolded_flops_per_pixel(wl.degrees, M, k)
+                                                   if form == "separable" else None),
                      "paper_flop_per_pixel": flops.paper_flops_gfb(N, k),
                      "paper_model_tflops": round(flops.paper_flops_gfb(N, k) * px
                                                  / (hr["ms"] * 1e-3) / 1e12, 3)},

@@ -27,6 +27,15 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]
+# Per-file additions.  separable.hip: the contraction folds up to four column
+# factors of one parity on the same pair sums, in variants chosen at run time;
+# machine CSE merges the pair sums of the variants ahead of the branch, and
+# machine LICM and common-code hoisting lift them further, which keeps every
+# pair sum of the window live at once and spills registers.
+FILE_FLAGS = {
+    "separable.hip": ["-mllvm", "-disable-machine-cse", "-mllvm", "-disable-machine-licm",
+                      "-mllvm", "-simplifycfg-hoist-common=false"],
+}
 
 
 def sources():
@@ -35,7 +44,7 @@ def sources():
 
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + FLAGS + FILE_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     # the host pass does not know the packed-fp32 feature; that warning is expected
     err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)

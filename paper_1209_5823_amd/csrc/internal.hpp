@@ -67,6 +67,8 @@ struct ContractArgs {
 
 // Separable form (Gaussian bases only): one-dimensional factors per family.
 constexpr int kSepMaxFactors = 10;   // degree <= 9 (N <= 64)
+// spatial terms of the largest spatial degree (the padded coefficient stride)
+constexpr int kSepCoefPad = (kMaxSpatialDegree + 1) * (kMaxSpatialDegree + 2) / 2;
 struct SepArgs {
     const float* X;             // [H][W]
     const float* I;             // nullable
@@ -80,6 +82,8 @@ struct SepArgs {
     const float* coef;          // [N][M]
     const double* coefd;        // [N][M] float64 copy of coef (written by sep_prep)
     const double* gamma;        // [M] sum_n coef[n][m] beta[n] (written by sep_prep)
+    const double* coefp;        // [N][kSepCoefPad] coefd padded with zeros beyond M (sep_prep)
+    const double* gammap;       // [kSepCoefPad] gamma padded likewise (sep_prep)
     int M, d_s;
     double sx, ox, sy, oy;
     int tiles_x, n_tiles;
@@ -106,6 +110,7 @@ struct svconv_plan {
     std::vector<double> basis;          // host B[n][v+h][u+h], float64
     double* dSep1d = nullptr;           // separable factors (Gaussian plans with h >= 1)
     int* dSepFam = nullptr;             // [2 G] degree, first basis
+    double* dSepCoef = nullptr;         // [N + 1][kSepCoefPad] padded coefficients and gamma
 
     // device tables (basis form, fixed per plan)
     float* dF32 = nullptr;              // [N][k][k] correlation-oriented basis, float32
@@ -157,7 +162,7 @@ int launch_contract_lowp(const ContractArgs& a, const uint16_t* frag, int nb, in
 // separable.hip, separable_adjoint.hip
 int launch_contract_sep(SepArgs a, hipStream_t s);
 int launch_sep_prep(const float* coef, const double* beta, int N, int M, double* coefd,
-                    double* gamma, hipStream_t s);
+                    double* gamma, double* coefp, hipStream_t s);
 int launch_adjoint_a_sep(svconv_plan* p, const float* R, const float* G, double* ga);
 bool sep_adjoint_supported(const svconv_plan* p);
 int launch_adjoint_r_sep(svconv_plan* p, const float* a32, const float* G, float* gR);

@@ -71,7 +71,7 @@ static int dalloc(T** p, size_t count, const char* what) {
 }
 
 static void free_plan(svconv_plan* p) {
-    void* ptrs[] = {p->dSep1d, p->dSepFam,
+    void* ptrs[] = {p->dSep1d, p->dSepFam, p->dSepCoef,
                     p->dF32,   p->dF64,   p->dBeta,   p->dFragF32, p->dFragLoB, p->dFragLoH,
                     p->dScaleB, p->dScaleH, p->dFt32, p->dBetaT, p->dFragT32, p->dFragTB,  p->dFragTH,
                     p->dScaleT, p->dQpart, p->dQ,    p->dGrad,    p->dVec,     p->dStatus,
@@ -196,6 +196,7 @@ static int finish_plan(svconv_plan* p, svconv_plan** out) {
         }
         st = dalloc(&p->dSep1d, f1d.size(), "separable factors");
         if (!st) st = dalloc(&p->dSepFam, fam.size(), "separable families");
+        if (!st) st = dalloc(&p->dSepCoef, (size_t)(p->N + 1) * kSepCoefPad, "separable coefficients");
         if (!st) st = hip_status(hipMemcpy(p->dSep1d, f1d.data(), f1d.size() * 8, hipMemcpyHostToDevice), "upload");
         if (!st) st = hip_status(hipMemcpy(p->dSepFam, fam.data(), fam.size() * 4, hipMemcpyHostToDevice), "upload");
     }
@@ -252,10 +253,12 @@ int run_forward(svconv_plan* p, const float* R, const float* I, const float* a, 
         // per-call tables in the plan's vector scratch, past what the fit uses
         double* coefd = p->dVec + 7 * (size_t)kMaxCoefficients;
         double* gamma = p->dVec + 8 * (size_t)kMaxCoefficients;
-        int st = launch_sep_prep(a, p->dBeta, p->N, p->M, coefd, gamma, p->stream);
+        int st = launch_sep_prep(a, p->dBeta, p->N, p->M, coefd, gamma, p->dSepCoef, p->stream);
         if (st) return st;
         sa.coefd = coefd;
         sa.gamma = gamma;
+        sa.coefp = p->dSepCoef;
+        sa.gammap = p->dSepCoef + (size_t)p->N * kSepCoefPad;
         return launch_contract_sep(sa, p->stream);
     }
     if (p->form == SVCONV_FORM_BASIS) {

@@ -17,12 +17,19 @@
 // pedestal s is subtracted from R when it is staged and restored through
 // s * beta_n, as in the matrix-core forms.
 //
-// Workgroup: SEP_NW waves, output tile 64 x 4 SEP_NW.  Phase A (row pass):
-// each task is one staged row and 4 consecutive columns, computing up to
-// SEP_CHUNK row factors from one register window.  Phase B (column pass):
-// thread (lane x, wave w) owns column x and rows 4w..4w+3; it reads the column of a row
-// response into registers once and applies every column factor of that row
-// factor, then folds T_n + s beta_n into D with c_n(x,y) = sum_m a_nm P_m.
+// Both passes use the symmetry of the factors (f_e is even or odd in w with
+// e): each pair of taps +-w costs one add, shared by all factors of a parity,
+// and one FMA per factor (fold_conv below).
+//
+// Workgroup: SEP_NW waves, output tile 64 x SEP_ROWS SEP_NW.  Phase A (row
+// pass): each task is one staged row and SEP_AOUT consecutive columns,
+// computing up to SEP_CHUNK row factors from one register window.  Phase B
+// (column pass): thread (lane x, wave w) owns column x and SEP_ROWS rows; it
+// reads the column of a row response into registers once and applies every
+// column factor of that row factor, four at a time, then folds T_n + s beta_n
+// into D with c_n(x,y) = sum_m a_nm P_m.
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace svc {
@@ -44,6 +51,9 @@ constexpr int SEP_TW = 64, SEP_TH = SEP_RPT * SEP_NW;
 #define SEP_ROUND 4
 #endif
 constexpr int SEP_CHUNK = SEP_ROUND;       // row factors per phase A / phase B round
+// rounds start at even factors (the fold needs the parity of each factor) and
+// a round folds at most 4 factors together
+static_assert(SEP_CHUNK == 2 || SEP_CHUNK == 4, "SEP_ROUND must be 2 or 4");
 
 // Read-only tables (factors, coefficients, sums) are read through the
 // constant address space: every lane reads the same element, so the loads
@@ -60,7 +70,114 @@ __device__ __forceinline__ int sep_xcd_remap(int bid, int n) {
     return x8 * q8 + (x8 < r8 ? x8 : r8) + tt;
 }
 
-template <int H>
+// Symmetric fold.  f_e(-w) = (-1)^e f_e(w) and f_e(0) = 0 for e >= 1, so a
+// k-tap convolution of a window x is
+//   sum_w f_e(w) x[o - w] = f_e(0) x[o] + sum_{w=1..h} f_e(w) (x[o-w] + (-1)^e x[o+w]):
+// one add per tap pair, shared by the factors of one parity that use the
+// window, and one FMA per factor.  fold_conv applies the NF factors
+// f_e, f_{e+2}, ... of parity ODD to a window of NO + 2h samples: out[c][o]
+// for the NO outputs; f points at the taps of f_e.  The centre tap is applied
+// to the first factor of an even group (it is zero for every other factor).
+template <int H, int NF, int NO, bool ODD>
+__device__ __forceinline__ void fold_conv(const double (&x)[NO + 2 * H], cptr<double> f,
+                                          double (&out)[NF][NO]) {
+    constexpr int K = 2 * H + 1;
+#pragma unroll
+    for (int o = 0; o < NO; ++o) out[0][o] = ODD ? 0.0 : f[H] * x[o + H];
+#pragma unroll
+    for (int c = 1; c < NF; ++c)
+#pragma unroll
+        for (int o = 0; o < NO; ++o) out[c][o] = 0.0;
+#pragma unroll
+    for (int w = 1; w <= H; ++w) {
+        double p[NO];
+#pragma unroll
+        for (int o = 0; o < NO; ++o) p[o] = ODD ? x[o + H - w] - x[o + H + w] : x[o + H - w] + x[o + H + w];
+#pragma unroll
+        for (int c = 0; c < NF; ++c) {
+            const double fw = f[2 * c * K + H + w];
+#pragma unroll
+            for (int o = 0; o < NO; ++o) out[c][o] = fma(fw, p[o], out[c][o]);
+        }
+    }
+}
+
+// Calls fn(NF) with NF = nf (1 <= nf <= 4) as a compile-time constant.
+template <class Fn>
+__device__ __forceinline__ void with_nf(int nf, Fn&& fn) {
+    switch (nf) {
+        case 1: fn(std::integral_constant<int, 1>{}); break;
+        case 2: fn(std::integral_constant<int, 2>{}); break;
+        case 3: fn(std::integral_constant<int, 3>{}); break;
+        default: fn(std::integral_constant<int, 4>{}); break;
+    }
+}
+
+// Plain k-tap convolution of one factor (no fold): out[o] = sum_u f[u] x[o + 2h - u].
+template <int H, int NO>
+__device__ __forceinline__ void direct_conv(const double (&x)[NO + 2 * H], cptr<double> f,
+                                            double (&out)[NO]) {
+#pragma unroll
+    for (int o = 0; o < NO; ++o) out[o] = 0.0;
+#pragma unroll
+    for (int u = 0; u < 2 * H + 1; ++u) {
+        const double fu = f[u];
+#pragma unroll
+        for (int o = 0; o < NO; ++o) out[o] = fma(fu, x[o + 2 * H - u], out[o]);
+    }
+}
+
+// Cy[q] = sum_ie c[m(ie, q)] xh^ie for q <= DSM, the coefficients of a
+// spatial polynomial sum_m c_m P_m in yh at column x; the terms m are ordered
+// by total degree, and within one by falling power of xh, and c is padded
+// with zeros past the plan's terms, so every instance reads all its terms.
+template <int DSM>
+__device__ __forceinline__ void coef_in_x(cptr<double> c, const double (&xpow)[DSM + 1],
+                                          double (&cy)[DSM + 1]) {
+#pragma unroll
+    for (int q = 0; q <= DSM; ++q) cy[q] = 0.0;
+    int m = 0;
+#pragma unroll
+    for (int tt = 0; tt <= DSM; ++tt) {
+#pragma unroll
+        for (int ie = tt; ie >= 0; --ie) cy[tt - ie] = fma(c[m + tt - ie], xpow[ie], cy[tt - ie]);
+        m += tt + 1;
+    }
+}
+
+// One basis response T_n on a thread's SEP_RPT rows: in the T-only mode
+// written out as T_n + s beta_n, else D += c_n T_n with
+// c_n(x, y) = sum_q Cy[q] yh^q (Horner in yh; DSM bounds the spatial degree
+// of the kernel instance).  The pedestal term s beta_n c_n is summed once per
+// pixel at the end.
+template <bool TONLY, int DSM>
+__device__ __forceinline__ void sep_basis_out(const SepArgs& a, int n, const double (&tv)[SEP_RPT],
+                                              int x, int y0, int y_end, int d_s,
+                                              const double (&xpow)[DSM + 1],
+                                              const double (&yh)[SEP_RPT], double (&dacc)[SEP_RPT]) {
+    if (TONLY) {
+        const double pbt = (double)a.ped * as_const(a.beta)[n];
+        if (x < a.W) {
+#pragma unroll
+            for (int o = 0; o < SEP_RPT; ++o) {
+                const int y = y0 + o;
+                if (y < y_end) a.tout[((size_t)n * a.n_rows + (y - a.y_begin)) * a.W + x] = (float)(tv[o] + pbt);
+            }
+        }
+        return;
+    }
+    double cy[DSM + 1];
+    coef_in_x<DSM>(as_const(a.coefp) + (size_t)n * kSepCoefPad, xpow, cy);
+#pragma unroll
+    for (int o = 0; o < SEP_RPT; ++o) {
+        double cn = cy[DSM];
+#pragma unroll
+        for (int q = DSM - 1; q >= 0; --q) cn = fma(cn, yh[o], cy[q]);
+        dacc[o] = fma(cn, tv[o], dacc[o]);
+    }
+}
+
+template <int H, bool TONLY, int DSM>
 __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
     constexpr int NT = 64 * SEP_NW;
     constexpr int K = 2 * H + 1;
@@ -76,8 +193,6 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
     float* rc = sep_lds + RA * TP;              // [SEP_CHUNK][RA][RP]
 
     const cptr<double> f1d = as_const(a.f1d);
-    const cptr<double> beta = as_const(a.beta);
-    const cptr<double> coefd = as_const(a.coefd);
     const cptr<int> fam = as_const(a.fam);
 
     const int tid = threadIdx.x;
@@ -85,7 +200,6 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
     const int X0 = (t % a.tiles_x) * SEP_TW;
     const int Y0 = a.y_begin + (t / a.tiles_x) * SEP_TH;
     const int y_end = min(a.H, a.y_begin + a.n_rows);
-    const bool t_only = a.tout != nullptr;   // write the basis responses instead of D
 
     // stage R - s; outside the image R is 0, so the staged value is -s there
     for (int q = tid; q < RA * CA; q += NT) {
@@ -99,10 +213,10 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
     const int lane = tid & 63, w = tid >> 6;
     const int x = X0 + lane;
     const double xh = a.sx * x + a.ox;
-    double xpow[kMaxSpatialDegree + 1];
+    double xpow[DSM + 1];
     xpow[0] = 1.0;
 #pragma unroll
-    for (int q = 1; q <= kMaxSpatialDegree; ++q) xpow[q] = xpow[q - 1] * xh;
+    for (int q = 1; q <= DSM; ++q) xpow[q] = xpow[q - 1] * xh;
     double yh[SEP_RPT], dacc[SEP_RPT];
 #pragma unroll
     for (int rr = 0; rr < SEP_RPT; ++rr) {
@@ -127,21 +241,26 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
                     double win[WA];
 #pragma unroll
                     for (int s = 0; s < WA; ++s) win[s] = (double)tile[r * TP + q4 + s];
-                    for (int c = 0; c < nc; ++c) {
-                        const cptr<double> f = fg + (size_t)(i0 + c) * K;
-                        double acc[SEP_APT];
+                    // the round's factors i0..i0+nc-1 as an even and an odd group
+                    auto group = [&](auto odd_c) {
+                        constexpr int par = decltype(odd_c)::value ? 1 : 0;
+                        const int nf = (nc - par + 1) / 2;
+                        if (nf > 0) {
+                            with_nf(nf, [&](auto nf_c) {
+                                constexpr int NF = decltype(nf_c)::value < 2 ? decltype(nf_c)::value : 2;
+                                double acc[NF][SEP_APT];
+                                fold_conv<H, NF, SEP_APT, par == 1>(win, fg + (size_t)(i0 + par) * K, acc);
 #pragma unroll
-                        for (int o = 0; o < SEP_APT; ++o) acc[o] = 0.0;
+                                for (int cc = 0; cc < NF; ++cc) {
+                                    float* dst = rc + ((size_t)(par + 2 * cc) * RA + r) * RP + q4;
 #pragma unroll
-                        for (int u = 0; u < K; ++u) {
-                            const double fu = f[u];
-#pragma unroll
-                            for (int o = 0; o < SEP_APT; ++o) acc[o] = fma(fu, win[o + 2 * H - u], acc[o]);
+                                    for (int o = 0; o < SEP_APT; ++o) dst[o] = (float)acc[cc][o];
+                                }
+                            });
                         }
-                        float* dst = rc + ((size_t)c * RA + r) * RP + q4;
-#pragma unroll
-                        for (int o = 0; o < SEP_APT; ++o) dst[o] = (float)acc[o];
-                    }
+                    };
+                    group(std::false_type{});
+                    group(std::true_type{});
                 }
             }
             __syncthreads();
@@ -151,89 +270,49 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
                 double col[WB];
 #pragma unroll
                 for (int s = 0; s < WB; ++s) col[s] = (double)rc[((size_t)c * RA + SEP_RPT * w + s) * RP + lane];
-                for (int j = 0; j + i <= deg; ++j) {
-                    const int n = base + (i + j) * (i + j + 1) / 2 + j;
-                    const cptr<double> f = fg + (size_t)j * K;
-                    double tv[SEP_RPT];
+                // the column factors of row factor i in two groups of one
+                // parity, f_0, f_2, ... and f_1, f_3, ..., up to 4 folded together
+                // (a degree above 7 leaves f_8 or f_9, applied unfolded)
+                auto group = [&](auto odd_c) {
+                    constexpr int par = decltype(odd_c)::value ? 1 : 0;
+                    if (deg - i < par) return;
+                    const int cnt = (deg - i - par) / 2 + 1;   // j = par, par + 2, ... <= deg - i
+                    const int nf = min(cnt, 4);
+                    with_nf(nf, [&](auto nf_c) {
+                        constexpr int NF = decltype(nf_c)::value;
+                        double tv[NF][SEP_RPT];
+                        fold_conv<H, NF, SEP_RPT, par == 1>(col, fg + (size_t)par * K, tv);
 #pragma unroll
-                    for (int o = 0; o < SEP_RPT; ++o) tv[o] = 0.0;
-#pragma unroll
-                    for (int v = 0; v < K; ++v) {
-                        const double fv = f[v];
-#pragma unroll
-                        for (int o = 0; o < SEP_RPT; ++o) tv[o] = fma(fv, col[o + 2 * H - v], tv[o]);
-                    }
-                    if (t_only) {
-                        const double pbt = (double)a.ped * beta[n];
-                        if (x < a.W) {
-#pragma unroll
-                            for (int o = 0; o < SEP_RPT; ++o) {
-                                const int y = Y0 + SEP_RPT * w + o;
-                                if (y < y_end)
-                                    a.tout[((size_t)n * a.n_rows + (y - a.y_begin)) * a.W + x] = (float)(tv[o] + pbt);
-                            }
+                        for (int jj = 0; jj < NF; ++jj) {
+                            const int j = par + 2 * jj;
+                            sep_basis_out<TONLY, DSM>(a, base + (i + j) * (i + j + 1) / 2 + j, tv[jj], x,
+                                                 Y0 + SEP_RPT * w, y_end, d_s, xpow, yh, dacc);
                         }
-                        continue;
+                    });
+                    if (cnt > 4) {
+                        const int j = par + 8;
+                        double tv1[SEP_RPT];
+                        direct_conv<H, SEP_RPT>(col, fg + (size_t)j * K, tv1);
+                        sep_basis_out<TONLY, DSM>(a, base + (i + j) * (i + j + 1) / 2 + j, tv1, x,
+                                         Y0 + SEP_RPT * w, y_end, d_s, xpow, yh, dacc);
                     }
-                    // c_n(x, y) = sum_jj Cy[jj] yh^jj with Cy[jj] = sum_ie a[n][m(ie, jj)] xh^ie
-                    double cy[kMaxSpatialDegree + 1];
-#pragma unroll
-                    for (int q = 0; q <= kMaxSpatialDegree; ++q) cy[q] = 0.0;
-                    const cptr<double> an = coefd + (size_t)n * a.M;
-                    int m = 0;
-#pragma unroll
-                    for (int tt = 0; tt <= kMaxSpatialDegree; ++tt) {
-                        if (tt <= d_s) {
-#pragma unroll
-                            for (int ie = tt; ie >= 0; --ie) cy[tt - ie] = fma(an[m + tt - ie], xpow[ie], cy[tt - ie]);
-                        }
-                        m += tt + 1;
-                    }
-                    // Horner in yh; the terms above d_s are zero, so the
-                    // quadratic path is exact for d_s <= 2 (the uniform branch
-                    // keeps the common case short).  The pedestal term
-                    // s beta_n c_n is summed once per pixel at the end.
-                    if (d_s <= 2) {
-#pragma unroll
-                        for (int o = 0; o < SEP_RPT; ++o) {
-                            const double cn = fma(fma(cy[2], yh[o], cy[1]), yh[o], cy[0]);
-                            dacc[o] = fma(cn, tv[o], dacc[o]);
-                        }
-                    } else {
-#pragma unroll
-                        for (int o = 0; o < SEP_RPT; ++o) {
-                            double cn = cy[kMaxSpatialDegree];
-#pragma unroll
-                            for (int q = kMaxSpatialDegree - 1; q >= 0; --q) cn = fma(cn, yh[o], cy[q]);
-                            dacc[o] = fma(cn, tv[o], dacc[o]);
-                        }
-                    }
-                }
+                };
+                group(std::false_type{});
+                group(std::true_type{});
             }
         }
     }
-    if (!t_only && x < a.W) {
+    if (!TONLY && x < a.W) {
         // pedestal restore: s sum_n beta_n c_n = s sum_m gamma_m P_m
-        const cptr<double> gam = as_const(a.gamma);
-        double cy[kMaxSpatialDegree + 1];
-#pragma unroll
-        for (int q = 0; q <= kMaxSpatialDegree; ++q) cy[q] = 0.0;
-        int m = 0;
-#pragma unroll
-        for (int tt = 0; tt <= kMaxSpatialDegree; ++tt) {
-            if (tt <= d_s) {
-#pragma unroll
-                for (int ie = tt; ie >= 0; --ie) cy[tt - ie] = fma(gam[m + tt - ie], xpow[ie], cy[tt - ie]);
-            }
-            m += tt + 1;
-        }
+        double cy[DSM + 1];
+        coef_in_x<DSM>(as_const(a.gammap), xpow, cy);
 #pragma unroll
         for (int o = 0; o < SEP_RPT; ++o) {
             const int y = Y0 + SEP_RPT * w + o;
             if (y < y_end) {
-                double pg = cy[kMaxSpatialDegree];
+                double pg = cy[DSM];
 #pragma unroll
-                for (int q = kMaxSpatialDegree - 1; q >= 0; --q) pg = fma(pg, yh[o], cy[q]);
+                for (int q = DSM - 1; q >= 0; --q) pg = fma(pg, yh[o], cy[q]);
                 const size_t idx = (size_t)y * a.W + x;
                 const double iv = a.I ? (double)a.I[idx] : 0.0;
                 a.out[idx] = (float)(fma((double)a.ped, pg, dacc[o]) - iv);
@@ -243,22 +322,34 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
 }
 
 // Per-call tables of the separable epilogue: coef in float64 (read by scalar
-// loads without conversions) and gamma_m = sum_n coef[n][m] beta_n.
+// loads without conversions), gamma_m = sum_n coef[n][m] beta_n, and, when
+// coefp is given, both again with the stride kSepCoefPad and zeros beyond M
+// (coefp[N * kSepCoefPad + m] is gamma), so that the contraction reads a
+// fixed number of terms without branches.
 __global__ __launch_bounds__(1024) void sep_prep_kernel(const float* __restrict__ coef,
                                                         const double* __restrict__ beta, int N,
                                                         int M, double* __restrict__ coefd,
-                                                        double* __restrict__ gamma) {
+                                                        double* __restrict__ gamma,
+                                                        double* __restrict__ coefp) {
     for (int i = threadIdx.x; i < N * M; i += 1024) coefd[i] = (double)coef[i];
-    if ((int)threadIdx.x < M) {
+    if (coefp)
+        for (int i = threadIdx.x; i < (N + 1) * kSepCoefPad; i += 1024) {
+            const int n = i / kSepCoefPad, m = i - n * kSepCoefPad;
+            if (n < N) coefp[i] = m < M ? (double)coef[n * M + m] : 0.0;
+        }
+    if ((int)threadIdx.x < kSepCoefPad) {
+        const int m = threadIdx.x;
         double g = 0.0;
-        for (int n = 0; n < N; ++n) g = fma((double)coef[n * M + threadIdx.x], beta[n], g);
-        gamma[threadIdx.x] = g;
+        if (m < M)
+            for (int n = 0; n < N; ++n) g = fma((double)coef[n * M + m], beta[n], g);
+        if (m < M) gamma[m] = g;
+        if (coefp) coefp[(size_t)N * kSepCoefPad + m] = g;
     }
 }
 
 int launch_sep_prep(const float* coef, const double* beta, int N, int M, double* coefd,
-                    double* gamma, hipStream_t s) {
-    hipLaunchKernelGGL(sep_prep_kernel, dim3(1), dim3(1024), 0, s, coef, beta, N, M, coefd, gamma);
+                    double* gamma, double* coefp, hipStream_t s) {
+    hipLaunchKernelGGL(sep_prep_kernel, dim3(1), dim3(1024), 0, s, coef, beta, N, M, coefd, gamma, coefp);
     return hip_status(hipGetLastError(), "sep_prep_kernel");
 }
 
@@ -266,7 +357,15 @@ template <int H>
 static int launch_sep_t(const SepArgs& a, hipStream_t s) {
     constexpr int RA = SEP_TH + 2 * H, CA = SEP_TW + 2 * H;
     const size_t lds = ((size_t)RA * (CA | 1) + (size_t)SEP_CHUNK * RA * (SEP_TW + 1)) * sizeof(float);
-    hipLaunchKernelGGL(contract_sep_kernel<H>, dim3(a.n_tiles), dim3(64 * SEP_NW), lds, s, a);
+    // TONLY: write the basis responses T_n + s beta_n instead of D; spatial
+    // degrees up to 2 take the instance with the short polynomial in yh
+    if (a.tout)
+        hipLaunchKernelGGL((contract_sep_kernel<H, true, 0>), dim3(a.n_tiles), dim3(64 * SEP_NW), lds, s, a);
+    else if (a.d_s <= 2)
+        hipLaunchKernelGGL((contract_sep_kernel<H, false, 2>), dim3(a.n_tiles), dim3(64 * SEP_NW), lds, s, a);
+    else
+        hipLaunchKernelGGL((contract_sep_kernel<H, false, kMaxSpatialDegree>), dim3(a.n_tiles),
+                           dim3(64 * SEP_NW), lds, s, a);
     return hip_status(hipGetLastError(), "contract_sep_kernel");
 }
 

@@ -517,7 +517,7 @@ int launch_adjoint_r_sep(svconv_plan* p, const float* a32, const float* G, float
     const int h = p->h;
     double* coefd = p->dVec + 7 * (size_t)kMaxCoefficients;
     double* gamma = p->dVec + 8 * (size_t)kMaxCoefficients;
-    int st = launch_sep_prep(a32, p->dBeta, p->N, p->M, coefd, gamma, p->stream);
+    int st = launch_sep_prep(a32, p->dBeta, p->N, p->M, coefd, gamma, nullptr, p->stream);
     if (st) return st;
     SepRArgs a{};
     a.G = G;

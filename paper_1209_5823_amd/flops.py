@@ -47,10 +47,32 @@ BYTES_PER_PIXEL = 12          # R in, I in, D out (float32)
 BYTES_PER_PIXEL_FORWARD = 8   # R in, C out
 
 
-def separable_flops_per_pixel(degrees, M, k):
-    """FLOP per pixel of the separable Gaussian-basis form: a row pass with the
-    (d_g + 1) one-dimensional factors of each family, a column pass per basis,
-    then the coefficients, the dot with c and the subtraction."""
+def separable_unfolded_flops_per_pixel(degrees, M, k):
+    """FLOP per pixel of the separable Gaussian-basis form taken tap by tap: a
+    row pass with the (d_g + 1) one-dimensional factors of each family, a
+    column pass per basis, then the coefficients, the dot with c and the
+    subtraction."""
     n_factors = sum(d + 1 for d in degrees)
     N = sum((d + 1) * (d + 2) // 2 for d in degrees)
     return 2 * n_factors * k + 2 * N * k + 2 * N * M + 2 * N + 1
+
+
+def separable_flops_per_pixel(degrees, M, k):
+    """FLOP per pixel of the separable Gaussian-basis form with the symmetric
+    fold.  A factor is even or odd, f_e(-w) = (-1)^e f_e(w), and f_e(0) = 0
+    for e >= 1, so applying the factors e = 0..J-1 to one window costs h adds
+    per parity present (the pair sums x[-w] + x[w], or differences) and, per
+    factor, h FMAs, plus one FMA for the centre tap of f_0.  Windows: one per
+    family in the row pass (J = d + 1), one per row factor i in the column
+    pass (J = d - i + 1).  Then 2 N M + 2 N + 1 as in the other forms."""
+    h = (k - 1) // 2
+
+    def window(J):
+        adds = h * min(J, 2)
+        fmas = J * h + 1
+        return adds + 2 * fmas
+
+    row = sum(window(d + 1) for d in degrees)
+    col = sum(window(d - i + 1) for d in degrees for i in range(d + 1))
+    N = sum((d + 1) * (d + 2) // 2 for d in degrees)
+    return row + col + 2 * N * M + 2 * N + 1

@@ -35,10 +35,34 @@ def test_algorithmic_counts_at_workloads():
     assert flops.flops_per_pixel(22, 6, 15) == 10209
 
 
-def test_separable_count_at_the_chip_workload():
+def test_separable_unfolded_count_at_the_chip_workload():
     # 15 row factors (degrees 6, 4, 2) and 49 column passes of 21 taps, then
     # 2 N M + 2 N + 1 for the coefficients, the dot and the subtraction
-    assert flops.separable_flops_per_pixel((6, 4, 2), 6, 21) == 2 * 15 * 21 + 2 * 49 * 21 + 2 * 49 * 6 + 2 * 49 + 1
-    assert flops.separable_flops_per_pixel((6, 4, 2), 6, 21) == 3375
+    assert flops.separable_unfolded_flops_per_pixel((6, 4, 2), 6, 21) == 2 * 15 * 21 + 2 * 49 * 21 + 2 * 49 * 6 + 2 * 49 + 1
+    assert flops.separable_unfolded_flops_per_pixel((6, 4, 2), 6, 21) == 3375
     # a single delta family: one factor, one basis
-    assert flops.separable_flops_per_pixel((0,), 1, 3) == 2 * 3 + 2 * 3 + 2 + 2 + 1
+    assert flops.separable_unfolded_flops_per_pixel((0,), 1, 3) == 2 * 3 + 2 * 3 + 2 + 2 + 1
+
+
+def _folded_by_enumeration(degrees, M, k):
+    # every factor application and every window of pair sums counted one by one
+    h = (k - 1) // 2
+    total = 0
+    for d in degrees:
+        windows = [list(range(d + 1))] + [list(range(d - i + 1)) for i in range(d + 1)]
+        for factors in windows:
+            total += h * len({e % 2 for e in factors})          # pair sums / differences
+            for e in factors:
+                total += 2 * h + (2 if e == 0 else 0)          # h FMAs (+ the centre of f_0)
+    N = sum((d + 1) * (d + 2) // 2 for d in degrees)
+    return total + 2 * N * M + 2 * N + 1
+
+
+def test_separable_folded_count():
+    for degrees, M, k in (((6, 4, 2), 6, 21), ((6, 4, 2), 10, 31), ((0,), 1, 3), ((9,), 3, 11), ((1, 3), 1, 5)):
+        assert flops.separable_flops_per_pixel(degrees, M, k) == _folded_by_enumeration(degrees, M, k)
+    # the chip workload: row 366, column 1280, coefficients and dot 687
+    assert flops.separable_flops_per_pixel((6, 4, 2), 6, 21) == 2333
+    # a fold never costs more than the tap-by-tap count
+    for degrees, M, k in (((6, 4, 2), 6, 21), ((0,), 1, 3), ((2,), 1, 3)):
+        assert flops.separable_flops_per_pixel(degrees, M, k) <= flops.separable_unfolded_flops_per_pixel(degrees, M, k)
