@@ -27,15 +27,14 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]
-# Per-file additions.  separable.hip: the contraction folds up to four column
+# Per-file additions.  separable*.hip: the kernels fold up to four column
 # factors of one parity on the same pair sums, in variants chosen at run time;
 # machine CSE merges the pair sums of the variants ahead of the branch, and
 # machine LICM and common-code hoisting lift them further, which keeps every
 # pair sum of the window live at once and spills registers.
-FILE_FLAGS = {
-    "separable.hip": ["-mllvm", "-disable-machine-cse", "-mllvm", "-disable-machine-licm",
-                      "-mllvm", "-simplifycfg-hoist-common=false"],
-}
+_SEP_FLAGS = ["-mllvm", "-disable-machine-cse", "-mllvm", "-disable-machine-licm",
+              "-mllvm", "-simplifycfg-hoist-common=false"]
+FILE_FLAGS = {"separable.hip": _SEP_FLAGS, "separable_adjoint.hip": _SEP_FLAGS}
 
 
 def sources():

@@ -19,6 +19,7 @@
 // walk.  Per-workgroup results go to a partial array that a second kernel
 // sums in a fixed order.
 #include "internal.hpp"
+#include "sep_fold.hpp"
 
 namespace svc {
 
@@ -30,6 +31,7 @@ namespace svc {
 #endif
 constexpr int SA_NW = 8, SA_RPT = SA_ROWS, SA_TW = 64, SA_TH = SA_NW * SA_RPT, SA_APT = 8;
 constexpr int SA_CHUNK = SA_ROUND;         // row factors per round
+static_assert(SA_CHUNK == 2 || SA_CHUNK == 4, "SA_ROUND must be 2 or 4 (rounds start at even factors)");
 
 struct SepAdjArgs {
     const float* R;
@@ -46,12 +48,29 @@ struct SepAdjArgs {
     double* part;               // [n_wg][N M]
 };
 
-template <class T>
-using acptr = const __attribute__((address_space(4))) T*;
-
-__device__ __forceinline__ int sep_xcd_remap_r(int bid, int n) {
-    const int x8 = bid & 7, tt = bid >> 3, q8 = n >> 3, r8 = n & 7;
-    return x8 * q8 + (x8 < r8 ? x8 : r8) + tt;
+// V[slot][q][lane] += sum_o G T yh^q over a thread's SA_RPT rows, q <= d_s
+// (float64 LDS atomics: the 8 waves of a workgroup share a column).
+__device__ __forceinline__ void sa_moments(const SepAdjArgs& a, double* V, int slot, int DS1, int lane,
+                                           const double (&gv)[SA_RPT], const double (&yv)[SA_RPT],
+                                           const double (&tv)[SA_RPT]) {
+    double mom[kMaxSpatialDegree + 1];
+#pragma unroll
+    for (int q = 0; q <= kMaxSpatialDegree; ++q) mom[q] = 0.0;
+#pragma unroll
+    for (int o = 0; o < SA_RPT; ++o) {
+        double pw = gv[o] * tv[o];
+#pragma unroll
+        for (int q = 0; q <= kMaxSpatialDegree; ++q) {
+            if (q <= a.d_s) {
+                mom[q] += pw;
+                pw *= yv[o];
+            }
+        }
+    }
+    double* vrow = V + (size_t)slot * DS1 * 64 + lane;
+#pragma unroll
+    for (int q = 0; q <= kMaxSpatialDegree; ++q)
+        if (q <= a.d_s) atomicAdd(vrow + q * 64, mom[q]);
 }
 
 template <int H>
@@ -69,8 +88,8 @@ __global__ __launch_bounds__(64 * SA_NW) void adjoint_a_sep_kernel(SepAdjArgs a)
     float* tile = reinterpret_cast<float*>(xpt + (size_t)DS1 * 64);   // [RA][TP]
     float* rc = tile + RA * TP;                          // [SA_CHUNK][RA][RP]
 
-    const acptr<double> f1d = (acptr<double>)a.f1d;
-    const acptr<int> fam = (acptr<int>)a.fam;
+    const cptr<double> f1d = (cptr<double>)a.f1d;
+    const cptr<int> fam = (cptr<int>)a.fam;
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int sxi = blockIdx.x % a.strips, seg = blockIdx.x / a.strips;
@@ -92,7 +111,7 @@ __global__ __launch_bounds__(64 * SA_NW) void adjoint_a_sep_kernel(SepAdjArgs a)
 
     for (int g = 0; g < a.G_fam; ++g) {
         const int deg = fam[2 * g], base = fam[2 * g + 1];
-        const acptr<double> fg = f1d + (size_t)g * kSepMaxFactors * K;
+        const cptr<double> fg = f1d + (size_t)g * kSepMaxFactors * K;
         for (int i0 = 0; i0 <= deg; i0 += SA_CHUNK) {
             const int nc = min(SA_CHUNK, deg + 1 - i0);
             int nn = 0;
@@ -121,21 +140,26 @@ __global__ __launch_bounds__(64 * SA_NW) void adjoint_a_sep_kernel(SepAdjArgs a)
                         double win[WA];
 #pragma unroll
                         for (int s = 0; s < WA; ++s) win[s] = (double)tile[r * TP + q0 + s];
-                        for (int c = 0; c < nc; ++c) {
-                            const acptr<double> f = fg + (size_t)(i0 + c) * K;
-                            double acc[SA_APT];
+                        // the round's factors as an even and an odd group (symmetric fold)
+                        auto group = [&](auto odd_c) {
+                            constexpr int par = decltype(odd_c)::value ? 1 : 0;
+                            const int nf = (nc - par + 1) / 2;
+                            if (nf > 0) {
+                                with_nf(nf, [&](auto nf_c) {
+                                    constexpr int NF = decltype(nf_c)::value < 2 ? decltype(nf_c)::value : 2;
+                                    double acc[NF][SA_APT];
+                                    fold_conv<H, NF, SA_APT, par == 1>(win, fg + (size_t)(i0 + par) * K, acc);
 #pragma unroll
-                            for (int o = 0; o < SA_APT; ++o) acc[o] = 0.0;
+                                    for (int cc = 0; cc < NF; ++cc) {
+                                        float* dst = rc + ((size_t)(par + 2 * cc) * RA + r) * RP + q0;
 #pragma unroll
-                            for (int u = 0; u < K; ++u) {
-                                const double fu = f[u];
-#pragma unroll
-                                for (int o = 0; o < SA_APT; ++o) acc[o] = fma(fu, win[o + 2 * H - u], acc[o]);
+                                        for (int o = 0; o < SA_APT; ++o) dst[o] = (float)acc[cc][o];
+                                    }
+                                });
                             }
-                            float* dst = rc + ((size_t)c * RA + r) * RP + q0;
-#pragma unroll
-                            for (int o = 0; o < SA_APT; ++o) dst[o] = (float)acc[o];
-                        }
+                        };
+                        group(std::false_type{});
+                        group(std::true_type{});
                     }
                 }
                 __syncthreads();
@@ -167,42 +191,33 @@ __global__ __launch_bounds__(64 * SA_NW) void adjoint_a_sep_kernel(SepAdjArgs a)
                     for (int q = 0; q <= kMaxSpatialDegree; ++q)
                         if (q <= a.d_s) atomicAdd(vrow + q * 64, mom[q]);
                 }
-                int nl = 0;
+                int nl = 0;   // slot of basis (i, 0) in this round
                 for (int c = 0; c < nc; ++c) {
                     const int i = i0 + c;
                     double col[WB];
 #pragma unroll
                     for (int s = 0; s < WB; ++s) col[s] = (double)rc[((size_t)c * RA + SA_RPT * w + s) * RP + lane];
-                    for (int j = 0; j + i <= deg; ++j, ++nl) {
-                        const acptr<double> f = fg + (size_t)j * K;
-                        double tv[SA_RPT];
+                    // column factors f_0, f_2, ... and f_1, f_3, ... of row factor i, folded
+                    auto group = [&](auto odd_c) {
+                        constexpr int par = decltype(odd_c)::value ? 1 : 0;
+                        if (deg - i < par) return;
+                        const int cnt = (deg - i - par) / 2 + 1;
+                        with_nf(min(cnt, 4), [&](auto nf_c) {
+                            constexpr int NF = decltype(nf_c)::value;
+                            double tv[NF][SA_RPT];
+                            fold_conv<H, NF, SA_RPT, par == 1>(col, fg + (size_t)par * K, tv);
 #pragma unroll
-                        for (int o = 0; o < SA_RPT; ++o) tv[o] = 0.0;
-#pragma unroll
-                        for (int v = 0; v < K; ++v) {
-                            const double fv = f[v];
-#pragma unroll
-                            for (int o = 0; o < SA_RPT; ++o) tv[o] = fma(fv, col[o + 2 * H - v], tv[o]);
+                            for (int jj = 0; jj < NF; ++jj) sa_moments(a, V, nl + par + 2 * jj, DS1, lane, gv, yv, tv[jj]);
+                        });
+                        if (cnt > 4) {
+                            double tv1[SA_RPT];
+                            direct_conv<H, SA_RPT>(col, fg + (size_t)(par + 8) * K, tv1);
+                            sa_moments(a, V, nl + par + 8, DS1, lane, gv, yv, tv1);
                         }
-                        double mom[kMaxSpatialDegree + 1];
-#pragma unroll
-                        for (int q = 0; q <= kMaxSpatialDegree; ++q) mom[q] = 0.0;
-#pragma unroll
-                        for (int o = 0; o < SA_RPT; ++o) {
-                            double pw = gv[o] * tv[o];
-#pragma unroll
-                            for (int q = 0; q <= kMaxSpatialDegree; ++q) {
-                                if (q <= a.d_s) {
-                                    mom[q] += pw;
-                                    pw *= yv[o];
-                                }
-                            }
-                        }
-                        double* vrow = V + (size_t)nl * DS1 * 64 + lane;
-#pragma unroll
-                        for (int q = 0; q <= kMaxSpatialDegree; ++q)
-                            if (q <= a.d_s) atomicAdd(vrow + q * 64, mom[q]);
-                    }
+                    };
+                    group(std::false_type{});
+                    group(std::true_type{});
+                    nl += deg - i + 1;
                 }
             }
             __syncthreads();
@@ -389,11 +404,11 @@ __global__ __launch_bounds__(SR_NT, SR_WG_PER_CU) void adjoint_r_sep_kernel(SepR
     float* en = gt + (SR_GLOBAL_G ? 0 : RA * CP);       // [RA][CP] E_n tile
     float* ce = en + RA * CP;                           // [SR_TH][CP] CE_i
 
-    const acptr<double> f1d = (acptr<double>)a.f1d;
-    const acptr<int> fam = (acptr<int>)a.fam;
-    const acptr<double> coefd = (acptr<double>)a.coefd;
+    const cptr<double> f1d = (cptr<double>)a.f1d;
+    const cptr<int> fam = (cptr<int>)a.fam;
+    const cptr<double> coefd = (cptr<double>)a.coefd;
     const int tid = threadIdx.x;
-    const int t = sep_xcd_remap_r(blockIdx.x, a.n_tiles);
+    const int t = sep_xcd_remap(blockIdx.x, a.n_tiles);
     const int X0 = (t % a.tiles_x) * SR_TW, Y0 = (t / a.tiles_x) * SR_TH;
     const int DS1 = a.d_s + 1;
 
@@ -411,7 +426,7 @@ __global__ __launch_bounds__(SR_NT, SR_WG_PER_CU) void adjoint_r_sep_kernel(SepR
 
     for (int g = 0; g < a.G_fam; ++g) {
         const int deg = fam[2 * g], base = fam[2 * g + 1];
-        const acptr<double> fg = f1d + (size_t)g * kSepMaxFactors * K;
+        const cptr<double> fg = f1d + (size_t)g * kSepMaxFactors * K;
         for (int i = 0; i <= deg; ++i) {
             double cacc[TPT][SR_RPT];
 #pragma unroll
@@ -420,7 +435,7 @@ __global__ __launch_bounds__(SR_NT, SR_WG_PER_CU) void adjoint_r_sep_kernel(SepR
                 for (int o = 0; o < SR_RPT; ++o) cacc[tk][o] = 0.0;
             for (int j = 0; j + i <= deg; ++j) {
                 const int n = base + (i + j) * (i + j + 1) / 2 + j;
-                const acptr<double> an = coefd + (size_t)n * a.M;
+                const cptr<double> an = coefd + (size_t)n * a.M;
                 __syncthreads();   // previous E_n / cyt consumed (and G staged)
                 // coefficients of c_n in yh for every staged column
                 for (int e = tid; e < CA * DS1; e += SR_NT) {
@@ -452,7 +467,7 @@ __global__ __launch_bounds__(SR_NT, SR_WG_PER_CU) void adjoint_r_sep_kernel(SepR
                 }
                 __syncthreads();
                 // column correlation with f_j, accumulated over j
-                const acptr<double> f = fg + (size_t)j * K;
+                const cptr<double> f = fg + (size_t)j * K;
 #pragma unroll
                 for (int tk = 0; tk < TPT; ++tk) {
                     const int task = tid + tk * SR_NT;
@@ -482,7 +497,7 @@ __global__ __launch_bounds__(SR_NT, SR_WG_PER_CU) void adjoint_r_sep_kernel(SepR
             }
             __syncthreads();
             {
-                const acptr<double> f = fg + (size_t)i * K;
+                const cptr<double> f = fg + (size_t)i * K;
                 double win[WB];
 #pragma unroll
                 for (int s = 0; s < WB; ++s) win[s] = (double)ce[rr * CP + q8 + s];
