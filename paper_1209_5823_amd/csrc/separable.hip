@@ -264,13 +264,17 @@ __global__ __launch_bounds__(1024) void sep_prep_kernel(const float* __restrict_
             const int n = i / kSepCoefPad, m = i - n * kSepCoefPad;
             if (n < N) coefp[i] = m < M ? (double)coef[n * M + m] : 0.0;
         }
-    if ((int)threadIdx.x < kSepCoefPad) {
-        const int m = threadIdx.x;
-        double g = 0.0;
+    // gamma_m: one wave per term, the lanes over the bases, summed across the wave
+    const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    for (int m = wave; m < kSepCoefPad; m += 1024 / 64) {
+        double v = 0.0;
         if (m < M)
-            for (int n = 0; n < N; ++n) g = fma((double)coef[n * M + m], beta[n], g);
-        if (m < M) gamma[m] = g;
-        if (coefp) coefp[(size_t)N * kSepCoefPad + m] = g;
+            for (int n = ln; n < N; n += 64) v = fma((double)coef[n * M + m], beta[n], v);
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (ln == 0) {
+            if (m < M) gamma[m] = v;
+            if (coefp) coefp[(size_t)N * kSepCoefPad + m] = v;
+        }
     }
 }
 
