@@ -245,3 +245,67 @@ def test_separable_autograd_matches_dense_form(svc, orc):
     for k in range(2):
         g0, g1 = grads["basis"][k], grads["separable"][k]
         assert np.abs(g1 - g0).max() <= 1e-4 * np.abs(g0).max()
+
+
+# ------------------------------------------- the symmetric fold's variants ----
+# Families of degree 1..9: the column pass folds 1, 2, 3 or 4 factors of one
+# parity together and applies f_8 / f_9 tap by tap (degrees 8 and 9); spatial
+# degrees above 2 take the kernel instance with the long polynomial in yh.
+FOLD_CASES = {
+    # name: (H, W, h, sigmas, degrees, d_s, frame)
+    "degree9": (70, 100, 8, (2.0,), (9,), 2, None),
+    "degree8_and_1": (61, 90, 5, (1.5, 3.0), (8, 1), 1, None),
+    "degree7_ds4": (64, 70, 6, (1.8,), (7,), 4, None),
+    "degree5_3_ds3_h15": (80, 75, 15, (2.5, 5.0), (5, 3), 3, (9, 40, 400, 300)),
+    "degree1_ds0": (33, 47, 2, (1.0,), (1,), 0, None),
+}
+
+
+@pytest.mark.parametrize("name", list(FOLD_CASES))
+def test_separable_fold_variants(svc, orc, name):
+    case = FOLD_CASES[name]
+    H, W, h, sig, deg, d_s, frame = case
+    R, I, a = _edge_inputs(name, case)
+    B = orc.basis(h, sig, deg)
+    Dref = orc.difference(R, I, h, B, d_s, a, frame=frame)
+    say("separable fold", name, (H, W, h, len(B), d_s))
+    D = run_difference(svc, R, I, a, h, sig, deg, d_s, form="separable", frame=frame)
+    mx, rms = err_stats(D, Dref)
+    say("  max %.3e rms %.3e" % (mx, rms))
+    assert mx <= TOL_FP32
+
+
+@pytest.mark.parametrize("name", list(FOLD_CASES))
+def test_separable_fold_variants_adjoint_a(svc, orc, name):
+    case = FOLD_CASES[name]
+    H, W, h, sig, deg, d_s, frame = case
+    R, I, a = _edge_inputs(name, case)
+    G = synth.uniform_image(H, W, seed=23, lo=-40.0, hi=40.0)
+    B = orc.basis(h, sig, deg)
+    ga_ref = orc.grad_a(R, h, B, d_s, G, frame=frame)
+    sa = orc.grad_a(np.abs(R), h, np.abs(B), 0, np.abs(G), frame=frame)[:, :1]
+    say("separable fold, adjoint in a", name)
+    with svc.Plan(H, W, h, sig, deg, d_s, form="separable", frame=frame,
+                  pedestal=synth.SKY_LEVEL) as plan:
+        _, ga = plan.backward(to_dev(R), to_dev(a), to_dev(G), want_gR=False)
+        ga = to_host(ga)
+    e = np.abs(ga - ga_ref)
+    say("  max err %.3e" % e.max())
+    assert np.all(e <= 2e-5 * sa + 1e-9)
+
+
+@pytest.mark.parametrize("name", ["degree9", "degree8_and_1", "degree5_3_ds3_h15"])
+def test_separable_fold_variants_normal_matrix(svc, orc, name):
+    # the T-only instance of the contraction writes the basis responses
+    case = FOLD_CASES[name]
+    H, W, h, sig, deg, d_s, frame = case
+    R, I, a = _edge_inputs(name, case)
+    B = orc.basis(h, sig, deg)
+    JtJ_ref, _ = orc.normal_equations(R, None, h, B, d_s, frame=frame)
+    say("separable fold, normal matrix", name)
+    with svc.Plan(H, W, h, sig, deg, d_s, form="separable", frame=frame,
+                  pedestal=synth.SKY_LEVEL) as plan:
+        JtJ = to_host(plan.normal_matrix(to_dev(R)))
+    err = np.abs(JtJ - JtJ_ref).max() / np.abs(JtJ_ref).max()
+    say("  rel err %.3e" % err)
+    assert err <= 2e-6
