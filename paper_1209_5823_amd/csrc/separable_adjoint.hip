@@ -49,28 +49,25 @@ struct SepAdjArgs {
 };
 
 // V[slot][q][lane] += sum_o G T yh^q over a thread's SA_RPT rows, q <= d_s
-// (float64 LDS atomics: the 8 waves of a workgroup share a column).
-__device__ __forceinline__ void sa_moments(const SepAdjArgs& a, double* V, int slot, int DS1, int lane,
+// (float64 LDS atomics: the 8 waves of a workgroup share a column).  The
+// loop over q runs to the plan's degree; each step multiplies the row terms
+// by yh once.
+__device__ __forceinline__ void sa_moments(double* V, int slot, int DS1, int lane,
                                            const double (&gv)[SA_RPT], const double (&yv)[SA_RPT],
                                            const double (&tv)[SA_RPT]) {
-    double mom[kMaxSpatialDegree + 1];
+    double t[SA_RPT];
 #pragma unroll
-    for (int q = 0; q <= kMaxSpatialDegree; ++q) mom[q] = 0.0;
-#pragma unroll
-    for (int o = 0; o < SA_RPT; ++o) {
-        double pw = gv[o] * tv[o];
-#pragma unroll
-        for (int q = 0; q <= kMaxSpatialDegree; ++q) {
-            if (q <= a.d_s) {
-                mom[q] += pw;
-                pw *= yv[o];
-            }
-        }
-    }
+    for (int o = 0; o < SA_RPT; ++o) t[o] = gv[o] * tv[o];
     double* vrow = V + (size_t)slot * DS1 * 64 + lane;
+#pragma unroll 1
+    for (int q = 0; q < DS1; ++q) {
+        double m = t[0];
 #pragma unroll
-    for (int q = 0; q <= kMaxSpatialDegree; ++q)
-        if (q <= a.d_s) atomicAdd(vrow + q * 64, mom[q]);
+        for (int o = 1; o < SA_RPT; ++o) m += t[o];
+        atomicAdd(vrow + q * 64, m);
+#pragma unroll
+        for (int o = 0; o < SA_RPT; ++o) t[o] *= yv[o];
+    }
 }
 
 template <int H>
@@ -172,24 +169,10 @@ __global__ __launch_bounds__(64 * SA_NW) void adjoint_a_sep_kernel(SepAdjArgs a)
                     yv[o] = a.sy * y + a.oy;
                 }
                 if (first) {
-                    double mom[kMaxSpatialDegree + 1];
+                    double ones[SA_RPT];
 #pragma unroll
-                    for (int q = 0; q <= kMaxSpatialDegree; ++q) mom[q] = 0.0;
-#pragma unroll
-                    for (int o = 0; o < SA_RPT; ++o) {
-                        double pw = gv[o];
-#pragma unroll
-                        for (int q = 0; q <= kMaxSpatialDegree; ++q) {
-                            if (q <= a.d_s) {
-                                mom[q] += pw;
-                                pw *= yv[o];
-                            }
-                        }
-                    }
-                    double* vrow = V + (size_t)nn * DS1 * 64 + lane;
-#pragma unroll
-                    for (int q = 0; q <= kMaxSpatialDegree; ++q)
-                        if (q <= a.d_s) atomicAdd(vrow + q * 64, mom[q]);
+                    for (int o = 0; o < SA_RPT; ++o) ones[o] = 1.0;
+                    sa_moments(V, nn, DS1, lane, gv, yv, ones);   // G P_m sums
                 }
                 int nl = 0;   // slot of basis (i, 0) in this round
                 for (int c = 0; c < nc; ++c) {
@@ -207,12 +190,12 @@ __global__ __launch_bounds__(64 * SA_NW) void adjoint_a_sep_kernel(SepAdjArgs a)
                             double tv[NF][SA_RPT];
                             fold_conv<H, NF, SA_RPT, par == 1>(col, fg + (size_t)par * K, tv);
 #pragma unroll
-                            for (int jj = 0; jj < NF; ++jj) sa_moments(a, V, nl + par + 2 * jj, DS1, lane, gv, yv, tv[jj]);
+                            for (int jj = 0; jj < NF; ++jj) sa_moments(V, nl + par + 2 * jj, DS1, lane, gv, yv, tv[jj]);
                         });
                         if (cnt > 4) {
                             double tv1[SA_RPT];
                             direct_conv<H, SA_RPT>(col, fg + (size_t)(par + 8) * K, tv1);
-                            sa_moments(a, V, nl + par + 8, DS1, lane, gv, yv, tv1);
+                            sa_moments(V, nl + par + 8, DS1, lane, gv, yv, tv1);
                         }
                     };
                     group(std::false_type{});
