@@ -111,6 +111,7 @@ struct svconv_plan {
     double* dSep1d = nullptr;           // separable factors (Gaussian plans with h >= 1)
     int* dSepFam = nullptr;             // [2 G] degree, first basis
     double* dSepCoef = nullptr;         // [N + 1][kSepCoefPad] padded coefficients and gamma
+    uint16_t* dSepFrag = nullptr;       // matrix-core Toeplitz fragments of the factors (fp16, bf16)
 
     // device tables (basis form, fixed per plan)
     float* dF32 = nullptr;              // [N][k][k] correlation-oriented basis, float32
@@ -163,6 +164,9 @@ int launch_contract_lowp(const ContractArgs& a, const uint16_t* frag, int nb, in
 int launch_contract_sep(SepArgs a, hipStream_t s);
 int launch_sep_prep(const float* coef, const double* beta, int N, int M, double* coefd,
                     double* gamma, double* coefp, hipStream_t s);
+size_t sep_mma_frag_entries(int G);
+int build_sep_mma_fragments(const double* f1d, int G, int h, uint16_t* frag, hipStream_t s);
+int launch_contract_sep_mma(SepArgs a, const uint16_t* frag, int precision, hipStream_t s);
 int launch_adjoint_a_sep(svconv_plan* p, const float* R, const float* G, double* ga);
 bool sep_adjoint_supported(const svconv_plan* p);
 int launch_adjoint_r_sep(svconv_plan* p, const float* a32, const float* G, float* gR);

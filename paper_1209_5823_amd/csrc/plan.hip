@@ -71,7 +71,7 @@ static int dalloc(T** p, size_t count, const char* what) {
 }
 
 static void free_plan(svconv_plan* p) {
-    void* ptrs[] = {p->dSep1d, p->dSepFam, p->dSepCoef,
+    void* ptrs[] = {p->dSep1d, p->dSepFam, p->dSepCoef, p->dSepFrag,
                     p->dF32,   p->dF64,   p->dBeta,   p->dFragF32, p->dFragLoB, p->dFragLoH,
                     p->dScaleB, p->dScaleH, p->dFt32, p->dBetaT, p->dFragT32, p->dFragTB,  p->dFragTH,
                     p->dScaleT, p->dQpart, p->dQ,    p->dGrad,    p->dVec,     p->dStatus,
@@ -199,6 +199,10 @@ static int finish_plan(svconv_plan* p, svconv_plan** out) {
         if (!st) st = dalloc(&p->dSepCoef, (size_t)(p->N + 1) * kSepCoefPad, "separable coefficients");
         if (!st) st = hip_status(hipMemcpy(p->dSep1d, f1d.data(), f1d.size() * 8, hipMemcpyHostToDevice), "upload");
         if (!st) st = hip_status(hipMemcpy(p->dSepFam, fam.data(), fam.size() * 4, hipMemcpyHostToDevice), "upload");
+        if (!st && h <= 15) {
+            st = dalloc(&p->dSepFrag, sep_mma_frag_entries(G), "separable matrix-core fragments");
+            if (!st) st = build_sep_mma_fragments(p->dSep1d, G, h, p->dSepFrag, nullptr);
+        }
     }
     if (!st && p->N <= kMaxFilters) {
         st = build_f32_fragments(p->dF32, p->N, k, p->dFragF32, nullptr);
@@ -259,6 +263,11 @@ int run_forward(svconv_plan* p, const float* R, const float* I, const float* a, 
         sa.gamma = gamma;
         sa.coefp = p->dSepCoef;
         sa.gammap = p->dSepCoef + (size_t)p->N * kSepCoefPad;
+        // the split 16-bit precisions take the matrix-core passes, the others float64
+        if (p->precision == SVCONV_FP16X3 || p->precision == SVCONV_BF16X3 || p->precision == SVCONV_FP16X2) {
+            if (!p->dSepFrag) return fail(SVCONV_EUNSUPPORTED, "separable matrix-core form needs half-width <= 15");
+            return launch_contract_sep_mma(sa, p->dSepFrag, p->precision, p->stream);
+        }
         return launch_contract_sep(sa, p->stream);
     }
     if (p->form == SVCONV_FORM_BASIS) {

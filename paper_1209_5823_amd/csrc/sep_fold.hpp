@@ -81,4 +81,22 @@ __device__ __forceinline__ void direct_conv(const double (&x)[NO + 2 * H], cptr<
     }
 }
 
+// Cy[q] = sum_ie c[m(ie, q)] xh^ie for q <= DSM, the coefficients of a
+// spatial polynomial sum_m c_m P_m in yh at column x; the terms m are ordered
+// by total degree, and within one by falling power of xh, and c is padded
+// with zeros past the plan's terms, so every instance reads all its terms.
+template <int DSM>
+__device__ __forceinline__ void coef_in_x(cptr<double> c, const double (&xpow)[DSM + 1],
+                                          double (&cy)[DSM + 1]) {
+#pragma unroll
+    for (int q = 0; q <= DSM; ++q) cy[q] = 0.0;
+    int m = 0;
+#pragma unroll
+    for (int tt = 0; tt <= DSM; ++tt) {
+#pragma unroll
+        for (int ie = tt; ie >= 0; --ie) cy[tt - ie] = fma(c[m + tt - ie], xpow[ie], cy[tt - ie]);
+        m += tt + 1;
+    }
+}
+
 }  // namespace svc

@@ -54,24 +54,6 @@ constexpr int SEP_CHUNK = SEP_ROUND;       // row factors per phase A / phase B 
 // a round folds at most 4 factors together
 static_assert(SEP_CHUNK == 2 || SEP_CHUNK == 4, "SEP_ROUND must be 2 or 4");
 
-// Cy[q] = sum_ie c[m(ie, q)] xh^ie for q <= DSM, the coefficients of a
-// spatial polynomial sum_m c_m P_m in yh at column x; the terms m are ordered
-// by total degree, and within one by falling power of xh, and c is padded
-// with zeros past the plan's terms, so every instance reads all its terms.
-template <int DSM>
-__device__ __forceinline__ void coef_in_x(cptr<double> c, const double (&xpow)[DSM + 1],
-                                          double (&cy)[DSM + 1]) {
-#pragma unroll
-    for (int q = 0; q <= DSM; ++q) cy[q] = 0.0;
-    int m = 0;
-#pragma unroll
-    for (int tt = 0; tt <= DSM; ++tt) {
-#pragma unroll
-        for (int ie = tt; ie >= 0; --ie) cy[tt - ie] = fma(c[m + tt - ie], xpow[ie], cy[tt - ie]);
-        m += tt + 1;
-    }
-}
-
 // One basis response T_n on a thread's SEP_RPT rows: in the T-only mode
 // written out as T_n + s beta_n, else D += c_n T_n with
 // c_n(x, y) = sum_q Cy[q] yh^q (Horner in yh; DSM bounds the spatial degree

@@ -1,0 +1,305 @@
+// Separable form of the Gaussian-basis contraction on the matrix cores.
+//
+// The same factorisation as the float64 form (Sec. 2, Eq. 2 with separable
+// Gaussian bases, B_n(u,v) = f_i(u) f_j(v)): a row pass per factor f_i, then
+// a column pass per basis with f_j.  Each one-dimensional pass over a block
+// of 16 outputs is a product with a banded Toeplitz matrix,
+//   out[o] = sum_k F[o][k] x[k],   F[o][k] = f(o + 2h - k),  k in [0, 64),
+// whose 64-long reduction covers the 16 + 2h samples the block needs (h <= 15
+// gives at most 46).  The Toeplitz fragments depend only on the factor, so a
+// per-plan table holds them in the lane order of v_mfma_f32_16x16x32_{f16,bf16}
+// (lane l: index l mod 16, reduction entries 8 (l / 16) + 0..7 of each
+// 32-long chunk), and the same values serve as the B operand of the row pass
+// (n = output column) and the A operand of the column pass (m = output row).
+//
+// Precision: 16-bit inputs, float32 accumulation, with hi + lo splits
+//   x = xh + xl, F = Fh + Fl (each rounded to nearest even),
+//   F x ~ Fh xh + Fh xl + Fl xh   (NT = 3; NT = 2 drops Fl xh),
+// for R - s (scaled by 1/4 in fp16, as in the dense low-precision form) and for
+// the row responses U between the passes.  The coefficient weighting, the
+// pedestal restore s sum_m gamma_m P_m and the sum over the bases run in
+// float64 on the vector units.
+//
+// Workgroup: 8 waves, output tile 64 x 64.  LDS: the staged tile as hi / lo
+// rows [96][120] (96 >= 64 + 2h rows; columns 0..111, zero past the halo) and,
+// per round of up to 3 row factors, the row responses column-major as hi / lo
+// [64][120] (rows 0..111; rows 96..111 stay zero), 138 KB.  A round: the row
+// pass (6 x 4 blocks of 16 x 16 per factor, spread over the waves), a barrier,
+// then the column pass, where wave w owns the 16-column block w mod 4 and the
+// two 16-row blocks 2 (w / 4), 2 (w / 4) + 1 for every basis of the round.
+#include "internal.hpp"
+#include "sep_fold.hpp"
+
+namespace svc {
+
+typedef float smm_f4 __attribute__((ext_vector_type(4)));
+typedef _Float16 smm_h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 smm_b8 __attribute__((ext_vector_type(8)));
+
+constexpr int SM_NW = 8;
+constexpr int SM_NT = 64 * SM_NW;
+constexpr int SM_RB = 6;                 // row blocks of the row pass
+constexpr int SM_XR = 16 * SM_RB;        // staged rows, >= 64 + 2h for h <= 15
+constexpr int SM_XC = 112;               // staged columns the 64-long windows reach
+constexpr int SM_UR = SM_XR + 16;        // row-response rows the column windows reach
+constexpr int SM_P = 120;                // row / column pitch in 16-bit elements: 15 x 16 B (odd)
+constexpr int SM_SLOTS = 3;              // row factors per round
+constexpr int SM_FRAG = 2 * 2 * 64 * 8;  // 16-bit entries of one factor's table: [chunk][hi/lo][lane][8]
+constexpr size_t SM_LDS = (size_t)(2 * SM_XR * SM_P + SM_SLOTS * 2 * 64 * SM_P) * sizeof(uint16_t);
+
+__device__ __forceinline__ uint32_t smm_f2h(float x) {
+    return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)x);
+}
+__device__ __forceinline__ float smm_h2f(uint32_t b) { return (float)__builtin_bit_cast(_Float16, (uint16_t)b); }
+__device__ __forceinline__ uint32_t smm_f2bf(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ float smm_bf2f(uint32_t b) { return __uint_as_float(b << 16); }
+
+template <bool FP16>
+__device__ __forceinline__ void smm_split(float x, uint32_t& hi, uint32_t& lo) {
+    if (FP16) {
+        hi = smm_f2h(x);
+        lo = smm_f2h(x - smm_h2f(hi));
+    } else {
+        hi = smm_f2bf(x);
+        lo = smm_f2bf(x - smm_bf2f(hi));
+    }
+}
+
+template <bool FP16>
+__device__ __forceinline__ smm_f4 smm_mfma(const uint4& a, const uint4& b, smm_f4 c) {
+    if constexpr (FP16) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(smm_h8, a),
+                                                      __builtin_bit_cast(smm_h8, b), c, 0, 0, 0);
+    } else {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(smm_b8, a),
+                                                       __builtin_bit_cast(smm_b8, b), c, 0, 0, 0);
+    }
+}
+
+// Toeplitz fragment tables of every factor, fp16 then bf16:
+// frag[p][g][e][chunk][hi/lo][lane][t] = split(f_e^(g)(n + 2h - k)), n = lane mod 16,
+// k = 32 chunk + 8 (lane / 16) + t, zero where n + 2h - k is outside [0, 2h].
+__global__ void sep_mma_frag_kernel(const double* __restrict__ f1d, int G, int h,
+                                    uint16_t* __restrict__ frag) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long per_factor = 2 * 64 * 8;             // [chunk][lane][t]
+    const long total = 2L * G * kSepMaxFactors * per_factor;
+    if (idx >= total) return;
+    const int t = (int)(idx & 7);
+    const int lane = (int)((idx >> 3) & 63);
+    const int chunk = (int)((idx >> 9) & 1);
+    const long ge = (idx >> 10) % ((long)G * kSepMaxFactors);
+    const int p = (int)((idx >> 10) / ((long)G * kSepMaxFactors));
+    const int k = 2 * h + 1;
+    const int n = lane & 15, kk = 32 * chunk + 8 * (lane >> 4) + t;
+    const int u = n + 2 * h - kk;
+    const float v = (u >= 0 && u < k) ? (float)f1d[ge * k + u] : 0.f;
+    uint32_t hi, lo;
+    if (p == 0) smm_split<true>(v, hi, lo);
+    else smm_split<false>(v, hi, lo);
+    uint16_t* dst = frag + ((size_t)p * G * kSepMaxFactors + ge) * SM_FRAG;
+    dst[((chunk * 2 + 0) * 64 + lane) * 8 + t] = (uint16_t)hi;
+    dst[((chunk * 2 + 1) * 64 + lane) * 8 + t] = (uint16_t)lo;
+}
+
+int build_sep_mma_fragments(const double* f1d, int G, int h, uint16_t* frag, hipStream_t s) {
+    const long total = 2L * G * kSepMaxFactors * 2 * 64 * 8;
+    hipLaunchKernelGGL(sep_mma_frag_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, f1d,
+                       G, h, frag);
+    return hip_status(hipGetLastError(), "sep_mma_frag_kernel");
+}
+
+size_t sep_mma_frag_entries(int G) { return 2 * (size_t)G * kSepMaxFactors * SM_FRAG; }
+
+// One factor's fragments for this lane: f[chunk][hi/lo].
+__device__ __forceinline__ void smm_load_frag(const uint16_t* tab, int lane, uint4 (&f)[2][2]) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int hl = 0; hl < 2; ++hl)
+            f[c][hl] = *reinterpret_cast<const uint4*>(tab + ((c * 2 + hl) * 64 + lane) * 8);
+}
+
+template <bool FP16, int NT, int DSM>
+__global__ __launch_bounds__(SM_NT) void contract_sepmm_kernel(SepArgs a, const uint16_t* __restrict__ frag) {
+    extern __shared__ uint4 smm_lds[];
+    uint16_t* xs = reinterpret_cast<uint16_t*>(smm_lds);   // [2][SM_XR][SM_P]
+    uint16_t* ut = xs + 2 * SM_XR * SM_P;                     // [SM_SLOTS][2][64][SM_P]
+
+    const int h = a.h;
+    const int RA = 64 + 2 * h, CA = 64 + 2 * h;
+    const float xscale = FP16 ? 0.25f : 1.f;
+    const double unscale = FP16 ? 4.0 : 1.0;
+    const cptr<int> fam = as_const(a.fam);
+    const uint16_t* ftab = frag + (FP16 ? 0 : (size_t)a.G * kSepMaxFactors * SM_FRAG);
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int t = sep_xcd_remap(blockIdx.x, a.n_tiles);
+    const int X0 = (t % a.tiles_x) * 64;
+    const int Y0 = a.y_begin + (t / a.tiles_x) * 64;
+    const int y_end = min(a.H, a.y_begin + a.n_rows);
+
+    // stage (R - s) * xscale as hi / lo; R = 0 outside the image; zero past the halo
+    for (int q = tid; q < SM_XR * SM_XC; q += SM_NT) {
+        const int r = q / SM_XC, c = q - r * SM_XC;
+        float v = 0.f;
+        if (r < RA && c < CA) {
+            const int gy = Y0 - h + r, gx = X0 - h + c;
+            const float x = (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) ? a.X[(size_t)gy * a.W + gx] : 0.f;
+            v = (x - a.ped) * xscale;
+        }
+        uint32_t hi, lo;
+        smm_split<FP16>(v, hi, lo);
+        xs[r * SM_P + c] = (uint16_t)hi;
+        xs[(SM_XR + r) * SM_P + c] = (uint16_t)lo;
+    }
+    // row-response rows SM_XR .. SM_UR - 1 are read by the column windows and never written
+    for (int q = tid; q < SM_SLOTS * 2 * 64 * (SM_UR - SM_XR); q += SM_NT) {
+        const int col = q / (SM_UR - SM_XR), rr = q - col * (SM_UR - SM_XR);
+        ut[col * SM_P + SM_XR + rr] = 0;
+    }
+
+    // column-pass ownership: 16-column block cbB, row blocks rb0, rb0 + 1
+    const int g4 = lane >> 4, j16 = lane & 15;
+    const int cbB = w & 3, rb0 = 2 * (w >> 2);
+    const int xl = 16 * cbB + j16;          // tile column of this lane's outputs
+    const int x = X0 + xl;
+    const double xh = a.sx * x + a.ox;
+    double xpow[DSM + 1];
+    xpow[0] = 1.0;
+#pragma unroll
+    for (int q = 1; q <= DSM; ++q) xpow[q] = xpow[q - 1] * xh;
+    double yh[2][4], dacc[2][4];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            yh[b][e] = a.sy * (Y0 + 16 * (rb0 + b) + 4 * g4 + e) + a.oy;
+            dacc[b][e] = 0.0;
+        }
+    const cptr<double> coefp = as_const(a.coefp);
+
+    for (int g = 0; g < a.G; ++g) {
+        const int deg = fam[2 * g], base = fam[2 * g + 1];
+        const uint16_t* fg = ftab + (size_t)g * kSepMaxFactors * SM_FRAG;
+        for (int i0 = 0; i0 <= deg; i0 += SM_SLOTS) {
+            const int nc = min(SM_SLOTS, deg + 1 - i0);
+            __syncthreads();   // tile staged / previous round's row responses consumed
+            // row pass: U_e[r][x'] for the round's factors, blocks of 16 rows x 16 columns
+            for (int item = w; item < nc * SM_RB * 4; item += SM_NW) {
+                const int slot = item / (SM_RB * 4), blk = item - slot * (SM_RB * 4);
+                const int rb = blk >> 2, cb = blk & 3;
+                uint4 tf[2][2];
+                smm_load_frag(fg + (size_t)(i0 + slot) * SM_FRAG, lane, tf);
+                smm_f4 acc = {0.f, 0.f, 0.f, 0.f};
+                const int r = 16 * rb + j16;
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int col = 16 * cb + 32 * c + 8 * g4;
+                    const uint4 dh = *reinterpret_cast<const uint4*>(xs + r * SM_P + col);
+                    const uint4 dl = *reinterpret_cast<const uint4*>(xs + (SM_XR + r) * SM_P + col);
+                    acc = smm_mfma<FP16>(dh, tf[c][0], acc);
+                    if (NT >= 2) acc = smm_mfma<FP16>(dl, tf[c][0], acc);
+                    if (NT >= 3) acc = smm_mfma<FP16>(dh, tf[c][1], acc);
+                }
+                // lane (g4, j16) holds U at rows 16 rb + 4 g4 + e, column 16 cb + j16
+                uint32_t hv[4], lv[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) smm_split<FP16>(acc[e], hv[e], lv[e]);
+                uint16_t* dst = ut + ((size_t)(slot * 2) * 64 + 16 * cb + j16) * SM_P + 16 * rb + 4 * g4;
+                *reinterpret_cast<uint2*>(dst) = make_uint2(hv[0] | (hv[1] << 16), hv[2] | (hv[3] << 16));
+                *reinterpret_cast<uint2*>(dst + 64 * SM_P) = make_uint2(lv[0] | (lv[1] << 16), lv[2] | (lv[3] << 16));
+            }
+            __syncthreads();
+            // column pass: T_n = f_j (x)_y U_i on this wave's two blocks, then D += c_n T_n
+            for (int c = 0; c < nc; ++c) {
+                const int i = i0 + c;
+                uint4 ub[2][2][2];   // [block][chunk][hi/lo]
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int ch = 0; ch < 2; ++ch)
+#pragma unroll
+                        for (int hl = 0; hl < 2; ++hl)
+                            ub[b][ch][hl] = *reinterpret_cast<const uint4*>(
+                                ut + ((size_t)(c * 2 + hl) * 64 + xl) * SM_P + 16 * (rb0 + b) + 32 * ch + 8 * g4);
+                for (int j = 0; j + i <= deg; ++j) {
+                    const int n = base + (i + j) * (i + j + 1) / 2 + j;
+                    uint4 tf[2][2];
+                    smm_load_frag(fg + (size_t)j * SM_FRAG, lane, tf);
+                    smm_f4 acc[2];
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) acc[b] = smm_f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int ch = 0; ch < 2; ++ch)
+#pragma unroll
+                        for (int b = 0; b < 2; ++b) {
+                            acc[b] = smm_mfma<FP16>(tf[ch][0], ub[b][ch][0], acc[b]);
+                            if (NT >= 2) acc[b] = smm_mfma<FP16>(tf[ch][0], ub[b][ch][1], acc[b]);
+                            if (NT >= 3) acc[b] = smm_mfma<FP16>(tf[ch][1], ub[b][ch][0], acc[b]);
+                        }
+                    // c_n(x, y) = sum_q Cy[q] yh^q, Cy from the padded coefficients
+                    double cy[DSM + 1];
+                    coef_in_x<DSM>(coefp + (size_t)n * kSepCoefPad, xpow, cy);
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            double cn = cy[DSM];
+#pragma unroll
+                            for (int q = DSM - 1; q >= 0; --q) cn = fma(cn, yh[b][e], cy[q]);
+                            dacc[b][e] = fma(cn, (double)acc[b][e], dacc[b][e]);
+                        }
+                }
+            }
+        }
+    }
+    if (x < a.W) {
+        // pedestal restore s sum_m gamma_m P_m, then D = sum_n c_n T_n - I
+        double cy[DSM + 1];
+        coef_in_x<DSM>(as_const(a.gammap), xpow, cy);
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int y = Y0 + 16 * (rb0 + b) + 4 * g4 + e;
+                if (y < y_end) {
+                    double pg = cy[DSM];
+#pragma unroll
+                    for (int q = DSM - 1; q >= 0; --q) pg = fma(pg, yh[b][e], cy[q]);
+                    const size_t idx = (size_t)y * a.W + x;
+                    const double iv = a.I ? (double)a.I[idx] : 0.0;
+                    a.out[idx] = (float)(fma(dacc[b][e], unscale, (double)a.ped * pg) - iv);
+                }
+            }
+    }
+}
+
+template <bool FP16, int NT>
+static int launch_sepmm_p(const SepArgs& a, const uint16_t* frag, hipStream_t s) {
+    if (a.d_s <= 2)
+        hipLaunchKernelGGL((contract_sepmm_kernel<FP16, NT, 2>), dim3(a.n_tiles), dim3(SM_NT), SM_LDS, s, a, frag);
+    else
+        hipLaunchKernelGGL((contract_sepmm_kernel<FP16, NT, kMaxSpatialDegree>), dim3(a.n_tiles), dim3(SM_NT),
+                           SM_LDS, s, a, frag);
+    return hip_status(hipGetLastError(), "contract_sepmm_kernel");
+}
+
+int launch_contract_sep_mma(SepArgs a, const uint16_t* frag, int precision, hipStream_t s) {
+    if (a.h < 1 || a.h > 15) return fail(SVCONV_EUNSUPPORTED, "separable form needs 1 <= half-width <= 15");
+    if (a.tout) return fail(SVCONV_EINVAL, "the matrix-core separable kernel has no T-only mode");
+    a.tiles_x = (a.W + 63) / 64;
+    a.n_tiles = a.tiles_x * ((a.n_rows + 63) / 64);
+    switch (precision) {
+        case SVCONV_FP16X3: return launch_sepmm_p<true, 3>(a, frag, s);
+        case SVCONV_BF16X3: return launch_sepmm_p<false, 3>(a, frag, s);
+        case SVCONV_FP16X2: return launch_sepmm_p<true, 2>(a, frag, s);
+        default: return fail(SVCONV_EINVAL, "no matrix-core separable kernel for this precision");
+    }
+}
+
+}  // namespace svc

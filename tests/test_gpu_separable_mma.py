@@ -1,0 +1,108 @@
+"""GPU parity of the separable form on the matrix cores (the split 16-bit
+precisions): the row and column passes of the Gaussian factors as banded
+Toeplitz products, against the FP64 oracle's direct two-dimensional
+convolution, at the matrix-core forms' bounds (1e-2 sigma_sky; fp16x2 at its
+measured level)."""
+
+import numpy as np
+import pytest
+
+import synth
+from tests.helpers import TOL_MFMA, say, err_stats, sample_pixels, to_dev, to_host
+from tests.test_gpu_forward import EDGE_CASES, _edge_inputs, run_difference, lowp_tol, LOWP
+from tests.test_gpu_separable import FOLD_CASES
+
+pytestmark = pytest.mark.gpu
+
+C0 = synth.WORKLOADS["c0"]
+
+
+@pytest.mark.parametrize("precision", LOWP)
+@pytest.mark.parametrize("pedestal", [0.0, 1000.0])
+def test_c0_full_frame(svc, orc, precision, pedestal):
+    R, a = synth.workload_inputs(C0)
+    B = orc.basis(C0.half_width, C0.sigmas, C0.degrees)
+    C = orc.convolve(R, C0.half_width, B, C0.spatial_degree, a)
+    I = (C + 10.0).astype(np.float32)
+    Dref = C - I.astype(np.float64)
+    say("separable mma c0", precision, pedestal)
+    D = run_difference(svc, R, I, a, C0.half_width, C0.sigmas, C0.degrees, C0.spatial_degree,
+                       precision=precision, form="separable", pedestal=pedestal)
+    mx, rms = err_stats(D, Dref)
+    say("  max %.3e rms %.3e (%.2e sigma)" % (mx, rms, mx / np.sqrt(1000)))
+    assert mx <= lowp_tol(precision)
+
+
+@pytest.mark.parametrize("precision", LOWP)
+def test_c2_crops(svc, orc, precision):
+    # 512 x 512 crops of the 2048 x 4096 chip: the centre and the brightest star
+    wl = synth.WORKLOADS["c2"]
+    R, a = synth.workload_inputs(wl)
+    I = synth.second_image(wl)
+    B = orc.basis(wl.half_width, wl.sigmas, wl.degrees)
+    yb, xb = np.unravel_index(np.argmax(R), R.shape)
+    crops = [(768, 1792), (int(np.clip(yb - 256, 0, wl.height - 512)),
+                           int(np.clip(xb - 256, 0, wl.width - 512)))]
+    for (y0, x0) in crops:
+        Rc = np.ascontiguousarray(R[y0:y0 + 512, x0:x0 + 512])
+        Ic = np.ascontiguousarray(I[y0:y0 + 512, x0:x0 + 512])
+        frame = (x0, y0, wl.width, wl.height)
+        Dref = orc.difference(Rc, Ic, wl.half_width, B, wl.spatial_degree, a, frame=frame)
+        say("separable mma c2 crop", precision, (y0, x0))
+        D = run_difference(svc, Rc, Ic, a, wl.half_width, wl.sigmas, wl.degrees, wl.spatial_degree,
+                           precision=precision, form="separable", frame=frame, pedestal=synth.SKY_LEVEL)
+        mx, rms = err_stats(D, Dref)
+        say("  max %.3e rms %.3e (%.2e sigma)" % (mx, rms, mx / np.sqrt(1000)))
+        assert mx <= lowp_tol(precision)
+
+
+@pytest.mark.parametrize("precision", ["fp16x3", "bf16x3"])
+@pytest.mark.parametrize("name", ["h1_ragged", "nb3_degree3", "c1_kernel_ragged_crop", "c3_kernel_degree4",
+                                  "max_filters_64", "max_spatial_degree_6", "single_row", "single_column",
+                                  "all_border_8x8", "kernel_larger_than_image"])
+def test_edge_cases(svc, orc, name, precision):
+    case = EDGE_CASES[name]
+    H, W, h, sig, deg, d_s, frame = case
+    R, I, a = _edge_inputs(name, case)
+    B = orc.basis(h, sig, deg)
+    Dref = orc.difference(R, I, h, B, d_s, a, frame=frame)
+    say("separable mma edge", name, precision)
+    D = run_difference(svc, R, I, a, h, sig, deg, d_s, precision=precision, form="separable",
+                       frame=frame, pedestal=synth.SKY_LEVEL)
+    mx, rms = err_stats(D, Dref)
+    say("  max %.3e rms %.3e" % (mx, rms))
+    assert mx <= TOL_MFMA
+
+
+@pytest.mark.parametrize("name", list(FOLD_CASES))
+def test_high_degree_families(svc, orc, name):
+    case = FOLD_CASES[name]
+    H, W, h, sig, deg, d_s, frame = case
+    R, I, a = _edge_inputs(name, case)
+    B = orc.basis(h, sig, deg)
+    Dref = orc.difference(R, I, h, B, d_s, a, frame=frame)
+    say("separable mma family", name)
+    D = run_difference(svc, R, I, a, h, sig, deg, d_s, precision="fp16x3", form="separable",
+                       frame=frame, pedestal=synth.SKY_LEVEL)
+    mx, rms = err_stats(D, Dref)
+    say("  max %.3e rms %.3e" % (mx, rms))
+    assert mx <= TOL_MFMA
+
+
+@pytest.mark.parametrize("precision", ["fp16x3", "bf16x3"])
+def test_full_chip_sampled(svc, orc, precision):
+    # the 2048 x 4096 chip at full size in the launch configuration the bench
+    # times, checked on sampled pixels (and the brightest ones) against the oracle
+    wl = synth.WORKLOADS["c1"]
+    R, a = synth.workload_inputs(wl)
+    I = synth.second_image(wl)
+    B = orc.basis(wl.half_width, wl.sigmas, wl.degrees)
+    say("separable mma c1 full size", precision)
+    D = run_difference(svc, R, I, a, wl.half_width, wl.sigmas, wl.degrees, wl.spatial_degree,
+                       precision=precision, form="separable", pedestal=synth.SKY_LEVEL)
+    xs, ys = sample_pixels(wl.height, wl.width, 20000, seed=5, R=R, h=wl.half_width)
+    Dref = orc.convolve_at(R, wl.half_width, B, wl.spatial_degree, a, xs, ys) - I[ys, xs]
+    e = np.abs(D[ys, xs] - Dref)
+    say("  max %.3e (%.2e sigma) over %d pixels" % (e.max(), e.max() / np.sqrt(1000), len(ys)))
+    assert e.max() <= TOL_MFMA
+    assert np.all(np.isfinite(D))
