@@ -22,11 +22,11 @@
 //
 // Workgroup: 8 waves, output tile 64 x 64.  LDS: the staged tile as hi / lo
 // rows [96][120] (96 >= 64 + 2h rows; columns 0..111, zero past the halo) and,
-// per round of up to 3 row factors, the row responses column-major as hi / lo
-// [64][120] (rows 0..111; rows 96..111 stay zero), 138 KB.  A round: the row
-// pass (6 x 4 blocks of 16 x 16 per factor, spread over the waves), a barrier,
-// then the column pass, where wave w owns the 16-column block w mod 4 and the
-// two 16-row blocks 2 (w / 4), 2 (w / 4) + 1 for every basis of the round.
+// per round of SM_ROUND row factors, the row responses column-major as hi / lo
+// [64][120] (rows 0..111; rows 96..111 stay zero).  A round: the row pass
+// (6 x 4 blocks of 16 x 16 per factor, spread over the waves), a barrier, then
+// the column pass, where wave w owns the 16-column block w mod 4 and the two
+// 16-row blocks 2 (w / 4), 2 (w / 4) + 1 for every basis of the round.
 #include "internal.hpp"
 #include "sep_fold.hpp"
 
@@ -43,7 +43,16 @@ constexpr int SM_XR = 16 * SM_RB;        // staged rows, >= 64 + 2h for h <= 15
 constexpr int SM_XC = 112;               // staged columns the 64-long windows reach
 constexpr int SM_UR = SM_XR + 16;        // row-response rows the column windows reach
 constexpr int SM_P = 120;                // row / column pitch in 16-bit elements: 15 x 16 B (odd)
-constexpr int SM_SLOTS = 3;              // row factors per round
+// One row factor per round keeps the LDS at 77 KB, two workgroups per CU, and
+// the registers within four waves per SIMD (measured faster than three factors
+// per round at one workgroup per CU).
+#ifndef SM_ROUND
+#define SM_ROUND 1
+#endif
+#ifndef SM_MINW
+#define SM_MINW 4
+#endif
+constexpr int SM_SLOTS = SM_ROUND;       // row factors per round
 constexpr int SM_FRAG = 2 * 2 * 64 * 8;  // 16-bit entries of one factor's table: [chunk][hi/lo][lane][8]
 constexpr size_t SM_LDS = (size_t)(2 * SM_XR * SM_P + SM_SLOTS * 2 * 64 * SM_P) * sizeof(uint16_t);
 
@@ -125,7 +134,7 @@ __device__ __forceinline__ void smm_load_frag(const uint16_t* tab, int lane, uin
 }
 
 template <bool FP16, int NT, int DSM>
-__global__ __launch_bounds__(SM_NT) void contract_sepmm_kernel(SepArgs a, const uint16_t* __restrict__ frag) {
+__global__ __launch_bounds__(SM_NT, SM_MINW) void contract_sepmm_kernel(SepArgs a, const uint16_t* __restrict__ frag) {
     extern __shared__ uint4 smm_lds[];
     uint16_t* xs = reinterpret_cast<uint16_t*>(smm_lds);   // [2][SM_XR][SM_P]
     uint16_t* ut = xs + 2 * SM_XR * SM_P;                     // [SM_SLOTS][2][64][SM_P]
@@ -143,24 +152,29 @@ __global__ __launch_bounds__(SM_NT) void contract_sepmm_kernel(SepArgs a, const 
     const int Y0 = a.y_begin + (t / a.tiles_x) * 64;
     const int y_end = min(a.H, a.y_begin + a.n_rows);
 
-    // stage (R - s) * xscale as hi / lo; R = 0 outside the image; zero past the halo
-    for (int q = tid; q < SM_XR * SM_XC; q += SM_NT) {
-        const int r = q / SM_XC, c = q - r * SM_XC;
-        float v = 0.f;
-        if (r < RA && c < CA) {
-            const int gy = Y0 - h + r, gx = X0 - h + c;
-            const float x = (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) ? a.X[(size_t)gy * a.W + gx] : 0.f;
-            v = (x - a.ped) * xscale;
+    // stage (R - s) * xscale as hi / lo, two columns per thread (32-bit LDS
+    // writes); R = 0 outside the image; zero past the halo
+    for (int q = tid; q < SM_XR * (SM_XC / 2); q += SM_NT) {
+        const int r = q / (SM_XC / 2), c = 2 * (q - r * (SM_XC / 2));
+        uint32_t hi[2], lo[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            float v = 0.f;
+            if (r < RA && c + e < CA) {
+                const int gy = Y0 - h + r, gx = X0 - h + c + e;
+                const float x = (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) ? a.X[(size_t)gy * a.W + gx] : 0.f;
+                v = (x - a.ped) * xscale;
+            }
+            smm_split<FP16>(v, hi[e], lo[e]);
         }
-        uint32_t hi, lo;
-        smm_split<FP16>(v, hi, lo);
-        xs[r * SM_P + c] = (uint16_t)hi;
-        xs[(SM_XR + r) * SM_P + c] = (uint16_t)lo;
+        *reinterpret_cast<uint32_t*>(xs + r * SM_P + c) = hi[0] | (hi[1] << 16);
+        *reinterpret_cast<uint32_t*>(xs + (SM_XR + r) * SM_P + c) = lo[0] | (lo[1] << 16);
     }
-    // row-response rows SM_XR .. SM_UR - 1 are read by the column windows and never written
-    for (int q = tid; q < SM_SLOTS * 2 * 64 * (SM_UR - SM_XR); q += SM_NT) {
-        const int col = q / (SM_UR - SM_XR), rr = q - col * (SM_UR - SM_XR);
-        ut[col * SM_P + SM_XR + rr] = 0;
+    // row-response rows SM_XR .. SM_UR - 1 are read by the column windows and never
+    // written: zeroed once, 8 entries per write
+    for (int q = tid; q < SM_SLOTS * 2 * 64 * ((SM_UR - SM_XR) / 8); q += SM_NT) {
+        const int col = q / ((SM_UR - SM_XR) / 8), part = q - col * ((SM_UR - SM_XR) / 8);
+        *reinterpret_cast<uint4*>(ut + col * SM_P + SM_XR + 8 * part) = make_uint4(0u, 0u, 0u, 0u);
     }
 
     // column-pass ownership: 16-column block cbB, row blocks rb0, rb0 + 1
