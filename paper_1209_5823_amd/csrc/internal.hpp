@@ -84,6 +84,7 @@ struct SepArgs {
     const double* gamma;        // [M] sum_n coef[n][m] beta[n] (written by sep_prep)
     const double* coefp;        // [N][kSepCoefPad] coefd padded with zeros beyond M (sep_prep)
     const double* gammap;       // [kSepCoefPad] gamma padded likewise (sep_prep)
+    const float* coefpf;        // [N][kSepCoefPad] float32 copy of coefp (sep_prep)
     int M, d_s;
     double sx, ox, sy, oy;
     int tiles_x, n_tiles;
@@ -110,7 +111,8 @@ struct svconv_plan {
     std::vector<double> basis;          // host B[n][v+h][u+h], float64
     double* dSep1d = nullptr;           // separable factors (Gaussian plans with h >= 1)
     int* dSepFam = nullptr;             // [2 G] degree, first basis
-    double* dSepCoef = nullptr;         // [N + 1][kSepCoefPad] padded coefficients and gamma
+    double* dSepCoef = nullptr;         // [N + 1][kSepCoefPad] padded coefficients and gamma, then
+                                        // the coefficients again in float32 (same layout)
     uint16_t* dSepFrag = nullptr;       // matrix-core Toeplitz fragments of the factors (fp16, bf16)
 
     // device tables (basis form, fixed per plan)

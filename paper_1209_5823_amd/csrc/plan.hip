@@ -196,7 +196,8 @@ static int finish_plan(svconv_plan* p, svconv_plan** out) {
         }
         st = dalloc(&p->dSep1d, f1d.size(), "separable factors");
         if (!st) st = dalloc(&p->dSepFam, fam.size(), "separable families");
-        if (!st) st = dalloc(&p->dSepCoef, (size_t)(p->N + 1) * kSepCoefPad, "separable coefficients");
+        // float64 table then its float32 copy (the matrix-core epilogue)
+        if (!st) st = dalloc(&p->dSepCoef, 2 * (size_t)(p->N + 1) * kSepCoefPad, "separable coefficients");
         if (!st) st = hip_status(hipMemcpy(p->dSep1d, f1d.data(), f1d.size() * 8, hipMemcpyHostToDevice), "upload");
         if (!st) st = hip_status(hipMemcpy(p->dSepFam, fam.data(), fam.size() * 4, hipMemcpyHostToDevice), "upload");
         if (!st && h <= 15) {
@@ -263,6 +264,7 @@ int run_forward(svconv_plan* p, const float* R, const float* I, const float* a, 
         sa.gamma = gamma;
         sa.coefp = p->dSepCoef;
         sa.gammap = p->dSepCoef + (size_t)p->N * kSepCoefPad;
+        sa.coefpf = reinterpret_cast<const float*>(p->dSepCoef + (size_t)(p->N + 1) * kSepCoefPad);
         // the split 16-bit precisions take the matrix-core passes, the others float64
         if (p->precision == SVCONV_FP16X3 || p->precision == SVCONV_BF16X3 || p->precision == SVCONV_FP16X2) {
             if (!p->dSepFrag) return fail(SVCONV_EUNSUPPORTED, "separable matrix-core form needs half-width <= 15");

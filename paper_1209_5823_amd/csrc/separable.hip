@@ -234,18 +234,23 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
 // loads without conversions), gamma_m = sum_n coef[n][m] beta_n, and, when
 // coefp is given, both again with the stride kSepCoefPad and zeros beyond M
 // (coefp[N * kSepCoefPad + m] is gamma), so that the contraction reads a
-// fixed number of terms without branches.
+// fixed number of terms without branches, followed by a float32 copy of the
+// coefficients in the same layout (N + 1 rows, the last one zero).
 __global__ __launch_bounds__(1024) void sep_prep_kernel(const float* __restrict__ coef,
                                                         const double* __restrict__ beta, int N,
                                                         int M, double* __restrict__ coefd,
                                                         double* __restrict__ gamma,
                                                         double* __restrict__ coefp) {
     for (int i = threadIdx.x; i < N * M; i += 1024) coefd[i] = (double)coef[i];
-    if (coefp)
+    if (coefp) {
+        float* coefpf = reinterpret_cast<float*>(coefp + (size_t)(N + 1) * kSepCoefPad);
         for (int i = threadIdx.x; i < (N + 1) * kSepCoefPad; i += 1024) {
             const int n = i / kSepCoefPad, m = i - n * kSepCoefPad;
-            if (n < N) coefp[i] = m < M ? (double)coef[n * M + m] : 0.0;
+            const float c = (n < N && m < M) ? coef[n * M + m] : 0.f;
+            if (n < N) coefp[i] = (double)c;
+            coefpf[i] = c;
         }
+    }
     // gamma_m: one wave per term, the lanes over the bases, summed across the wave
     const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63;
     for (int m = wave; m < kSepCoefPad; m += 1024 / 64) {

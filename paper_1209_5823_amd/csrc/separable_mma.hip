@@ -16,9 +16,10 @@
 //   x = xh + xl, F = Fh + Fl (each rounded to nearest even),
 //   F x ~ Fh xh + Fh xl + Fl xh   (NT = 3; NT = 2 drops Fl xh),
 // for R - s (scaled by 1/4 in fp16, as in the dense low-precision form) and for
-// the row responses U between the passes.  The coefficient weighting, the
-// pedestal restore s sum_m gamma_m P_m and the sum over the bases run in
-// float64 on the vector units.
+// the row responses U between the passes.  The coefficient weighting c_n T_n
+// and the sum over the bases of one row factor run in float32 on the vector
+// units; the sum over the row factors, the pedestal restore
+// s sum_m gamma_m P_m and the subtraction of I in float64.
 //
 // Workgroup: 8 waves, output tile 64 x 64.  LDS: the staged tile as hi / lo
 // rows [96][120] (96 >= 64 + 2h rows; columns 0..111, zero past the halo) and,
@@ -183,19 +184,19 @@ __global__ __launch_bounds__(SM_NT, SM_MINW) void contract_sepmm_kernel(SepArgs 
     const int xl = 16 * cbB + j16;          // tile column of this lane's outputs
     const int x = X0 + xl;
     const double xh = a.sx * x + a.ox;
-    double xpow[DSM + 1];
-    xpow[0] = 1.0;
+    float xpf[DSM + 1], yhf[2][4];
+    xpf[0] = 1.f;
 #pragma unroll
-    for (int q = 1; q <= DSM; ++q) xpow[q] = xpow[q - 1] * xh;
-    double yh[2][4], dacc[2][4];
+    for (int q = 1; q <= DSM; ++q) xpf[q] = xpf[q - 1] * (float)xh;
+    double dacc[2][4];
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            yh[b][e] = a.sy * (Y0 + 16 * (rb0 + b) + 4 * g4 + e) + a.oy;
+            yhf[b][e] = (float)(a.sy * (Y0 + 16 * (rb0 + b) + 4 * g4 + e) + a.oy);
             dacc[b][e] = 0.0;
         }
-    const cptr<double> coefp = as_const(a.coefp);
+    const cptr<float> coefpf = as_const(a.coefpf);
 
     for (int g = 0; g < a.G; ++g) {
         const int deg = fam[2 * g], base = fam[2 * g + 1];
@@ -241,6 +242,12 @@ __global__ __launch_bounds__(SM_NT, SM_MINW) void contract_sepmm_kernel(SepArgs 
                         for (int hl = 0; hl < 2; ++hl)
                             ub[b][ch][hl] = *reinterpret_cast<const uint4*>(
                                 ut + ((size_t)(c * 2 + hl) * 64 + xl) * SM_P + 16 * (rb0 + b) + 32 * ch + 8 * g4);
+                // the bases of row factor i are summed in float32, then added in float64
+                float acc32[2][4];
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc32[b][e] = 0.f;
                 for (int j = 0; j + i <= deg; ++j) {
                     const int n = base + (i + j) * (i + j + 1) / 2 + j;
                     uint4 tf[2][2];
@@ -256,24 +263,43 @@ __global__ __launch_bounds__(SM_NT, SM_MINW) void contract_sepmm_kernel(SepArgs 
                             if (NT >= 2) acc[b] = smm_mfma<FP16>(tf[ch][0], ub[b][ch][1], acc[b]);
                             if (NT >= 3) acc[b] = smm_mfma<FP16>(tf[ch][1], ub[b][ch][0], acc[b]);
                         }
-                    // c_n(x, y) = sum_q Cy[q] yh^q, Cy from the padded coefficients
-                    double cy[DSM + 1];
-                    coef_in_x<DSM>(coefp + (size_t)n * kSepCoefPad, xpow, cy);
+                    // c_n(x, y) = sum_q Cy[q] yh^q, Cy[q] = sum_ie c[m(ie, q)] xh^ie (float32)
+                    float cy[DSM + 1];
+#pragma unroll
+                    for (int q = 0; q <= DSM; ++q) cy[q] = 0.f;
+                    {
+                        const cptr<float> cn_ = coefpf + (size_t)n * kSepCoefPad;
+                        int m = 0;
+#pragma unroll
+                        for (int tt = 0; tt <= DSM; ++tt) {
+#pragma unroll
+                            for (int ie = tt; ie >= 0; --ie) cy[tt - ie] = fmaf(cn_[m + tt - ie], xpf[ie], cy[tt - ie]);
+                            m += tt + 1;
+                        }
+                    }
 #pragma unroll
                     for (int b = 0; b < 2; ++b)
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
-                            double cn = cy[DSM];
+                            float cn = cy[DSM];
 #pragma unroll
-                            for (int q = DSM - 1; q >= 0; --q) cn = fma(cn, yh[b][e], cy[q]);
-                            dacc[b][e] = fma(cn, (double)acc[b][e], dacc[b][e]);
+                            for (int q = DSM - 1; q >= 0; --q) cn = fmaf(cn, yhf[b][e], cy[q]);
+                            acc32[b][e] = fmaf(cn, acc[b][e], acc32[b][e]);
                         }
                 }
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) dacc[b][e] += (double)acc32[b][e];
             }
         }
     }
     if (x < a.W) {
-        // pedestal restore s sum_m gamma_m P_m, then D = sum_n c_n T_n - I
+        // pedestal restore s sum_m gamma_m P_m (float64), then D = sum_n c_n T_n - I
+        double xpow[DSM + 1];
+        xpow[0] = 1.0;
+#pragma unroll
+        for (int q = 1; q <= DSM; ++q) xpow[q] = xpow[q - 1] * xh;
         double cy[DSM + 1];
         coef_in_x<DSM>(as_const(a.gammap), xpow, cy);
 #pragma unroll
@@ -282,9 +308,10 @@ __global__ __launch_bounds__(SM_NT, SM_MINW) void contract_sepmm_kernel(SepArgs 
             for (int e = 0; e < 4; ++e) {
                 const int y = Y0 + 16 * (rb0 + b) + 4 * g4 + e;
                 if (y < y_end) {
+                    const double yh = a.sy * y + a.oy;
                     double pg = cy[DSM];
 #pragma unroll
-                    for (int q = DSM - 1; q >= 0; --q) pg = fma(pg, yh[b][e], cy[q]);
+                    for (int q = DSM - 1; q >= 0; --q) pg = fma(pg, yh, cy[q]);
                     const size_t idx = (size_t)y * a.W + x;
                     const double iv = a.I ? (double)a.I[idx] : 0.0;
                     a.out[idx] = (float)(fma(dacc[b][e], unscale, (double)a.ped * pg) - iv);
