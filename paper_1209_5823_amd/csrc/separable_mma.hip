@@ -13,7 +13,8 @@
 // (n = output column) and the A operand of the column pass (m = output row).
 //
 // Precision: 16-bit inputs, float32 accumulation, with hi + lo splits
-//   x = xh + xl, F = Fh + Fl (each rounded to nearest even),
+//   x = xh + xl, F = Fh + Fl (the taps rounded to nearest even; the data in
+//   fp16 by the packed truncating conversion, the lo part holding the rest),
 //   F x ~ Fh xh + Fh xl + Fl xh   (NT = 3; NT = 2 drops Fl xh),
 // for R - s (scaled by 1/4 in fp16, as in the dense low-precision form) and for
 // the row responses U between the passes.  The coefficient weighting c_n T_n
@@ -23,7 +24,7 @@
 //
 // Workgroup: 8 waves, output tile 64 x 64.  LDS: the staged tile as hi / lo
 // rows [96][120] (96 >= 64 + 2h rows; columns 0..111, zero past the halo) and,
-// per round of SM_ROUND row factors, the row responses column-major as hi / lo
+// per round (one row factor), the row responses column-major as hi / lo
 // [64][120] (rows 0..111; rows 96..111 stay zero).  A round: the row pass
 // (6 x 4 blocks of 16 x 16 per factor, spread over the waves), a barrier, then
 // the column pass, where wave w owns the 16-column block w mod 4 and the two
@@ -47,13 +48,10 @@ constexpr int SM_P = 120;                // row / column pitch in 16-bit element
 // One row factor per round keeps the LDS at 77 KB, two workgroups per CU, and
 // the registers within four waves per SIMD (measured faster than three factors
 // per round at one workgroup per CU).
-#ifndef SM_ROUND
-#define SM_ROUND 1
-#endif
-#ifndef SM_MINW
-#define SM_MINW 4
-#endif
-constexpr int SM_SLOTS = SM_ROUND;       // row factors per round
+constexpr int SM_SLOTS = 1;              // row factors per round
+constexpr int SM_MINW = 4;               // waves per SIMD the registers allow
+constexpr int SM_IB = SM_RB * 4 / SM_NW; // row-pass blocks per wave and round (3)
+static_assert(SM_RB * 4 == SM_IB * SM_NW, "row-pass blocks must spread evenly over the waves");
 constexpr int SM_FRAG = 2 * 2 * 64 * 8;  // 16-bit entries of one factor's table: [chunk][hi/lo][lane][8]
 constexpr size_t SM_LDS = (size_t)(2 * SM_XR * SM_P + SM_SLOTS * 2 * 64 * SM_P) * sizeof(uint16_t);
 
@@ -76,6 +74,24 @@ __device__ __forceinline__ void smm_split(float x, uint32_t& hi, uint32_t& lo) {
     } else {
         hi = smm_f2bf(x);
         lo = smm_f2bf(x - smm_bf2f(hi));
+    }
+}
+
+// Two values split into packed hi and lo parts.  fp16: the packed truncating
+// conversion, the lo part carrying the remainder x - hi (exact in float32);
+// bf16: rounded to nearest even one at a time.
+template <bool FP16>
+__device__ __forceinline__ void smm_split2(float x0, float x1, uint32_t& hi2, uint32_t& lo2) {
+    if (FP16) {
+        const auto h = __builtin_amdgcn_cvt_pkrtz(x0, x1);
+        hi2 = __builtin_bit_cast(uint32_t, h);
+        lo2 = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(x0 - (float)h[0], x1 - (float)h[1]));
+    } else {
+        uint32_t h0, l0, h1, l1;
+        smm_split<false>(x0, h0, l0);
+        smm_split<false>(x1, h1, l1);
+        hi2 = h0 | (h1 << 16);
+        lo2 = l0 | (l1 << 16);
     }
 }
 
@@ -157,19 +173,20 @@ __global__ __launch_bounds__(SM_NT, SM_MINW) void contract_sepmm_kernel(SepArgs 
     // writes); R = 0 outside the image; zero past the halo
     for (int q = tid; q < SM_XR * (SM_XC / 2); q += SM_NT) {
         const int r = q / (SM_XC / 2), c = 2 * (q - r * (SM_XC / 2));
-        uint32_t hi[2], lo[2];
+        float v[2];
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
-            float v = 0.f;
+            v[e] = 0.f;
             if (r < RA && c + e < CA) {
                 const int gy = Y0 - h + r, gx = X0 - h + c + e;
                 const float x = (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) ? a.X[(size_t)gy * a.W + gx] : 0.f;
-                v = (x - a.ped) * xscale;
+                v[e] = (x - a.ped) * xscale;
             }
-            smm_split<FP16>(v, hi[e], lo[e]);
         }
-        *reinterpret_cast<uint32_t*>(xs + r * SM_P + c) = hi[0] | (hi[1] << 16);
-        *reinterpret_cast<uint32_t*>(xs + (SM_XR + r) * SM_P + c) = lo[0] | (lo[1] << 16);
+        uint32_t hi2, lo2;
+        smm_split2<FP16>(v[0], v[1], hi2, lo2);
+        *reinterpret_cast<uint32_t*>(xs + r * SM_P + c) = hi2;
+        *reinterpret_cast<uint32_t*>(xs + (SM_XR + r) * SM_P + c) = lo2;
     }
     // row-response rows SM_XR .. SM_UR - 1 are read by the column windows and never
     // written: zeroed once, 8 entries per write
@@ -201,97 +218,125 @@ __global__ __launch_bounds__(SM_NT, SM_MINW) void contract_sepmm_kernel(SepArgs 
     for (int g = 0; g < a.G; ++g) {
         const int deg = fam[2 * g], base = fam[2 * g + 1];
         const uint16_t* fg = ftab + (size_t)g * kSepMaxFactors * SM_FRAG;
-        for (int i0 = 0; i0 <= deg; i0 += SM_SLOTS) {
-            const int nc = min(SM_SLOTS, deg + 1 - i0);
+        for (int i = 0; i <= deg; ++i) {
             __syncthreads();   // tile staged / previous round's row responses consumed
-            // row pass: U_e[r][x'] for the round's factors, blocks of 16 rows x 16 columns
-            for (int item = w; item < nc * SM_RB * 4; item += SM_NW) {
-                const int slot = item / (SM_RB * 4), blk = item - slot * (SM_RB * 4);
-                const int rb = blk >> 2, cb = blk & 3;
+            // row pass: U_i[r][x'] in blocks of 16 rows x 16 columns, SM_IB per wave;
+            // one accumulator per block and chunk, the products of a term issued
+            // across the blocks so that dependent matrix-core operations are apart
+            {
                 uint4 tf[2][2];
-                smm_load_frag(fg + (size_t)(i0 + slot) * SM_FRAG, lane, tf);
-                smm_f4 acc = {0.f, 0.f, 0.f, 0.f};
-                const int r = 16 * rb + j16;
+                smm_load_frag(fg + (size_t)i * SM_FRAG, lane, tf);
+                uint4 dh[SM_IB][2], dl[SM_IB][2];
+                smm_f4 acc[SM_IB][2];
 #pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    const int col = 16 * cb + 32 * c + 8 * g4;
-                    const uint4 dh = *reinterpret_cast<const uint4*>(xs + r * SM_P + col);
-                    const uint4 dl = *reinterpret_cast<const uint4*>(xs + (SM_XR + r) * SM_P + col);
-                    acc = smm_mfma<FP16>(dh, tf[c][0], acc);
-                    if (NT >= 2) acc = smm_mfma<FP16>(dl, tf[c][0], acc);
-                    if (NT >= 3) acc = smm_mfma<FP16>(dh, tf[c][1], acc);
+                for (int k = 0; k < SM_IB; ++k) {
+                    const int blk = w + k * SM_NW, rb = blk >> 2, cb = blk & 3;
+                    const int r = 16 * rb + j16;
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const int col = 16 * cb + 32 * c + 8 * g4;
+                        dh[k][c] = *reinterpret_cast<const uint4*>(xs + r * SM_P + col);
+                        dl[k][c] = *reinterpret_cast<const uint4*>(xs + (SM_XR + r) * SM_P + col);
+                        acc[k][c] = smm_f4{0.f, 0.f, 0.f, 0.f};
+                    }
                 }
-                // lane (g4, j16) holds U at rows 16 rb + 4 g4 + e, column 16 cb + j16
-                uint32_t hv[4], lv[4];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) smm_split<FP16>(acc[e], hv[e], lv[e]);
-                uint16_t* dst = ut + ((size_t)(slot * 2) * 64 + 16 * cb + j16) * SM_P + 16 * rb + 4 * g4;
-                *reinterpret_cast<uint2*>(dst) = make_uint2(hv[0] | (hv[1] << 16), hv[2] | (hv[3] << 16));
-                *reinterpret_cast<uint2*>(dst + 64 * SM_P) = make_uint2(lv[0] | (lv[1] << 16), lv[2] | (lv[3] << 16));
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int k = 0; k < SM_IB; ++k) acc[k][c] = smm_mfma<FP16>(dh[k][c], tf[c][0], acc[k][c]);
+                if (NT >= 2)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+#pragma unroll
+                        for (int k = 0; k < SM_IB; ++k) acc[k][c] = smm_mfma<FP16>(dl[k][c], tf[c][0], acc[k][c]);
+                if (NT >= 3)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+#pragma unroll
+                        for (int k = 0; k < SM_IB; ++k) acc[k][c] = smm_mfma<FP16>(dh[k][c], tf[c][1], acc[k][c]);
+#pragma unroll
+                for (int k = 0; k < SM_IB; ++k) {
+                    const int blk = w + k * SM_NW, rb = blk >> 2, cb = blk & 3;
+                    // lane (g4, j16) holds U at rows 16 rb + 4 g4 + e, column 16 cb + j16
+                    const smm_f4 u = acc[k][0] + acc[k][1];
+                    uint32_t hv[2], lv[2];
+                    smm_split2<FP16>(u[0], u[1], hv[0], lv[0]);
+                    smm_split2<FP16>(u[2], u[3], hv[1], lv[1]);
+                    uint16_t* dst = ut + (size_t)(16 * cb + j16) * SM_P + 16 * rb + 4 * g4;
+                    *reinterpret_cast<uint2*>(dst) = make_uint2(hv[0], hv[1]);
+                    *reinterpret_cast<uint2*>(dst + 64 * SM_P) = make_uint2(lv[0], lv[1]);
+                }
             }
             __syncthreads();
             // column pass: T_n = f_j (x)_y U_i on this wave's two blocks, then D += c_n T_n
-            for (int c = 0; c < nc; ++c) {
-                const int i = i0 + c;
-                uint4 ub[2][2][2];   // [block][chunk][hi/lo]
+            uint4 ub[2][2][2];   // [block][chunk][hi/lo]
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int ch = 0; ch < 2; ++ch)
+#pragma unroll
+                    for (int hl = 0; hl < 2; ++hl)
+                        ub[b][ch][hl] = *reinterpret_cast<const uint4*>(
+                            ut + ((size_t)hl * 64 + xl) * SM_P + 16 * (rb0 + b) + 32 * ch + 8 * g4);
+            // the bases of row factor i are summed in float32, then added in float64
+            float acc32[2][4];
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc32[b][e] = 0.f;
+            for (int j = 0; j + i <= deg; ++j) {
+                const int n = base + (i + j) * (i + j + 1) / 2 + j;
+                uint4 tf[2][2];
+                smm_load_frag(fg + (size_t)j * SM_FRAG, lane, tf);
+                smm_f4 acc[2][2];   // [block][chunk]
 #pragma unroll
                 for (int b = 0; b < 2; ++b)
 #pragma unroll
-                    for (int ch = 0; ch < 2; ++ch)
+                    for (int ch = 0; ch < 2; ++ch) acc[b][ch] = smm_f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                        for (int hl = 0; hl < 2; ++hl)
-                            ub[b][ch][hl] = *reinterpret_cast<const uint4*>(
-                                ut + ((size_t)(c * 2 + hl) * 64 + xl) * SM_P + 16 * (rb0 + b) + 32 * ch + 8 * g4);
-                // the bases of row factor i are summed in float32, then added in float64
-                float acc32[2][4];
+                for (int ch = 0; ch < 2; ++ch)
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) acc32[b][e] = 0.f;
-                for (int j = 0; j + i <= deg; ++j) {
-                    const int n = base + (i + j) * (i + j + 1) / 2 + j;
-                    uint4 tf[2][2];
-                    smm_load_frag(fg + (size_t)j * SM_FRAG, lane, tf);
-                    smm_f4 acc[2];
-#pragma unroll
-                    for (int b = 0; b < 2; ++b) acc[b] = smm_f4{0.f, 0.f, 0.f, 0.f};
+                    for (int b = 0; b < 2; ++b) acc[b][ch] = smm_mfma<FP16>(tf[ch][0], ub[b][ch][0], acc[b][ch]);
+                if (NT >= 2)
 #pragma unroll
                     for (int ch = 0; ch < 2; ++ch)
 #pragma unroll
-                        for (int b = 0; b < 2; ++b) {
-                            acc[b] = smm_mfma<FP16>(tf[ch][0], ub[b][ch][0], acc[b]);
-                            if (NT >= 2) acc[b] = smm_mfma<FP16>(tf[ch][0], ub[b][ch][1], acc[b]);
-                            if (NT >= 3) acc[b] = smm_mfma<FP16>(tf[ch][1], ub[b][ch][0], acc[b]);
-                        }
-                    // c_n(x, y) = sum_q Cy[q] yh^q, Cy[q] = sum_ie c[m(ie, q)] xh^ie (float32)
-                    float cy[DSM + 1];
+                        for (int b = 0; b < 2; ++b) acc[b][ch] = smm_mfma<FP16>(tf[ch][0], ub[b][ch][1], acc[b][ch]);
+                if (NT >= 3)
 #pragma unroll
-                    for (int q = 0; q <= DSM; ++q) cy[q] = 0.f;
-                    {
-                        const cptr<float> cn_ = coefpf + (size_t)n * kSepCoefPad;
-                        int m = 0;
+                    for (int ch = 0; ch < 2; ++ch)
 #pragma unroll
-                        for (int tt = 0; tt <= DSM; ++tt) {
+                        for (int b = 0; b < 2; ++b) acc[b][ch] = smm_mfma<FP16>(tf[ch][1], ub[b][ch][0], acc[b][ch]);
+                // c_n(x, y) = sum_q Cy[q] yh^q, Cy[q] = sum_ie c[m(ie, q)] xh^ie (float32)
+                float cy[DSM + 1];
 #pragma unroll
-                            for (int ie = tt; ie >= 0; --ie) cy[tt - ie] = fmaf(cn_[m + tt - ie], xpf[ie], cy[tt - ie]);
-                            m += tt + 1;
-                        }
+                for (int q = 0; q <= DSM; ++q) cy[q] = 0.f;
+                {
+                    const cptr<float> cn_ = coefpf + (size_t)n * kSepCoefPad;
+                    int m = 0;
+#pragma unroll
+                    for (int tt = 0; tt <= DSM; ++tt) {
+#pragma unroll
+                        for (int ie = tt; ie >= 0; --ie) cy[tt - ie] = fmaf(cn_[m + tt - ie], xpf[ie], cy[tt - ie]);
+                        m += tt + 1;
                     }
-#pragma unroll
-                    for (int b = 0; b < 2; ++b)
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            float cn = cy[DSM];
-#pragma unroll
-                            for (int q = DSM - 1; q >= 0; --q) cn = fmaf(cn, yhf[b][e], cy[q]);
-                            acc32[b][e] = fmaf(cn, acc[b][e], acc32[b][e]);
-                        }
                 }
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
+                for (int b = 0; b < 2; ++b) {
+                    const smm_f4 tv = acc[b][0] + acc[b][1];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) dacc[b][e] += (double)acc32[b][e];
+                    for (int e = 0; e < 4; ++e) {
+                        float cn = cy[DSM];
+#pragma unroll
+                        for (int q = DSM - 1; q >= 0; --q) cn = fmaf(cn, yhf[b][e], cy[q]);
+                        acc32[b][e] = fmaf(cn, tv[e], acc32[b][e]);
+                    }
+                }
             }
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) dacc[b][e] += (double)acc32[b][e];
         }
     }
     if (x < a.W) {
