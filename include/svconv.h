@@ -61,7 +61,8 @@ enum svconv_status {
     SVCONV_ENOTSPD = -5       /* matrix not symmetric positive definite */
 };
 
-/* Arithmetic of the basis contraction (the dominant step). */
+/* Arithmetic of the basis contraction (the dominant step); for the
+ * SEPARABLE form see below. */
 enum svconv_precision {
     SVCONV_FP32 = 0,    /* float32 matrix cores (v_mfma_f32_16x16x4_f32)      */
     SVCONV_BF16 = 1,    /* bf16 inputs, fp32 accumulation, 1 product          */
@@ -80,12 +81,17 @@ enum svconv_form { SVCONV_FORM_BASIS = 0, SVCONV_FORM_REGROUPED = 1, SVCONV_FORM
 /* SEPARABLE (Gaussian bases, 1 <= half_width <= 15): each Gaussian basis is a
  * product f_i(u) f_j(v) of one-dimensional factors (the L1 norm of the
  * product is the product of the norms), so T_n = f_j (x)_y (f_i (x)_x R): a
- * row pass per factor f_i of a family, then a column pass per basis, in
- * float64 arithmetic with the row responses held in float32; the precision
- * setting does not apply.  In this form svconv_backward, svconv_normal_matrix,
- * svconv_gn_step and svconv_pcg_fit also go through the factors (the adjoint
- * in a falls back to the matrix-core product when its per-round moments do
- * not fit in LDS).  The adjoint in a sums with LDS atomics, so repeated calls
+ * row pass per factor f_i of a family, then a column pass per basis.  With
+ * SVCONV_FP32, SVCONV_BF16 or SVCONV_FP16 the passes run in float64 on the
+ * vector units (row responses held in float32); with SVCONV_FP16X3,
+ * SVCONV_BF16X3 or SVCONV_FP16X2 the forward passes run on the matrix cores
+ * as banded Toeplitz products of 16-bit hi/lo parts with float32
+ * accumulation (the coefficient weighting and the sums over the bases in
+ * float32 / float64 on the vector units).  In this form svconv_backward,
+ * svconv_normal_matrix, svconv_gn_step and svconv_pcg_fit also go through the
+ * factors; the adjoints and the basis responses of the normal matrix always in
+ * float64 (the adjoint in a falls back to the matrix-core product when its
+ * per-round moments do not fit in LDS).  The adjoint in a sums with LDS atomics, so repeated calls
  * agree to float64 rounding rather than bit for bit.  EUNSUPPORTED for
  * delta-basis plans. */
 

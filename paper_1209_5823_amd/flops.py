@@ -76,3 +76,16 @@ def separable_flops_per_pixel(degrees, M, k):
     col = sum(window(d - i + 1) for d in degrees for i in range(d + 1))
     N = sum((d + 1) * (d + 2) // 2 for d in degrees)
     return row + col + 2 * N * M + 2 * N + 1
+
+
+def separable_mma_executed_flops_per_pixel(degrees, passes, tile=64, row_pass_rows=96, window=64):
+    """Matrix-core FLOP issued per output pixel by the Toeplitz form of the
+    separable passes: every one-dimensional pass is a product with a
+    `window`-long reduction (16 + 2h samples padded to two 32-long chunks), the
+    row pass covers `row_pass_rows` staged rows per `tile` output rows, and
+    each product is issued `passes` times (the hi/lo split terms)."""
+    n_factors = sum(d + 1 for d in degrees)
+    N = sum((d + 1) * (d + 2) // 2 for d in degrees)
+    row = n_factors * window * 2 * passes * row_pass_rows / tile
+    col = N * window * 2 * passes
+    return int(round(row + col))

@@ -66,3 +66,11 @@ def test_separable_folded_count():
     # a fold never costs more than the tap-by-tap count
     for degrees, M, k in (((6, 4, 2), 6, 21), ((0,), 1, 3), ((2,), 1, 3)):
         assert flops.separable_flops_per_pixel(degrees, M, k) <= flops.separable_unfolded_flops_per_pixel(degrees, M, k)
+
+
+def test_separable_mma_executed_count():
+    # 15 factors x 1.5 staged rows per output row x 64-long windows x 2 FLOP x 3 terms,
+    # plus 49 bases x 64 x 2 x 3
+    assert flops.separable_mma_executed_flops_per_pixel((6, 4, 2), 3) == 15 * 96 * 6 + 49 * 64 * 6
+    assert flops.separable_mma_executed_flops_per_pixel((6, 4, 2), 3) == 27456
+    assert flops.separable_mma_executed_flops_per_pixel((0,), 1) == 64 * 2 * 96 // 64 + 64 * 2
