@@ -221,44 +221,38 @@ __global__ __launch_bounds__(SM_NT, SM_MINW) void contract_sepmm_kernel(SepArgs 
         for (int i = 0; i <= deg; ++i) {
             __syncthreads();   // tile staged / previous round's row responses consumed
             // row pass: U_i[r][x'] in blocks of 16 rows x 16 columns, SM_IB per wave;
-            // one accumulator per block and chunk, the products of a term issued
-            // across the blocks so that dependent matrix-core operations are apart
+            // one accumulator per block, the products of a term issued across the
+            // blocks so that dependent matrix-core operations are apart
             {
                 uint4 tf[2][2];
                 smm_load_frag(fg + (size_t)i * SM_FRAG, lane, tf);
-                uint4 dh[SM_IB][2], dl[SM_IB][2];
-                smm_f4 acc[SM_IB][2];
+                smm_f4 acc[SM_IB];
 #pragma unroll
-                for (int k = 0; k < SM_IB; ++k) {
-                    const int blk = w + k * SM_NW, rb = blk >> 2, cb = blk & 3;
-                    const int r = 16 * rb + j16;
+                for (int k = 0; k < SM_IB; ++k) acc[k] = smm_f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                    for (int c = 0; c < 2; ++c) {
-                        const int col = 16 * cb + 32 * c + 8 * g4;
-                        dh[k][c] = *reinterpret_cast<const uint4*>(xs + r * SM_P + col);
-                        dl[k][c] = *reinterpret_cast<const uint4*>(xs + (SM_XR + r) * SM_P + col);
-                        acc[k][c] = smm_f4{0.f, 0.f, 0.f, 0.f};
+                for (int c = 0; c < 2; ++c) {
+                    uint4 dh[SM_IB], dl[SM_IB];
+#pragma unroll
+                    for (int k = 0; k < SM_IB; ++k) {
+                        const int blk = w + k * SM_NW, rb = blk >> 2, cb = blk & 3;
+                        const int off = (16 * rb + j16) * SM_P + 16 * cb + 32 * c + 8 * g4;
+                        dh[k] = *reinterpret_cast<const uint4*>(xs + off);
+                        dl[k] = *reinterpret_cast<const uint4*>(xs + SM_XR * SM_P + off);
                     }
+#pragma unroll
+                    for (int k = 0; k < SM_IB; ++k) acc[k] = smm_mfma<FP16>(dh[k], tf[c][0], acc[k]);
+                    if (NT >= 2)
+#pragma unroll
+                        for (int k = 0; k < SM_IB; ++k) acc[k] = smm_mfma<FP16>(dl[k], tf[c][0], acc[k]);
+                    if (NT >= 3)
+#pragma unroll
+                        for (int k = 0; k < SM_IB; ++k) acc[k] = smm_mfma<FP16>(dh[k], tf[c][1], acc[k]);
                 }
-#pragma unroll
-                for (int c = 0; c < 2; ++c)
-#pragma unroll
-                    for (int k = 0; k < SM_IB; ++k) acc[k][c] = smm_mfma<FP16>(dh[k][c], tf[c][0], acc[k][c]);
-                if (NT >= 2)
-#pragma unroll
-                    for (int c = 0; c < 2; ++c)
-#pragma unroll
-                        for (int k = 0; k < SM_IB; ++k) acc[k][c] = smm_mfma<FP16>(dl[k][c], tf[c][0], acc[k][c]);
-                if (NT >= 3)
-#pragma unroll
-                    for (int c = 0; c < 2; ++c)
-#pragma unroll
-                        for (int k = 0; k < SM_IB; ++k) acc[k][c] = smm_mfma<FP16>(dh[k][c], tf[c][1], acc[k][c]);
 #pragma unroll
                 for (int k = 0; k < SM_IB; ++k) {
                     const int blk = w + k * SM_NW, rb = blk >> 2, cb = blk & 3;
                     // lane (g4, j16) holds U at rows 16 rb + 4 g4 + e, column 16 cb + j16
-                    const smm_f4 u = acc[k][0] + acc[k][1];
+                    const smm_f4 u = acc[k];
                     uint32_t hv[2], lv[2];
                     smm_split2<FP16>(u[0], u[1], hv[0], lv[0]);
                     smm_split2<FP16>(u[2], u[3], hv[1], lv[1]);
