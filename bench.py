@@ -324,6 +324,10 @@ def main():
                      "mfma_executed_flop_per_pixel": (
                          flops.separable_mma_executed_flops_per_pixel(wl.degrees, PASSES[prec])
                          if form == "separable" and prec != "f64" else None),
+                     "mfma_executed_frac": (
+                         round(flops.separable_mma_executed_flops_per_pixel(wl.degrees, PASSES[prec]) * px
+                               / (hr["ms"] * 1e-3) / 1e12 / peak, 4)
+                         if form == "separable" and prec != "f64" else None),
                      "paper_flop_per_pixel": flops.paper_flops_gfb(N, k),
                      "paper_model_tflops": round(flops.paper_flops_gfb(N, k) * px
                                                  / (hr["ms"] * 1e-3) / 1e12, 3)},
@@ -340,11 +344,14 @@ def main():
     fp = best(1e-4)
     if fp is not None:
         out["fp32_path"] = summary(fp)
-    mf = best(1e-2, forms=("basis", "regrouped"), precs=("bf16", "fp16", "bf16x3", "fp16x2", "fp16x3"))
+    mf = best(1e-2, forms=("basis", "regrouped", "separable"), precs=("bf16", "fp16", "bf16x3", "fp16x2", "fp16x3"))
     if mf is not None:
         out["mfma"] = summary(mf)
     if ("basis", "fp32") in results:
         out["fp32"] = summary(("basis", "fp32"))
+    if ("separable", "f64") in results:
+        # the float64 separable form on the vector units, with its own (ALU) roofline
+        out["separable_f64"] = summary(("separable", "f64"))
     rg = best(1e-2, forms=("regrouped",))
     if rg is not None:
         out["regrouped"] = summary(rg)
