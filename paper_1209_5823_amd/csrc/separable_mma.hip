@@ -210,7 +210,8 @@ __global__ __launch_bounds__(SM_NT, SM_MINW) void contract_sepmm_kernel(SepArgs 
     for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            yhf[b][e] = (float)(a.sy * (Y0 + 16 * (rb0 + b) + 4 * g4 + e) + a.oy);
+            // float32 arithmetic here: the float64 yh of the final pass is formed there
+            yhf[b][e] = fmaf((float)a.sy, (float)(Y0 + 16 * (rb0 + b) + 4 * g4 + e), (float)a.oy);
             dacc[b][e] = 0.0;
         }
     const cptr<float> coefpf = as_const(a.coefpf);
