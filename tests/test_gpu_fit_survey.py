@@ -2,7 +2,8 @@
 bases, spatial degree 4 (735 coefficients).  I = float32(Poisson(C(R;
 a_hidden))) with C from the oracle's FFT regrouping; the coefficients are
 fitted by Gauss-Newton with the bf16x3 and FP32 matrix-core forwards and with
-the separable form (forward and adjoint through the Gaussian factors).  Reports the
+the separable form (forward and adjoint through the Gaussian factors; the
+forward in float64 or on the matrix cores in fp16x3).  Reports the
 recovered-coefficient error, the final D RMS in sigma_sky and the Mpix/s of
 one iteration."""
 
@@ -29,7 +30,7 @@ def c4_case(orc):
 
 
 @pytest.mark.parametrize("precision,form", [("bf16x3", "basis"), ("fp32", "basis"),
-                                            ("fp32", "separable")])
+                                            ("fp32", "separable"), ("fp16x3", "separable")])
 def test_fit_survey_scale(svc, c4_case, precision, form):
     import torch
     from paper_1209_5823_amd.fit import gauss_newton_fit
