@@ -18,17 +18,19 @@
 //   F x ~ Fh xh + Fh xl + Fl xh   (NT = 3; NT = 2 drops Fl xh),
 // for R - s (scaled by 1/4 in fp16, as in the dense low-precision form) and for
 // the row responses U between the passes.  The coefficient weighting c_n T_n
-// and the sum over the bases of one row factor run in float32 on the vector
-// units; the sum over the row factors, the pedestal restore
-// s sum_m gamma_m P_m and the subtraction of I in float64.
+// and the sum over the bases run in float32 on the vector units; the pedestal
+// restore s sum_m gamma_m P_m and the subtraction of I in float64.
 //
 // Workgroup: 8 waves, output tile 64 x 64.  LDS: the staged tile as hi / lo
 // rows [96][120] (96 >= 64 + 2h rows; columns 0..111, zero past the halo) and,
 // per round (one row factor), the row responses column-major as hi / lo
-// [64][120] (rows 0..111; rows 96..111 stay zero).  A round: the row pass
-// (6 x 4 blocks of 16 x 16 per factor, spread over the waves), a barrier, then
-// the column pass, where wave w owns the 16-column block w mod 4 and the two
-// 16-row blocks 2 (w / 4), 2 (w / 4) + 1 for every basis of the round.
+// [64][120] (rows 0..111; rows 96..111 stay zero).  A round: the products of
+// the row pass (6 x 4 blocks of 16 x 16 per factor, spread over the waves; they
+// read only the staged tile, so a wave starts them as soon as it has finished
+// the previous round), a barrier, the responses written, a barrier, then the
+// column pass, where wave w owns the 16-column block w mod 4 and the two
+// 16-row blocks 2 (w / 4), 2 (w / 4) + 1 for every basis of the round, the
+// products of basis j + 1 issued ahead of the epilogue of basis j.
 #include "internal.hpp"
 #include "sep_fold.hpp"
 
@@ -205,25 +207,26 @@ __global__ __launch_bounds__(SM_NT, SM_MINW) void contract_sepmm_kernel(SepArgs 
     xpf[0] = 1.f;
 #pragma unroll
     for (int q = 1; q <= DSM; ++q) xpf[q] = xpf[q - 1] * (float)xh;
-    double dacc[2][4];
+    float acc32[2][4];
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             // float32 arithmetic here: the float64 yh of the final pass is formed there
             yhf[b][e] = fmaf((float)a.sy, (float)(Y0 + 16 * (rb0 + b) + 4 * g4 + e), (float)a.oy);
-            dacc[b][e] = 0.0;
+            acc32[b][e] = 0.f;
         }
     const cptr<float> coefpf = as_const(a.coefpf);
 
+    __syncthreads();   // tile staged
     for (int g = 0; g < a.G; ++g) {
         const int deg = fam[2 * g], base = fam[2 * g + 1];
         const uint16_t* fg = ftab + (size_t)g * kSepMaxFactors * SM_FRAG;
         for (int i = 0; i <= deg; ++i) {
-            __syncthreads();   // tile staged / previous round's row responses consumed
             // row pass: U_i[r][x'] in blocks of 16 rows x 16 columns, SM_IB per wave;
             // one accumulator per block, the products of a term issued across the
-            // blocks so that dependent matrix-core operations are apart
+            // blocks so that dependent matrix-core operations are apart; only the
+            // writes of the responses wait for every wave's previous column pass
             {
                 uint4 tf[2][2];
                 smm_load_frag(fg + (size_t)i * SM_FRAG, lane, tf);
@@ -249,6 +252,7 @@ __global__ __launch_bounds__(SM_NT, SM_MINW) void contract_sepmm_kernel(SepArgs 
 #pragma unroll
                         for (int k = 0; k < SM_IB; ++k) acc[k] = smm_mfma<FP16>(dh[k], tf[c][1], acc[k]);
                 }
+                __syncthreads();   // previous round's row responses consumed
 #pragma unroll
                 for (int k = 0; k < SM_IB; ++k) {
                     const int blk = w + k * SM_NW, rb = blk >> 2, cb = blk & 3;
@@ -273,36 +277,31 @@ __global__ __launch_bounds__(SM_NT, SM_MINW) void contract_sepmm_kernel(SepArgs 
                     for (int hl = 0; hl < 2; ++hl)
                         ub[b][ch][hl] = *reinterpret_cast<const uint4*>(
                             ut + ((size_t)hl * 64 + xl) * SM_P + 16 * (rb0 + b) + 32 * ch + 8 * g4);
-            // the bases of row factor i are summed in float32, then added in float64
-            float acc32[2][4];
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) acc32[b][e] = 0.f;
-            for (int j = 0; j + i <= deg; ++j) {
-                const int n = base + (i + j) * (i + j + 1) / 2 + j;
+            // the products of basis j + 1 are issued ahead of the epilogue of basis j
+            // (two accumulator sets, one accumulator per block over both chunks)
+            const int nb = deg - i + 1;
+            auto products = [&](int j, smm_f4 (&acc)[2]) {
                 uint4 tf[2][2];
                 smm_load_frag(fg + (size_t)j * SM_FRAG, lane, tf);
-                smm_f4 acc[2][2];   // [block][chunk]
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
-#pragma unroll
-                    for (int ch = 0; ch < 2; ++ch) acc[b][ch] = smm_f4{0.f, 0.f, 0.f, 0.f};
+                for (int b = 0; b < 2; ++b) acc[b] = smm_f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int ch = 0; ch < 2; ++ch)
 #pragma unroll
-                    for (int b = 0; b < 2; ++b) acc[b][ch] = smm_mfma<FP16>(tf[ch][0], ub[b][ch][0], acc[b][ch]);
+                    for (int b = 0; b < 2; ++b) acc[b] = smm_mfma<FP16>(tf[ch][0], ub[b][ch][0], acc[b]);
                 if (NT >= 2)
 #pragma unroll
                     for (int ch = 0; ch < 2; ++ch)
 #pragma unroll
-                        for (int b = 0; b < 2; ++b) acc[b][ch] = smm_mfma<FP16>(tf[ch][0], ub[b][ch][1], acc[b][ch]);
+                        for (int b = 0; b < 2; ++b) acc[b] = smm_mfma<FP16>(tf[ch][0], ub[b][ch][1], acc[b]);
                 if (NT >= 3)
 #pragma unroll
                     for (int ch = 0; ch < 2; ++ch)
 #pragma unroll
-                        for (int b = 0; b < 2; ++b) acc[b][ch] = smm_mfma<FP16>(tf[ch][1], ub[b][ch][0], acc[b][ch]);
-                // c_n(x, y) = sum_q Cy[q] yh^q, Cy[q] = sum_ie c[m(ie, q)] xh^ie (float32)
+                        for (int b = 0; b < 2; ++b) acc[b] = smm_mfma<FP16>(tf[ch][1], ub[b][ch][0], acc[b]);
+            };
+            auto epilogue = [&](int j, const smm_f4 (&acc)[2]) {
+                const int n = base + (i + j) * (i + j + 1) / 2 + j;
                 float cy[DSM + 1];
 #pragma unroll
                 for (int q = 0; q <= DSM; ++q) cy[q] = 0.f;
@@ -317,21 +316,25 @@ __global__ __launch_bounds__(SM_NT, SM_MINW) void contract_sepmm_kernel(SepArgs 
                     }
                 }
 #pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    const smm_f4 tv = acc[b][0] + acc[b][1];
+                for (int b = 0; b < 2; ++b)
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         float cn = cy[DSM];
 #pragma unroll
                         for (int q = DSM - 1; q >= 0; --q) cn = fmaf(cn, yhf[b][e], cy[q]);
-                        acc32[b][e] = fmaf(cn, tv[e], acc32[b][e]);
+                        acc32[b][e] = fmaf(cn, acc[b][e], acc32[b][e]);
                     }
-                }
+            };
+            smm_f4 accA[2], accB[2];
+            products(0, accA);
+            for (int j = 0;;) {
+                if (j + 1 < nb) products(j + 1, accB);
+                epilogue(j, accA);
+                if (++j >= nb) break;
+                if (j + 1 < nb) products(j + 1, accA);
+                epilogue(j, accB);
+                if (++j >= nb) break;
             }
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) dacc[b][e] += (double)acc32[b][e];
         }
     }
     if (x < a.W) {
@@ -354,7 +357,7 @@ __global__ __launch_bounds__(SM_NT, SM_MINW) void contract_sepmm_kernel(SepArgs 
                     for (int q = DSM - 1; q >= 0; --q) pg = fma(pg, yh, cy[q]);
                     const size_t idx = (size_t)y * a.W + x;
                     const double iv = a.I ? (double)a.I[idx] : 0.0;
-                    a.out[idx] = (float)(fma(dacc[b][e], unscale, (double)a.ped * pg) - iv);
+                    a.out[idx] = (float)(fma((double)acc32[b][e], unscale, (double)a.ped * pg) - iv);
                 }
             }
     }
