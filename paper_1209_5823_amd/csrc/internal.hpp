@@ -169,6 +169,8 @@ int launch_sep_prep(const float* coef, const double* beta, int N, int M, double*
 size_t sep_mma_frag_entries(int G);
 int build_sep_mma_fragments(const double* f1d, int G, int h, uint16_t* frag, hipStream_t s);
 int launch_contract_sep_mma(SepArgs a, const uint16_t* frag, int precision, hipStream_t s);
+// adjoint in R through the separable factors on the matrix cores (bf16x3); a.X = G, a.out = dL/dR
+int launch_adjoint_r_sep_mma(SepArgs a, const uint16_t* frag, hipStream_t s);
 int launch_adjoint_a_sep(svconv_plan* p, const float* R, const float* G, double* ga);
 bool sep_adjoint_supported(const svconv_plan* p);
 int launch_adjoint_r_sep(svconv_plan* p, const float* a32, const float* G, float* gR);

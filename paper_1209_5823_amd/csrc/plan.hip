@@ -486,7 +486,31 @@ int svconv_backward(svconv_plan* p, const float* R, const float* a, const float*
         return fail(SVCONV_EINVAL, "gR aliases R or gD");
     if (p->M > 32) return fail(SVCONV_EUNSUPPORTED, "adjoint in R needs M <= 32");
     int st = SVCONV_OK;
-    if (gR && p->form == SVCONV_FORM_SEPARABLE) {
+    if (gR && p->form == SVCONV_FORM_SEPARABLE &&
+        (p->precision == SVCONV_FP16X3 || p->precision == SVCONV_BF16X3) && p->dSepFrag) {
+        // through the separable factors on the matrix cores (bf16x3 for both split
+        // precisions: bf16 keeps the float32 range of c_n gD)
+        ContractArgs c{};
+        coords(p, c);
+        SepArgs sa{};
+        sa.X = gD;
+        sa.out = gR;
+        sa.H = p->H;
+        sa.W = p->W;
+        sa.h = p->h;
+        sa.G = (int)p->sigmas.size();
+        sa.fam = p->dSepFam;
+        sa.M = p->M;
+        sa.d_s = p->d_s;
+        sa.sx = c.sx; sa.ox = c.ox; sa.sy = c.sy; sa.oy = c.oy;
+        double* coefd = p->dVec + 7 * (size_t)kMaxCoefficients;
+        double* gamma = p->dVec + 8 * (size_t)kMaxCoefficients;
+        st = launch_sep_prep(a, p->dBeta, p->N, p->M, coefd, gamma, p->dSepCoef, p->stream);
+        if (st) return st;
+        sa.coefpf = reinterpret_cast<const float*>(p->dSepCoef + (size_t)(p->N + 1) * kSepCoefPad);
+        st = launch_adjoint_r_sep_mma(sa, p->dSepFrag, p->stream);
+        if (st) return st;
+    } else if (gR && p->form == SVCONV_FORM_SEPARABLE) {
         // through the separable factors (E_n = c_n gD correlated with B_n)
         st = launch_adjoint_r_sep(p, a, gD, gR);
         if (st) return st;

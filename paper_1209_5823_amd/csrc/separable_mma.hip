@@ -386,4 +386,200 @@ int launch_contract_sep_mma(SepArgs a, const uint16_t* frag, int precision, hipS
     }
 }
 
+
+// ------------------------------------------------------- adjoint in R ----
+//
+//   dL/dR(q) = sum_n sum_{u,v} B_n[u,v] E_n(q + (u,v)),   E_n = c_n G
+//
+// (the correlation of Sec. 2's forward with B_n = f_i(u) f_j(v)), on the same
+// Toeplitz fragments: a correlation is the convolution with the mirrored
+// factor, f_e(-w) = (-1)^e f_e(w), so the sign (-1)^j goes into E_n and (-1)^i
+// into CE_i.  Per 64 x 64 output tile and basis n = (i, j): E_n on the tile and
+// its halo ((64 + 2h)^2, c_n in float32 from the padded float coefficients, G
+// held in registers for the whole tile), split into bf16 hi + lo column-major
+// in LDS; the column pass CE_i += f_j (x)_y E_n accumulates over the bases of
+// row factor i in the matrix-core accumulators (4 x 6 blocks, 3 per wave); then
+// CE_i is split row-major into LDS and the row pass dR += f_i (x)_x CE_i
+// accumulates over all rounds (4 x 4 blocks, 2 per wave).  bf16 keeps the
+// float32 range of c_n G; three products per pass as in the forward.
+constexpr int SA_NI = 9;                  // E entries per thread and basis, as row pairs
+static_assert(SM_XR * (SM_XR / 2) == SA_NI * SM_NT, "E row pairs must spread evenly over the threads");
+
+template <int DSM>
+__global__ __launch_bounds__(SM_NT, SM_MINW) void adjoint_r_sepmm_kernel(SepArgs a, const uint16_t* __restrict__ frag) {
+    extern __shared__ uint4 smm_lds[];
+    uint16_t* et = reinterpret_cast<uint16_t*>(smm_lds);   // [2][SM_XR columns][SM_P]: E_n, rows contiguous
+    uint16_t* ce = et + 2 * SM_XR * SM_P;                    // [2][64 rows][SM_P]: CE_i, columns contiguous
+
+    const int h = a.h;
+    const int CA = 64 + 2 * h;
+    const cptr<int> fam = as_const(a.fam);
+    const cptr<float> coefpf = as_const(a.coefpf);
+    const uint16_t* ftab = frag + (size_t)a.G * kSepMaxFactors * SM_FRAG;   // bf16 tables
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int g4 = lane >> 4, j16 = lane & 15;
+    const int t = sep_xcd_remap(blockIdx.x, a.n_tiles);
+    const int X0 = (t % a.tiles_x) * 64, Y0 = (t / a.tiles_x) * 64;
+    const float sxf = (float)a.sx, oxf = (float)a.ox, syf = (float)a.sy, oyf = (float)a.oy;
+
+    // E rows SM_XR .. SM_UR - 1 and CE columns SM_XR .. SM_UR - 1 are read by the
+    // last windows and never written: zeroed once, 8 entries per write
+    for (int q = tid; q < 2 * SM_XR * 2; q += SM_NT)
+        *reinterpret_cast<uint4*>(et + (q >> 1) * SM_P + SM_XR + 8 * (q & 1)) = make_uint4(0u, 0u, 0u, 0u);
+    for (int q = tid; q < 2 * 64 * 2; q += SM_NT)
+        *reinterpret_cast<uint4*>(ce + (q >> 1) * SM_P + SM_XR + 8 * (q & 1)) = make_uint4(0u, 0u, 0u, 0u);
+    // G on the staged region (row pairs q = tid + k SM_NT: column q / 48, rows
+    // 2 (q mod 48) + 0, 1); zero outside the image and past the halo
+    float gv[SA_NI][2];
+#pragma unroll
+    for (int k = 0; k < SA_NI; ++k) {
+        const int q = tid + k * SM_NT, xq = q / (SM_XR / 2), pr = q - xq * (SM_XR / 2);
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int yq = 2 * pr + e, gx = X0 - h + xq, gy = Y0 - h + yq;
+            gv[k][e] = (xq < CA && yq < CA && gx >= 0 && gx < a.W && gy >= 0 && gy < a.H)
+                           ? a.X[(size_t)gy * a.W + gx] : 0.f;
+        }
+    }
+    smm_f4 accR[2];   // dR blocks w and w + 8 of the 4 x 4 output blocks
+#pragma unroll
+    for (int k = 0; k < 2; ++k) accR[k] = smm_f4{0.f, 0.f, 0.f, 0.f};
+
+    for (int g = 0; g < a.G; ++g) {
+        const int deg = fam[2 * g], base = fam[2 * g + 1];
+        const uint16_t* fg = ftab + (size_t)g * kSepMaxFactors * SM_FRAG;
+        for (int i = 0; i <= deg; ++i) {
+            smm_f4 accC[SM_IB];   // CE_i blocks w, w + 8, w + 16 of the 4 x 6 blocks
+#pragma unroll
+            for (int k = 0; k < SM_IB; ++k) accC[k] = smm_f4{0.f, 0.f, 0.f, 0.f};
+            for (int j = 0; j + i <= deg; ++j) {
+                const int n = base + (i + j) * (i + j + 1) / 2 + j;
+                const float sgn = (j & 1) ? -1.f : 1.f;
+                __syncthreads();   // previous basis' E consumed
+                // E_n = (-1)^j c_n G, c_n(x, y) = sum_q Cy[q] yh^q, Cy[q] = sum_ie c[m(ie, q)] xh^ie
+                const cptr<float> cn_ = coefpf + (size_t)n * kSepCoefPad;
+#pragma unroll
+                for (int k = 0; k < SA_NI; ++k) {
+                    const int q = tid + k * SM_NT, xq = q / (SM_XR / 2), pr = q - xq * (SM_XR / 2);
+                    const float xh = fmaf(sxf, (float)(X0 - h + xq), oxf);
+                    float xpf[DSM + 1], cy[DSM + 1];
+                    xpf[0] = 1.f;
+#pragma unroll
+                    for (int qq = 1; qq <= DSM; ++qq) xpf[qq] = xpf[qq - 1] * xh;
+#pragma unroll
+                    for (int qq = 0; qq <= DSM; ++qq) cy[qq] = 0.f;
+                    int m = 0;
+#pragma unroll
+                    for (int tt = 0; tt <= DSM; ++tt) {
+#pragma unroll
+                        for (int ie = tt; ie >= 0; --ie) cy[tt - ie] = fmaf(cn_[m + tt - ie], xpf[ie], cy[tt - ie]);
+                        m += tt + 1;
+                    }
+                    float v[2];
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const float yh = fmaf(syf, (float)(Y0 - h + 2 * pr + e), oyf);
+                        float cn = cy[DSM];
+#pragma unroll
+                        for (int qq = DSM - 1; qq >= 0; --qq) cn = fmaf(cn, yh, cy[qq]);
+                        v[e] = sgn * cn * gv[k][e];
+                    }
+                    uint32_t hi2, lo2;
+                    smm_split2<false>(v[0], v[1], hi2, lo2);
+                    *reinterpret_cast<uint32_t*>(et + xq * SM_P + 2 * pr) = hi2;
+                    *reinterpret_cast<uint32_t*>(et + (SM_XR + xq) * SM_P + 2 * pr) = lo2;
+                }
+                __syncthreads();
+                // column pass: block (rb, cb) = (blk mod 4, blk / 4), A = taps of f_j,
+                // B = E at columns 16 cb + (lane mod 16), rows 16 rb + [0, 64)
+                uint4 tf[2][2];
+                smm_load_frag(fg + (size_t)j * SM_FRAG, lane, tf);
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    uint4 eh[SM_IB], el[SM_IB];
+#pragma unroll
+                    for (int k = 0; k < SM_IB; ++k) {
+                        const int blk = w + k * SM_NW, rb = blk & 3, cb = blk >> 2;
+                        const int off = (16 * cb + j16) * SM_P + 16 * rb + 32 * c + 8 * g4;
+                        eh[k] = *reinterpret_cast<const uint4*>(et + off);
+                        el[k] = *reinterpret_cast<const uint4*>(et + SM_XR * SM_P + off);
+                    }
+#pragma unroll
+                    for (int k = 0; k < SM_IB; ++k) accC[k] = smm_mfma<false>(tf[c][0], eh[k], accC[k]);
+#pragma unroll
+                    for (int k = 0; k < SM_IB; ++k) accC[k] = smm_mfma<false>(tf[c][0], el[k], accC[k]);
+#pragma unroll
+                    for (int k = 0; k < SM_IB; ++k) accC[k] = smm_mfma<false>(tf[c][1], eh[k], accC[k]);
+                }
+            }
+            // CE_i (sign (-1)^i) split row-major: lane (g4, j16) holds rows
+            // 16 rb + 4 g4 + e, column 16 cb + j16
+            __syncthreads();   // previous round's CE consumed
+            {
+                const float sgi = (i & 1) ? -1.f : 1.f;
+#pragma unroll
+                for (int k = 0; k < SM_IB; ++k) {
+                    const int blk = w + k * SM_NW, rb = blk & 3, cb = blk >> 2;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        uint32_t hi, lo;
+                        smm_split<false>(sgi * accC[k][e], hi, lo);
+                        const int off = (16 * rb + 4 * g4 + e) * SM_P + 16 * cb + j16;
+                        ce[off] = (uint16_t)hi;
+                        ce[64 * SM_P + off] = (uint16_t)lo;
+                    }
+                }
+            }
+            __syncthreads();
+            // row pass: block (rb, cb) = (blk / 4, blk mod 4), A = CE at rows
+            // 16 rb + (lane mod 16), columns 16 cb + [0, 64), B = taps of f_i
+            {
+                uint4 tf[2][2];
+                smm_load_frag(fg + (size_t)i * SM_FRAG, lane, tf);
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    uint4 chh[2], chl[2];
+#pragma unroll
+                    for (int k = 0; k < 2; ++k) {
+                        const int blk = w + k * SM_NW, rb = blk >> 2, cb = blk & 3;
+                        const int off = (16 * rb + j16) * SM_P + 16 * cb + 32 * c + 8 * g4;
+                        chh[k] = *reinterpret_cast<const uint4*>(ce + off);
+                        chl[k] = *reinterpret_cast<const uint4*>(ce + 64 * SM_P + off);
+                    }
+#pragma unroll
+                    for (int k = 0; k < 2; ++k) accR[k] = smm_mfma<false>(chh[k], tf[c][0], accR[k]);
+#pragma unroll
+                    for (int k = 0; k < 2; ++k) accR[k] = smm_mfma<false>(chl[k], tf[c][0], accR[k]);
+#pragma unroll
+                    for (int k = 0; k < 2; ++k) accR[k] = smm_mfma<false>(chh[k], tf[c][1], accR[k]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int blk = w + k * SM_NW, rb = blk >> 2, cb = blk & 3;
+        const int x = X0 + 16 * cb + j16;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int y = Y0 + 16 * rb + 4 * g4 + e;
+            if (x < a.W && y < a.H) a.out[(size_t)y * a.W + x] = accR[k][e];
+        }
+    }
+}
+
+int launch_adjoint_r_sep_mma(SepArgs a, const uint16_t* frag, hipStream_t s) {
+    if (a.h < 1 || a.h > 15) return fail(SVCONV_EUNSUPPORTED, "separable form needs 1 <= half-width <= 15");
+    a.tiles_x = (a.W + 63) / 64;
+    a.n_tiles = a.tiles_x * ((a.H + 63) / 64);
+    if (a.d_s <= 2)
+        hipLaunchKernelGGL(adjoint_r_sepmm_kernel<2>, dim3(a.n_tiles), dim3(SM_NT), SM_LDS, s, a, frag);
+    else if (a.d_s <= 4)
+        hipLaunchKernelGGL(adjoint_r_sepmm_kernel<4>, dim3(a.n_tiles), dim3(SM_NT), SM_LDS, s, a, frag);
+    else
+        hipLaunchKernelGGL(adjoint_r_sepmm_kernel<kMaxSpatialDegree>, dim3(a.n_tiles), dim3(SM_NT), SM_LDS, s, a, frag);
+    return hip_status(hipGetLastError(), "adjoint_r_sepmm_kernel");
+}
+
 }  // namespace svc

@@ -106,3 +106,54 @@ def test_full_chip_sampled(svc, orc, precision):
     say("  max %.3e (%.2e sigma) over %d pixels" % (e.max(), e.max() / np.sqrt(1000), len(ys)))
     assert e.max() <= TOL_MFMA
     assert np.all(np.isfinite(D))
+
+
+# ------------------------------------ adjoint in R on the matrix cores ----
+# The split precisions route the separable adjoint in R through the Toeplitz
+# fragments (bf16x3 for both); its error is bounded by a multiple of the
+# magnitude sums, like the float32 adjoints, with the bf16x3 products' 2^-16.
+MMA_ADJ_REL = 2e-4
+
+
+@pytest.mark.parametrize("precision", ["fp16x3", "bf16x3"])
+def test_adjoint_R_mma_vs_oracle_c3_crop(svc, orc, precision):
+    from tests.test_gpu_backward import crop_case, C3
+    R, I, a, B, frame = crop_case(orc, C3)
+    h, d_s = C3.half_width, C3.spatial_degree
+    D = orc.difference(R, I, h, B, d_s, a, frame=frame)
+    G = (2.0 * D * orc.interior_mask(*R.shape, h)).astype(np.float32)
+    gR_ref = orc.grad_R(R.shape, h, B, d_s, a, G, frame=frame)
+    sR = orc.grad_R(R.shape, h, np.abs(B), 0, np.abs(a).sum(axis=1, keepdims=True), np.abs(G),
+                    frame=frame)
+    say("matrix-core separable adjoint in R, c3 crop,", precision)
+    with svc.Plan(R.shape[0], R.shape[1], h, C3.sigmas, C3.degrees, d_s, precision=precision,
+                  form="separable", frame=frame) as plan:
+        gR, _ = plan.backward(to_dev(R), to_dev(a), to_dev(G), want_ga=False)
+        gR = to_host(gR)
+    e = np.abs(gR - gR_ref)
+    say("  max err %.3e (scale %.3e), max err / scale %.3e" % (e.max(), sR.max(), (e / (sR + 1e-30)).max()))
+    assert np.all(e <= MMA_ADJ_REL * sR + 1e-5)
+
+
+@pytest.mark.parametrize("name", ["h1_ragged", "nb3_degree3", "max_filters_64",
+                                  "max_spatial_degree_6", "single_column", "single_row",
+                                  "all_border_8x8", "c1_kernel_ragged_crop", "one_pixel_h1"])
+def test_adjoint_R_mma_edge_cases(svc, orc, name):
+    if name == "one_pixel_h1":
+        case = (1, 1, 1, (1.5,), (1,), 1, None)
+    else:
+        case = EDGE_CASES[name]
+    H, W, h, sig, deg, d_s, frame = case
+    R, I, a = _edge_inputs(name, case)
+    G = synth.uniform_image(H, W, seed=19, lo=-40.0, hi=40.0)
+    B = orc.basis(h, sig, deg)
+    gR_ref = orc.grad_R((H, W), h, B, d_s, a, G, frame=frame)
+    sR = orc.grad_R((H, W), h, np.abs(B), 0, np.abs(a).sum(axis=1, keepdims=True), np.abs(G),
+                    frame=frame)
+    say("matrix-core separable adjoint in R, edge", name)
+    with svc.Plan(H, W, h, sig, deg, d_s, precision="fp16x3", form="separable", frame=frame) as plan:
+        gR, _ = plan.backward(to_dev(R), to_dev(a), to_dev(G), want_ga=False)
+        gR = to_host(gR)
+    e = np.abs(gR - gR_ref)
+    say("  max err %.3e (scale %.3e)" % (e.max(), sR.max()))
+    assert np.all(e <= MMA_ADJ_REL * sR + 1e-5)
