@@ -86,14 +86,19 @@ enum svconv_form { SVCONV_FORM_BASIS = 0, SVCONV_FORM_REGROUPED = 1, SVCONV_FORM
  * vector units (row responses held in float32); with SVCONV_FP16X3,
  * SVCONV_BF16X3 or SVCONV_FP16X2 the forward passes run on the matrix cores
  * as banded Toeplitz products of 16-bit hi/lo parts with float32
- * accumulation (the coefficient weighting and the sums over the bases in
- * float32 / float64 on the vector units).  In this form svconv_backward,
- * svconv_normal_matrix, svconv_gn_step and svconv_pcg_fit also go through the
- * factors; the adjoints and the basis responses of the normal matrix always in
- * float64 (the adjoint in a falls back to the matrix-core product when its
- * per-round moments do not fit in LDS).  The adjoint in a sums with LDS atomics, so repeated calls
- * agree to float64 rounding rather than bit for bit.  EUNSUPPORTED for
- * delta-basis plans. */
+ * accumulation (the coefficient weighting and the sum over the bases in
+ * float32 on the vector units, the pedestal restore in float64).  In this
+ * form svconv_backward, svconv_normal_matrix, svconv_gn_step and
+ * svconv_pcg_fit also go through the factors: with SVCONV_FP16X3 or
+ * SVCONV_BF16X3 the adjoint in R runs on the matrix cores too (bf16 hi/lo
+ * parts for both, which keep the float32 range of c_n gD; the correlation as
+ * the convolution with the mirrored factors f_e(-w) = (-1)^e f_e(w)); the
+ * adjoint in a, the adjoint in R at the other precisions and the basis
+ * responses of the normal matrix run in float64 (the adjoint in a falls
+ * back to the matrix-core product when its per-round moments do not fit in
+ * LDS).  The adjoint in a sums with LDS atomics, so repeated calls agree to
+ * float64 rounding rather than bit for bit.  EUNSUPPORTED for delta-basis
+ * plans. */
 
 /*
  * Create a plan for images of height x width with a (2 half_width + 1)^2
