@@ -97,6 +97,15 @@ __device__ __forceinline__ void smm_split2(float x0, float x1, uint32_t& hi2, ui
     }
 }
 
+// bf16 hi by truncation (the low 16 bits of the float32 cleared), lo the
+// remainder x - hi (exact in float32) rounded to nearest even: 2^-16 |x|, as
+// the rounded split, at fewer instructions.
+__device__ __forceinline__ void smm_split_bft(float x, uint32_t& hi, uint32_t& lo) {
+    const uint32_t u = __float_as_uint(x) & 0xffff0000u;
+    hi = u >> 16;
+    lo = smm_f2bf(x - __uint_as_float(u));
+}
+
 template <bool FP16>
 __device__ __forceinline__ smm_f4 smm_mfma(const uint4& a, const uint4& b, smm_f4 c) {
     if constexpr (FP16) {
@@ -401,15 +410,20 @@ int launch_contract_sep_mma(SepArgs a, const uint16_t* frag, int precision, hipS
 // row factor i in the matrix-core accumulators (4 x 6 blocks, 3 per wave); then
 // CE_i is split row-major into LDS and the row pass dR += f_i (x)_x CE_i
 // accumulates over all rounds (4 x 4 blocks, 2 per wave).  bf16 keeps the
-// float32 range of c_n G; three products per pass as in the forward.
+// float32 range of c_n G (hi by truncation, lo rounded); three products per
+// pass as in the forward.
 constexpr int SA_NI = 9;                  // E entries per thread and basis, as row pairs
 static_assert(SM_XR * (SM_XR / 2) == SA_NI * SM_NT, "E row pairs must spread evenly over the threads");
+constexpr int SA_CYP = 8;                 // Cy entries per staged column (spatial degree <= 7)
+constexpr size_t SA_LDS = SM_LDS + (size_t)SM_XR * SA_CYP * sizeof(float);   // 78 KB: two workgroups per CU
+static_assert(kMaxSpatialDegree + 1 <= SA_CYP, "Cy table too narrow");
 
 template <int DSM>
 __global__ __launch_bounds__(SM_NT, SM_MINW) void adjoint_r_sepmm_kernel(SepArgs a, const uint16_t* __restrict__ frag) {
     extern __shared__ uint4 smm_lds[];
     uint16_t* et = reinterpret_cast<uint16_t*>(smm_lds);   // [2][SM_XR columns][SM_P]: E_n, rows contiguous
     uint16_t* ce = et + 2 * SM_XR * SM_P;                    // [2][64 rows][SM_P]: CE_i, columns contiguous
+    float* cyt = reinterpret_cast<float*>(ce + 2 * 64 * SM_P);  // [SM_XR][SA_CYP]: Cy of the basis per column
 
     const int h = a.h;
     const int CA = 64 + 2 * h;
@@ -456,26 +470,27 @@ __global__ __launch_bounds__(SM_NT, SM_MINW) void adjoint_r_sepmm_kernel(SepArgs
             for (int j = 0; j + i <= deg; ++j) {
                 const int n = base + (i + j) * (i + j + 1) / 2 + j;
                 const float sgn = (j & 1) ? -1.f : 1.f;
-                __syncthreads();   // previous basis' E consumed
-                // E_n = (-1)^j c_n G, c_n(x, y) = sum_q Cy[q] yh^q, Cy[q] = sum_ie c[m(ie, q)] xh^ie
-                const cptr<float> cn_ = coefpf + (size_t)n * kSepCoefPad;
+                __syncthreads();   // previous basis' E and Cy consumed
+                // c_n(x, y) = sum_q Cy[q](x) yh^q with Cy[q] = sum_{t >= q} c[t (t + 1) / 2 + q] xh^(t - q)
+                // (the monomial x^(t-q) y^q), per staged column into LDS
+                {
+                    const cptr<float> cn_ = coefpf + (size_t)n * kSepCoefPad;
+                    for (int e = tid; e < SM_XR * (DSM + 1); e += SM_NT) {
+                        const int xq = e / (DSM + 1), qq = e - xq * (DSM + 1);
+                        const float xh = fmaf(sxf, (float)(X0 - h + xq), oxf);
+                        float cy = 0.f;
+                        for (int tt = DSM; tt >= qq; --tt) cy = fmaf(cy, xh, cn_[tt * (tt + 1) / 2 + qq]);
+                        cyt[xq * SA_CYP + qq] = cy;
+                    }
+                }
+                __syncthreads();
+                // E_n = (-1)^j c_n G
 #pragma unroll
                 for (int k = 0; k < SA_NI; ++k) {
                     const int q = tid + k * SM_NT, xq = q / (SM_XR / 2), pr = q - xq * (SM_XR / 2);
-                    const float xh = fmaf(sxf, (float)(X0 - h + xq), oxf);
-                    float xpf[DSM + 1], cy[DSM + 1];
-                    xpf[0] = 1.f;
+                    float cy[DSM + 1];
 #pragma unroll
-                    for (int qq = 1; qq <= DSM; ++qq) xpf[qq] = xpf[qq - 1] * xh;
-#pragma unroll
-                    for (int qq = 0; qq <= DSM; ++qq) cy[qq] = 0.f;
-                    int m = 0;
-#pragma unroll
-                    for (int tt = 0; tt <= DSM; ++tt) {
-#pragma unroll
-                        for (int ie = tt; ie >= 0; --ie) cy[tt - ie] = fmaf(cn_[m + tt - ie], xpf[ie], cy[tt - ie]);
-                        m += tt + 1;
-                    }
+                    for (int qq = 0; qq <= DSM; ++qq) cy[qq] = cyt[xq * SA_CYP + qq];
                     float v[2];
 #pragma unroll
                     for (int e = 0; e < 2; ++e) {
@@ -485,10 +500,11 @@ __global__ __launch_bounds__(SM_NT, SM_MINW) void adjoint_r_sepmm_kernel(SepArgs
                         for (int qq = DSM - 1; qq >= 0; --qq) cn = fmaf(cn, yh, cy[qq]);
                         v[e] = sgn * cn * gv[k][e];
                     }
-                    uint32_t hi2, lo2;
-                    smm_split2<false>(v[0], v[1], hi2, lo2);
-                    *reinterpret_cast<uint32_t*>(et + xq * SM_P + 2 * pr) = hi2;
-                    *reinterpret_cast<uint32_t*>(et + (SM_XR + xq) * SM_P + 2 * pr) = lo2;
+                    uint32_t h0, l0, h1, l1;
+                    smm_split_bft(v[0], h0, l0);
+                    smm_split_bft(v[1], h1, l1);
+                    *reinterpret_cast<uint32_t*>(et + xq * SM_P + 2 * pr) = h0 | (h1 << 16);
+                    *reinterpret_cast<uint32_t*>(et + (SM_XR + xq) * SM_P + 2 * pr) = l0 | (l1 << 16);
                 }
                 __syncthreads();
                 // column pass: block (rb, cb) = (blk mod 4, blk / 4), A = taps of f_j,
@@ -524,7 +540,7 @@ __global__ __launch_bounds__(SM_NT, SM_MINW) void adjoint_r_sepmm_kernel(SepArgs
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         uint32_t hi, lo;
-                        smm_split<false>(sgi * accC[k][e], hi, lo);
+                        smm_split_bft(sgi * accC[k][e], hi, lo);
                         const int off = (16 * rb + 4 * g4 + e) * SM_P + 16 * cb + j16;
                         ce[off] = (uint16_t)hi;
                         ce[64 * SM_P + off] = (uint16_t)lo;
@@ -574,11 +590,11 @@ int launch_adjoint_r_sep_mma(SepArgs a, const uint16_t* frag, hipStream_t s) {
     a.tiles_x = (a.W + 63) / 64;
     a.n_tiles = a.tiles_x * ((a.H + 63) / 64);
     if (a.d_s <= 2)
-        hipLaunchKernelGGL(adjoint_r_sepmm_kernel<2>, dim3(a.n_tiles), dim3(SM_NT), SM_LDS, s, a, frag);
+        hipLaunchKernelGGL(adjoint_r_sepmm_kernel<2>, dim3(a.n_tiles), dim3(SM_NT), SA_LDS, s, a, frag);
     else if (a.d_s <= 4)
-        hipLaunchKernelGGL(adjoint_r_sepmm_kernel<4>, dim3(a.n_tiles), dim3(SM_NT), SM_LDS, s, a, frag);
+        hipLaunchKernelGGL(adjoint_r_sepmm_kernel<4>, dim3(a.n_tiles), dim3(SM_NT), SA_LDS, s, a, frag);
     else
-        hipLaunchKernelGGL(adjoint_r_sepmm_kernel<kMaxSpatialDegree>, dim3(a.n_tiles), dim3(SM_NT), SM_LDS, s, a, frag);
+        hipLaunchKernelGGL(adjoint_r_sepmm_kernel<kMaxSpatialDegree>, dim3(a.n_tiles), dim3(SM_NT), SA_LDS, s, a, frag);
     return hip_status(hipGetLastError(), "adjoint_r_sepmm_kernel");
 }
 
