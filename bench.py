@@ -181,10 +181,12 @@ def main():
                 timed(lambda: plan3.backward(R3d, a3d, G3d, want_gR=False), n3), 4)
             adjoint["backward_dR_separable_ms"] = round(
                 timed(lambda: plan3.backward(R3d, a3d, G3d, want_ga=False), n3), 4)
-            # the split precisions take the adjoint in R on the matrix cores (bf16x3)
+            # the split precisions take both adjoints on the matrix cores
             plan3.set_precision("fp16x3")
             adjoint["backward_dR_separable_mma_ms"] = round(
                 timed(lambda: plan3.backward(R3d, a3d, G3d, want_ga=False), n3), 4)
+            adjoint["backward_da_separable_mma_ms"] = round(
+                timed(lambda: plan3.backward(R3d, a3d, G3d, want_gR=False), n3), 4)
             plan3.set_form("basis")
             plan3.set_precision("fp32")
             adjoint["backward_ms"] = round(timed(lambda: plan3.backward(R3d, a3d, G3d), n3), 4)
@@ -193,7 +195,8 @@ def main():
             adjoint["backward_da_ms"] = round(
                 timed(lambda: plan3.backward(R3d, a3d, G3d, want_gR=False), n3), 4)
             px3 = wl3.height * wl3.width
-            best_da = min(adjoint["backward_da_ms"], adjoint["backward_da_separable_ms"])
+            best_da = min(adjoint["backward_da_ms"], adjoint["backward_da_separable_ms"],
+                          adjoint["backward_da_separable_mma_ms"])
             best_dr = min(adjoint["backward_dR_ms"], adjoint["backward_dR_separable_ms"],
                           adjoint["backward_dR_separable_mma_ms"])
             best_fw = min(adjoint["forward_separable_ms"], adjoint["forward_separable_fp16x3_ms"])

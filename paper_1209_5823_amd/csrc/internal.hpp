@@ -86,10 +86,12 @@ struct SepArgs {
     const double* gammap;       // [kSepCoefPad] gamma padded likewise (sep_prep)
     const float* coefpf;        // [N][kSepCoefPad] float32 copy of coefp (sep_prep)
     int M, d_s;
+    int N;                      // bases (the adjoint in a)
     double sx, ox, sy, oy;
     int tiles_x, n_tiles;
     int y_begin, n_rows;        // output rows [y_begin, y_begin + n_rows)
     float* tout;                // nullable: T_n + s beta_n planes [N][n_rows][W] instead of D
+    double* mom;                // adjoint in a on the matrix cores: [kSepMomCopies][N + 1][M] sums
 };
 
 }  // namespace svc
@@ -114,6 +116,7 @@ struct svconv_plan {
     double* dSepCoef = nullptr;         // [N + 1][kSepCoefPad] padded coefficients and gamma, then
                                         // the coefficients again in float32 (same layout)
     uint16_t* dSepFrag = nullptr;       // matrix-core Toeplitz fragments of the factors (fp16, bf16)
+    double* dSepMom = nullptr;          // moment sums of the matrix-core adjoint in a
 
     // device tables (basis form, fixed per plan)
     float* dF32 = nullptr;              // [N][k][k] correlation-oriented basis, float32
@@ -171,6 +174,11 @@ int build_sep_mma_fragments(const double* f1d, int G, int h, uint16_t* frag, hip
 int launch_contract_sep_mma(SepArgs a, const uint16_t* frag, int precision, hipStream_t s);
 // adjoint in R through the separable factors on the matrix cores (bf16x3); a.X = G, a.out = dL/dR
 int launch_adjoint_r_sep_mma(SepArgs a, const uint16_t* frag, hipStream_t s);
+// adjoint in a through the separable factors on the matrix cores: a.X = R, a.I = G,
+// ga[n][m] = sum_p G P_m T_n (the split precision's products) + s beta_n sum_p G P_m
+constexpr int kSepMomCopies = 8;        // copies of the moment sums the tiles spread their atomics over
+int launch_adjoint_a_sep_mma(SepArgs a, const uint16_t* frag, int precision, const double* beta,
+                             double* ga, hipStream_t s);
 int launch_adjoint_a_sep(svconv_plan* p, const float* R, const float* G, double* ga);
 bool sep_adjoint_supported(const svconv_plan* p);
 int launch_adjoint_r_sep(svconv_plan* p, const float* a32, const float* G, float* gR);

@@ -71,7 +71,7 @@ static int dalloc(T** p, size_t count, const char* what) {
 }
 
 static void free_plan(svconv_plan* p) {
-    void* ptrs[] = {p->dSep1d, p->dSepFam, p->dSepCoef, p->dSepFrag,
+    void* ptrs[] = {p->dSep1d, p->dSepFam, p->dSepCoef, p->dSepFrag, p->dSepMom,
                     p->dF32,   p->dF64,   p->dBeta,   p->dFragF32, p->dFragLoB, p->dFragLoH,
                     p->dScaleB, p->dScaleH, p->dFt32, p->dBetaT, p->dFragT32, p->dFragTB,  p->dFragTH,
                     p->dScaleT, p->dQpart, p->dQ,    p->dGrad,    p->dVec,     p->dStatus,
@@ -203,6 +203,7 @@ static int finish_plan(svconv_plan* p, svconv_plan** out) {
         if (!st && h <= 15) {
             st = dalloc(&p->dSepFrag, sep_mma_frag_entries(G), "separable matrix-core fragments");
             if (!st) st = build_sep_mma_fragments(p->dSep1d, G, h, p->dSepFrag, nullptr);
+            if (!st) st = dalloc(&p->dSepMom, (size_t)kSepMomCopies * (p->N + 1) * p->M, "separable moments");
         }
     }
     if (!st && p->N <= kMaxFilters) {
@@ -538,7 +539,31 @@ int svconv_backward(svconv_plan* p, const float* R, const float* a, const float*
         st = launch_contract_f32(c, p->dFragT32, (p->M + 15) / 16, p->stream);
         if (st) return st;
     }
-    if (ga) st = launch_adjoint_a(p, R, gD, ga);
+    if (ga && p->form == SVCONV_FORM_SEPARABLE &&
+        (p->precision == SVCONV_FP16X3 || p->precision == SVCONV_BF16X3) && p->dSepFrag && p->dSepMom) {
+        // the forward's matrix-core passes with moment sums in place of the epilogue
+        ContractArgs c{};
+        coords(p, c);
+        SepArgs sa{};
+        sa.X = R;
+        sa.I = gD;
+        sa.H = p->H;
+        sa.W = p->W;
+        sa.h = p->h;
+        sa.ped = p->pedestal;
+        sa.G = (int)p->sigmas.size();
+        sa.fam = p->dSepFam;
+        sa.M = p->M;
+        sa.d_s = p->d_s;
+        sa.sx = c.sx; sa.ox = c.ox; sa.sy = c.sy; sa.oy = c.oy;
+        sa.y_begin = 0;
+        sa.n_rows = p->H;
+        sa.N = p->N;
+        sa.mom = p->dSepMom;
+        st = launch_adjoint_a_sep_mma(sa, p->dSepFrag, p->precision, p->dBeta, ga, p->stream);
+    } else if (ga) {
+        st = launch_adjoint_a(p, R, gD, ga);
+    }
     return st;
 }
 

@@ -161,7 +161,13 @@ __device__ __forceinline__ void smm_load_frag(const uint16_t* tab, int lane, uin
             f[c][hl] = *reinterpret_cast<const uint4*>(tab + ((c * 2 + hl) * 64 + lane) * 8);
 }
 
-template <bool FP16, int NT, int DSM>
+// ADJ: the adjoint in a instead of D.  The same passes give T_n(R - s) on the
+// tile; the epilogue forms the moments sum_p G P_m T_n of the tile (per lane
+// over its 8 pixels in powers of yh, over the 4 lanes of a column, weighted by
+// the column's powers of xh, over the 16 columns of the wave) and adds them to
+// one of kSepMomCopies copies of the sums (float64 atomics); slot N holds
+// sum_p G P_m for the pedestal term.
+template <bool FP16, int NT, int DSM, bool ADJ = false>
 __global__ __launch_bounds__(SM_NT, SM_MINW) void contract_sepmm_kernel(SepArgs a, const uint16_t* __restrict__ frag) {
     extern __shared__ uint4 smm_lds[];
     uint16_t* xs = reinterpret_cast<uint16_t*>(smm_lds);   // [2][SM_XR][SM_P]
@@ -226,6 +232,49 @@ __global__ __launch_bounds__(SM_NT, SM_MINW) void contract_sepmm_kernel(SepArgs 
             acc32[b][e] = 0.f;
         }
     const cptr<float> coefpf = as_const(a.coefpf);
+
+    // adjoint in a: G at this lane's 8 output pixels (0 outside the image)
+    float gq[2][4];
+    double* mom = ADJ ? a.mom + (size_t)(blockIdx.x % kSepMomCopies) * (a.N + 1) * a.M : nullptr;
+    auto flush = [&](int slot, float (&S)[DSM + 1]) {
+#pragma unroll
+        for (int q = 0; q <= DSM; ++q) {
+            S[q] += __shfl_xor(S[q], 16);
+            S[q] += __shfl_xor(S[q], 32);
+        }
+        // monomial m = tt (tt + 1) / 2 + jj is xh^(tt - jj) yh^jj; lane m keeps sum m
+        float mine = 0.f;
+        int m = 0;
+#pragma unroll
+        for (int tt = 0; tt <= DSM; ++tt)
+#pragma unroll
+            for (int jj = 0; jj <= tt; ++jj, ++m) {
+                float v = xpf[tt - jj] * S[jj];
+#pragma unroll
+                for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o);
+                if (lane == m) mine = v;
+            }
+        if (lane < a.M) atomicAdd(mom + (size_t)slot * a.M + lane, (double)mine);
+    };
+    if constexpr (ADJ) {
+        float S[DSM + 1];
+#pragma unroll
+        for (int q = 0; q <= DSM; ++q) S[q] = 0.f;
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int y = Y0 + 16 * (rb0 + b) + 4 * g4 + e;
+                gq[b][e] = (x < a.W && y < y_end) ? a.I[(size_t)y * a.W + x] : 0.f;
+                float tq = gq[b][e];
+#pragma unroll
+                for (int q = 0; q <= DSM; ++q) {
+                    S[q] += tq;
+                    tq *= yhf[b][e];
+                }
+            }
+        flush(a.N, S);   // sum_p G P_m
+    }
 
     __syncthreads();   // tile staged
     for (int g = 0; g < a.G; ++g) {
@@ -311,6 +360,24 @@ __global__ __launch_bounds__(SM_NT, SM_MINW) void contract_sepmm_kernel(SepArgs 
             };
             auto epilogue = [&](int j, const smm_f4 (&acc)[2]) {
                 const int n = base + (i + j) * (i + j + 1) / 2 + j;
+                if constexpr (ADJ) {
+                    float S[DSM + 1];
+#pragma unroll
+                    for (int q = 0; q <= DSM; ++q) S[q] = 0.f;
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            float tq = gq[b][e] * acc[b][e];
+#pragma unroll
+                            for (int q = 0; q <= DSM; ++q) {
+                                S[q] += tq;
+                                tq *= yhf[b][e];
+                            }
+                        }
+                    flush(n, S);
+                    return;
+                }
                 float cy[DSM + 1];
 #pragma unroll
                 for (int q = 0; q <= DSM; ++q) cy[q] = 0.f;
@@ -346,7 +413,7 @@ __global__ __launch_bounds__(SM_NT, SM_MINW) void contract_sepmm_kernel(SepArgs 
             }
         }
     }
-    if (x < a.W) {
+    if (!ADJ && x < a.W) {
         // pedestal restore s sum_m gamma_m P_m (float64), then D = sum_n c_n T_n - I
         double xpow[DSM + 1];
         xpow[0] = 1.0;
@@ -395,6 +462,58 @@ int launch_contract_sep_mma(SepArgs a, const uint16_t* frag, int precision, hipS
     }
 }
 
+
+__global__ void sep_mom_zero(double* __restrict__ mom, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) mom[i] = 0.0;
+}
+
+// ga[n][m] = unscale sum_c mom[c][n][m] + s beta_n sum_c mom[c][N][m] (copies in order)
+__global__ void sep_mom_final(const double* __restrict__ mom, int N, int M, double unscale,
+                              const double* __restrict__ beta, float ped, double* __restrict__ ga) {
+    const int nm = blockIdx.x * blockDim.x + threadIdx.x;
+    if (nm >= N * M) return;
+    const int n = nm / M, m = nm - n * M;
+    const size_t stride = (size_t)(N + 1) * M;
+    double s = 0.0, gp = 0.0;
+    for (int c = 0; c < kSepMomCopies; ++c) {
+        s += mom[c * stride + nm];
+        gp += mom[c * stride + (size_t)N * M + m];
+    }
+    ga[nm] = unscale * s + (double)ped * beta[n] * gp;
+}
+
+template <bool FP16>
+static int launch_asepmm_p(const SepArgs& a, const uint16_t* frag, hipStream_t s) {
+    if (a.d_s <= 2)
+        hipLaunchKernelGGL((contract_sepmm_kernel<FP16, 3, 2, true>), dim3(a.n_tiles), dim3(SM_NT), SM_LDS, s, a, frag);
+    else if (a.d_s <= 4)
+        hipLaunchKernelGGL((contract_sepmm_kernel<FP16, 3, 4, true>), dim3(a.n_tiles), dim3(SM_NT), SM_LDS, s, a, frag);
+    else
+        hipLaunchKernelGGL((contract_sepmm_kernel<FP16, 3, kMaxSpatialDegree, true>), dim3(a.n_tiles), dim3(SM_NT),
+                           SM_LDS, s, a, frag);
+    return hip_status(hipGetLastError(), "contract_sepmm_kernel (adjoint in a)");
+}
+
+int launch_adjoint_a_sep_mma(SepArgs a, const uint16_t* frag, int precision, const double* beta,
+                             double* ga, hipStream_t s) {
+    if (a.h < 1 || a.h > 15) return fail(SVCONV_EUNSUPPORTED, "separable form needs 1 <= half-width <= 15");
+    if (a.M > 64) return fail(SVCONV_EUNSUPPORTED, "matrix-core adjoint in a needs M <= 64");
+    a.tiles_x = (a.W + 63) / 64;
+    a.n_tiles = a.tiles_x * ((a.n_rows + 63) / 64);
+    a.tout = nullptr;
+    const int n_mom = kSepMomCopies * (a.N + 1) * a.M;
+    hipLaunchKernelGGL(sep_mom_zero, dim3((n_mom + 255) / 256), dim3(256), 0, s, a.mom, n_mom);
+    int st = hip_status(hipGetLastError(), "sep_mom_zero");
+    if (st) return st;
+    const bool fp16 = precision == SVCONV_FP16X3;
+    st = fp16 ? launch_asepmm_p<true>(a, frag, s) : launch_asepmm_p<false>(a, frag, s);
+    if (st) return st;
+    const int NM = a.N * a.M;
+    hipLaunchKernelGGL(sep_mom_final, dim3((NM + 255) / 256), dim3(256), 0, s, a.mom, a.N, a.M,
+                       fp16 ? 4.0 : 1.0, beta, a.ped, ga);
+    return hip_status(hipGetLastError(), "sep_mom_final");
+}
 
 // ------------------------------------------------------- adjoint in R ----
 //

@@ -157,3 +157,52 @@ def test_adjoint_R_mma_edge_cases(svc, orc, name):
     e = np.abs(gR - gR_ref)
     say("  max err %.3e (scale %.3e)" % (e.max(), sR.max()))
     assert np.all(e <= MMA_ADJ_REL * sR + 1e-5)
+
+
+# ------------------------------------ adjoint in a on the matrix cores ----
+# The split precisions take the adjoint in a through the forward's Toeplitz
+# passes, with the moment sums sum_p G P_m T_n in place of the epilogue; bound:
+# a multiple of the magnitude sums sum_p |G| |T_n|, ten times the float32
+# adjoints' (the products of the split precision and float32 tile sums).
+MMA_ADJ_A_REL = 2e-4
+
+
+@pytest.mark.parametrize("precision", ["fp16x3", "bf16x3"])
+@pytest.mark.parametrize("pedestal", [0.0, 1000.0])
+def test_adjoint_a_mma_vs_oracle_c3_crop(svc, orc, precision, pedestal):
+    from tests.test_gpu_backward import crop_case, C3
+    R, I, a, B, frame = crop_case(orc, C3)
+    h, d_s = C3.half_width, C3.spatial_degree
+    D = orc.difference(R, I, h, B, d_s, a, frame=frame)
+    G = (2.0 * D * orc.interior_mask(*R.shape, h)).astype(np.float32)
+    ga_ref = orc.grad_a(R, h, B, d_s, G, frame=frame)
+    sa = orc.grad_a(np.abs(R), h, np.abs(B), 0, np.abs(G), frame=frame)[:, :1]
+    say("matrix-core separable adjoint in a, c3 crop,", precision, "pedestal", pedestal)
+    with svc.Plan(R.shape[0], R.shape[1], h, C3.sigmas, C3.degrees, d_s, precision=precision,
+                  form="separable", frame=frame, pedestal=pedestal) as plan:
+        _, ga = plan.backward(to_dev(R), to_dev(a), to_dev(G), want_gR=False)
+        ga = to_host(ga)
+    e = np.abs(ga - ga_ref)
+    say("  max err %.3e (scale %.3e), max err / scale %.3e" % (e.max(), sa.max(), (e / sa).max()))
+    assert np.all(e <= MMA_ADJ_A_REL * sa + 1e-9)
+
+
+@pytest.mark.parametrize("name", ["h1_ragged", "nb3_degree3", "max_filters_64",
+                                  "max_spatial_degree_6", "single_column", "single_row",
+                                  "all_border_8x8", "c1_kernel_ragged_crop"])
+def test_adjoint_a_mma_edge_cases(svc, orc, name):
+    case = EDGE_CASES[name]
+    H, W, h, sig, deg, d_s, frame = case
+    R, I, a = _edge_inputs(name, case)
+    G = synth.uniform_image(H, W, seed=17, lo=-40.0, hi=40.0)
+    B = orc.basis(h, sig, deg)
+    ga_ref = orc.grad_a(R, h, B, d_s, G, frame=frame)
+    sa = orc.grad_a(np.abs(R), h, np.abs(B), 0, np.abs(G), frame=frame)[:, :1]
+    say("matrix-core separable adjoint in a, edge", name)
+    with svc.Plan(H, W, h, sig, deg, d_s, precision="fp16x3", form="separable", frame=frame,
+                  pedestal=synth.SKY_LEVEL) as plan:
+        _, ga = plan.backward(to_dev(R), to_dev(a), to_dev(G), want_gR=False)
+        ga = to_host(ga)
+    e = np.abs(ga - ga_ref)
+    say("  max err %.3e (scale %.3e)" % (e.max(), sa.max()))
+    assert np.all(e <= MMA_ADJ_A_REL * sa + 1e-9)
