@@ -97,6 +97,21 @@ __device__ __forceinline__ void smm_split2(float x0, float x1, uint32_t& hi2, ui
     }
 }
 
+// Sum over the 16 lanes of a DPP row, left in every lane of the row: mirror,
+// half mirror, then the two quad swaps pair the lanes so that each step doubles
+// the number of summed lanes.
+template <int CTRL>
+__device__ __forceinline__ float smm_dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float smm_row16_sum(float v) {
+    v += smm_dpp_mov<0x140>(v);   // row_mirror: lane i + lane 15 - i
+    v += smm_dpp_mov<0x141>(v);   // row_half_mirror: lane i + lane 7 - i within each half
+    v += smm_dpp_mov<0x4e>(v);    // quad_perm [2, 3, 0, 1]
+    v += smm_dpp_mov<0xb1>(v);    // quad_perm [1, 0, 3, 2]
+    return v;
+}
+
 // bf16 hi by truncation (the low 16 bits of the float32 cleared), lo the
 // remainder x - hi (exact in float32) rounded to nearest even: 2^-16 |x|, as
 // the rounded split, at fewer instructions.
@@ -249,9 +264,7 @@ __global__ __launch_bounds__(SM_NT, SM_MINW) void contract_sepmm_kernel(SepArgs 
         for (int tt = 0; tt <= DSM; ++tt)
 #pragma unroll
             for (int jj = 0; jj <= tt; ++jj, ++m) {
-                float v = xpf[tt - jj] * S[jj];
-#pragma unroll
-                for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o);
+                const float v = smm_row16_sum(xpf[tt - jj] * S[jj]);
                 if (lane == m) mine = v;
             }
         if (lane < a.M) atomicAdd(mom + (size_t)slot * a.M + lane, (double)mine);
