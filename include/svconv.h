@@ -90,15 +90,16 @@ enum svconv_form { SVCONV_FORM_BASIS = 0, SVCONV_FORM_REGROUPED = 1, SVCONV_FORM
  * float32 on the vector units, the pedestal restore in float64).  In this
  * form svconv_backward, svconv_normal_matrix, svconv_gn_step and
  * svconv_pcg_fit also go through the factors.  With SVCONV_FP16X3 or
- * SVCONV_BF16X3, svconv_backward runs both adjoints on the matrix cores: the
- * adjoint in R in bf16 hi/lo parts for both (they keep the float32 range of
- * c_n gD; the correlation as the convolution with the mirrored factors
+ * SVCONV_BF16X3, svconv_backward runs both adjoints on the matrix cores:
+ * the adjoint in R in bf16 hi/lo parts for both (they keep the float32 range
+ * of c_n gD; the correlation as the convolution with the mirrored factors
  * f_e(-w) = (-1)^e f_e(w)), the adjoint in a as the forward's passes in the
  * plan's split precision with moment sums in place of the epilogue.  At the
- * other precisions, and in the fit entry points, the adjoints and the basis
- * responses of the normal matrix run in float64 (the adjoint in a falls back
- * to the dense matrix-core product when its per-round moments do not fit in
- * LDS).  The adjoints in a sum with atomics, so repeated calls agree to
+ * other precisions, and in the fit entry points (whose steps go through the
+ * ill-conditioned normal matrix), the adjoints run in float64, and the basis
+ * responses of the normal matrix always do (the float64 adjoint in a falls
+ * back to the dense matrix-core product when its per-round moments do not
+ * fit in LDS).  The adjoints in a sum with atomics, so repeated calls agree to
  * float64 rounding rather than bit for bit.  EUNSUPPORTED for delta-basis
  * plans. */
 

@@ -480,6 +480,35 @@ int svconv_difference(svconv_plan* p, const float* R, const float* I, const floa
     return run_forward(p, R, I, a, D);
 }
 
+// Adjoint in a: with the separable form at a split precision, the forward's
+// matrix-core passes with moment sums in place of the epilogue; otherwise the
+// float64 separable kernel or the dense product.
+static int run_adjoint_a(svconv_plan* p, const float* R, const float* gD, double* ga) {
+    if (p->form == SVCONV_FORM_SEPARABLE && (p->precision == SVCONV_FP16X3 || p->precision == SVCONV_BF16X3) &&
+        p->dSepFrag && p->dSepMom) {
+        ContractArgs c{};
+        coords(p, c);
+        SepArgs sa{};
+        sa.X = R;
+        sa.I = gD;
+        sa.H = p->H;
+        sa.W = p->W;
+        sa.h = p->h;
+        sa.ped = p->pedestal;
+        sa.G = (int)p->sigmas.size();
+        sa.fam = p->dSepFam;
+        sa.M = p->M;
+        sa.d_s = p->d_s;
+        sa.sx = c.sx; sa.ox = c.ox; sa.sy = c.sy; sa.oy = c.oy;
+        sa.y_begin = 0;
+        sa.n_rows = p->H;
+        sa.N = p->N;
+        sa.mom = p->dSepMom;
+        return launch_adjoint_a_sep_mma(sa, p->dSepFrag, p->precision, p->dBeta, ga, p->stream);
+    }
+    return launch_adjoint_a(p, R, gD, ga);
+}
+
 int svconv_backward(svconv_plan* p, const float* R, const float* a, const float* gD, float* gR,
                     double* ga) {
     if (!p || !R || !a || !gD) return fail(SVCONV_EINVAL, "NULL argument");
@@ -539,31 +568,7 @@ int svconv_backward(svconv_plan* p, const float* R, const float* a, const float*
         st = launch_contract_f32(c, p->dFragT32, (p->M + 15) / 16, p->stream);
         if (st) return st;
     }
-    if (ga && p->form == SVCONV_FORM_SEPARABLE &&
-        (p->precision == SVCONV_FP16X3 || p->precision == SVCONV_BF16X3) && p->dSepFrag && p->dSepMom) {
-        // the forward's matrix-core passes with moment sums in place of the epilogue
-        ContractArgs c{};
-        coords(p, c);
-        SepArgs sa{};
-        sa.X = R;
-        sa.I = gD;
-        sa.H = p->H;
-        sa.W = p->W;
-        sa.h = p->h;
-        sa.ped = p->pedestal;
-        sa.G = (int)p->sigmas.size();
-        sa.fam = p->dSepFam;
-        sa.M = p->M;
-        sa.d_s = p->d_s;
-        sa.sx = c.sx; sa.ox = c.ox; sa.sy = c.sy; sa.oy = c.oy;
-        sa.y_begin = 0;
-        sa.n_rows = p->H;
-        sa.N = p->N;
-        sa.mom = p->dSepMom;
-        st = launch_adjoint_a_sep_mma(sa, p->dSepFrag, p->precision, p->dBeta, ga, p->stream);
-    } else if (ga) {
-        st = launch_adjoint_a(p, R, gD, ga);
-    }
+    if (ga) st = run_adjoint_a(p, R, gD, ga);
     return st;
 }
 
@@ -603,6 +608,8 @@ int svconv_gn_step(svconv_plan* p, const float* R, const float* I, const unsigne
     if (!st) st = run_forward(p, R, I, a32, D);
     if (!st && p->bg) st = launch_add_background(p, a32 + NK, D);
     if (!st) st = launch_loss_grad(p, D, mask, p->dGrad, loss);
+    // the float64 adjoint: the split-precision one's error, through the
+    // ill-conditioned normal matrix, keeps the steps from shrinking
     if (!st) st = launch_adjoint_a(p, R, p->dGrad, ga);
     if (!st && p->bg) st = launch_bg_grad(p, p->dGrad, ga + NK);
     if (!st) st = launch_scale(p, ga, 0.5, NM);
