@@ -500,6 +500,8 @@ template <bool FP16>
 static int launch_asepmm_p(const SepArgs& a, const uint16_t* frag, hipStream_t s) {
     if (a.d_s <= 2)
         hipLaunchKernelGGL((contract_sepmm_kernel<FP16, 3, 2, true>), dim3(a.n_tiles), dim3(SM_NT), SM_LDS, s, a, frag);
+    else if (a.d_s == 3)
+        hipLaunchKernelGGL((contract_sepmm_kernel<FP16, 3, 3, true>), dim3(a.n_tiles), dim3(SM_NT), SM_LDS, s, a, frag);
     else if (a.d_s <= 4)
         hipLaunchKernelGGL((contract_sepmm_kernel<FP16, 3, 4, true>), dim3(a.n_tiles), dim3(SM_NT), SM_LDS, s, a, frag);
     else
@@ -723,6 +725,8 @@ int launch_adjoint_r_sep_mma(SepArgs a, const uint16_t* frag, hipStream_t s) {
     a.n_tiles = a.tiles_x * ((a.H + 63) / 64);
     if (a.d_s <= 2)
         hipLaunchKernelGGL(adjoint_r_sepmm_kernel<2>, dim3(a.n_tiles), dim3(SM_NT), SA_LDS, s, a, frag);
+    else if (a.d_s == 3)
+        hipLaunchKernelGGL(adjoint_r_sepmm_kernel<3>, dim3(a.n_tiles), dim3(SM_NT), SA_LDS, s, a, frag);
     else if (a.d_s <= 4)
         hipLaunchKernelGGL(adjoint_r_sepmm_kernel<4>, dim3(a.n_tiles), dim3(SM_NT), SA_LDS, s, a, frag);
     else
