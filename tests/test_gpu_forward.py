@@ -133,45 +133,42 @@ def test_full_size_sampled_fp32(svc, orc, wl_name):
 
 # ------------------------------------------------ bf16 / fp16 matrix cores ----
 
-LOWP = ["bf16x3", "fp16x3", "fp16x2"]
-# fp16x2 keeps the filters in one fp16 part: its 11-bit taps leave 1.1e-2 to
-# 1.5e-2 sigma_sky at the brightest stars of the chip (basis form) and up to
-# 5e-2 sigma with the regrouped filters of random coefficients, outside the
-# 1e-2 bound, so it is held to the level it reaches (6e-2 sigma) and is never
-# chosen as a headline form.
-TOL_FP16X2 = 6e-2 * np.sqrt(1000.0)
+# the split precisions that meet the matrix-core bound of 1e-2 sigma_sky
+LOWP = ["bf16x3", "fp16x3"]
 
 
-def lowp_tol(precision):
-    return TOL_FP16X2 if precision == "fp16x2" else TOL_MFMA
-
-
-@pytest.mark.parametrize("precision", LOWP + ["bf16", "fp16"])
-def test_c2_crops_lowp(svc, orc, precision):
-    # 512 x 512 crops of the 2048 x 4096 chip (centre and brightest star),
-    # frame coordinates of the chip, pedestal at the sky level
+def c2_crops(orc):
+    """The 512 x 512 crops of the 2048 x 4096 chip at its centre and at its
+    brightest star, with the oracle's D on each (frame coordinates of the chip)."""
     wl = synth.WORKLOADS["c2"]
     R, a = synth.workload_inputs(wl)
     I = synth.second_image(wl)
     B = orc.basis(wl.half_width, wl.sigmas, wl.degrees)
     yb, xb = np.unravel_index(np.argmax(R), R.shape)
-    crops = [(768, 1792), (int(np.clip(yb - 256, 0, wl.height - 512)),
-                           int(np.clip(xb - 256, 0, wl.width - 512)))]
-    for (y0, x0) in crops:
+    out = []
+    for (y0, x0) in [(768, 1792), (int(np.clip(yb - 256, 0, wl.height - 512)),
+                                   int(np.clip(xb - 256, 0, wl.width - 512)))]:
         Rc = np.ascontiguousarray(R[y0:y0 + 512, x0:x0 + 512])
         Ic = np.ascontiguousarray(I[y0:y0 + 512, x0:x0 + 512])
         frame = (x0, y0, wl.width, wl.height)
-        Dref = orc.difference(Rc, Ic, wl.half_width, B, wl.spatial_degree, a, frame=frame)
-        say("c2 crop", precision, (y0, x0))
+        out.append((Rc, Ic, a, frame, orc.difference(Rc, Ic, wl.half_width, B, wl.spatial_degree, a,
+                                                     frame=frame)))
+    return wl, out
+
+
+@pytest.mark.parametrize("precision", LOWP)
+def test_c2_crops_lowp(svc, orc, precision):
+    # 512 x 512 crops of the 2048 x 4096 chip (centre and brightest star),
+    # frame coordinates of the chip, pedestal at the sky level
+    wl, crops = c2_crops(orc)
+    for Rc, Ic, a, frame, Dref in crops:
+        say("c2 crop", precision, frame)
         D = run_difference(svc, Rc, Ic, a, wl.half_width, wl.sigmas, wl.degrees,
                            wl.spatial_degree, precision=precision, frame=frame,
                            pedestal=synth.SKY_LEVEL)
         mx, rms = err_stats(D, Dref)
         say("  max %.3e rms %.3e (%.2e sigma)" % (mx, rms, mx / np.sqrt(1000)))
-        if precision in LOWP:
-            assert mx <= lowp_tol(precision)
-        else:
-            assert np.isfinite(mx) and mx < 100 * TOL_MFMA   # single pass: reported, not bound
+        assert mx <= TOL_MFMA
 
 
 @pytest.mark.parametrize("form", ["basis", "regrouped"])
@@ -190,7 +187,7 @@ def test_edge_cases_lowp(svc, orc, name, precision, form):
                        frame=frame, pedestal=synth.SKY_LEVEL)
     mx, rms = err_stats(D, Dref)
     say("  max %.3e rms %.3e" % (mx, rms))
-    assert mx <= lowp_tol(precision)
+    assert mx <= TOL_MFMA
 
 
 @pytest.mark.parametrize("precision", LOWP)
@@ -201,7 +198,7 @@ def test_c0_full_frame_lowp(svc, c0_case, precision):
                        precision=precision, pedestal=synth.SKY_LEVEL)
     mx, rms = err_stats(D, Dref)
     say("  max %.3e rms %.3e" % (mx, rms))
-    assert mx <= lowp_tol(precision)
+    assert mx <= TOL_MFMA
 
 
 def test_lowp_rejects_half_width_above_15(svc):
@@ -228,4 +225,36 @@ def test_full_size_sampled_lowp(svc, orc, precision):
     Dref = orc.convolve_at(R, wl.half_width, B, wl.spatial_degree, a, xs, ys) - I[ys, xs]
     mx, rms = err_stats(D[ys, xs], Dref)
     say("  max %.3e rms %.3e" % (mx, rms))
-    assert mx <= lowp_tol(precision)
+    assert mx <= TOL_MFMA
+
+
+# ------------------------------- precisions that miss the 1e-2 sigma bound ----
+# fp16x2 keeps the taps in one fp16 part (11-bit taps) and bf16 / fp16 keep
+# both operands in one part: at the chip's brightest star their error exceeds
+# the matrix-core bound (measured 1.1e-2 to 3.5e-2 sigma for fp16x2, 4e-2 to
+# 0.5 sigma for the single-part forms).  They stay available with that error
+# stated; each case is held to the bound and is an expected failure.
+def _miss(form, precision, measured):
+    return pytest.param(form, precision, id="%s-%s" % (form, precision),
+                        marks=pytest.mark.xfail(strict=True, reason="%s/%s misses 1e-2 sigma at the "
+                                                "brightest star (measured %s sigma)"
+                                                % (form, precision, measured)))
+
+
+OUTSIDE_BOUND = [_miss("basis", "fp16x2", "1.1e-2"), _miss("regrouped", "fp16x2", "1.2e-2"),
+                 _miss("separable", "fp16x2", "3.5e-2"), _miss("basis", "bf16", "0.29"),
+                 _miss("basis", "fp16", "4.4e-2"), _miss("regrouped", "bf16", "0.49"),
+                 _miss("regrouped", "fp16", "4.3e-2")]
+
+
+@pytest.mark.parametrize("form,precision", OUTSIDE_BOUND)
+def test_precisions_outside_bound(svc, orc, form, precision):
+    wl, crops = c2_crops(orc)
+    Rc, Ic, a, frame, Dref = crops[1]   # the brightest star
+    say("outside-bound precision at the brightest star", form, precision)
+    D = run_difference(svc, Rc, Ic, a, wl.half_width, wl.sigmas, wl.degrees, wl.spatial_degree,
+                       precision=precision, form=form, frame=frame, pedestal=synth.SKY_LEVEL)
+    mx, rms = err_stats(D, Dref)
+    say("  max %.3e rms %.3e (%.2e sigma)" % (mx, rms, mx / np.sqrt(1000)))
+    assert np.all(np.isfinite(D))
+    assert mx <= TOL_MFMA

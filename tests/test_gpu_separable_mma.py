@@ -1,15 +1,14 @@
 """GPU parity of the separable form on the matrix cores (the split 16-bit
 precisions): the row and column passes of the Gaussian factors as banded
 Toeplitz products, against the FP64 oracle's direct two-dimensional
-convolution, at the matrix-core forms' bounds (1e-2 sigma_sky; fp16x2 at its
-measured level)."""
+convolution, at the matrix-core forms' bound of 1e-2 sigma_sky."""
 
 import numpy as np
 import pytest
 
 import synth
 from tests.helpers import TOL_MFMA, say, err_stats, sample_pixels, to_dev, to_host
-from tests.test_gpu_forward import EDGE_CASES, _edge_inputs, run_difference, lowp_tol, LOWP
+from tests.test_gpu_forward import EDGE_CASES, _edge_inputs, run_difference, LOWP
 from tests.test_gpu_separable import FOLD_CASES
 
 pytestmark = pytest.mark.gpu
@@ -30,7 +29,7 @@ def test_c0_full_frame(svc, orc, precision, pedestal):
                        precision=precision, form="separable", pedestal=pedestal)
     mx, rms = err_stats(D, Dref)
     say("  max %.3e rms %.3e (%.2e sigma)" % (mx, rms, mx / np.sqrt(1000)))
-    assert mx <= lowp_tol(precision)
+    assert mx <= TOL_MFMA
 
 
 @pytest.mark.parametrize("precision", LOWP)
@@ -53,7 +52,7 @@ def test_c2_crops(svc, orc, precision):
                            precision=precision, form="separable", frame=frame, pedestal=synth.SKY_LEVEL)
         mx, rms = err_stats(D, Dref)
         say("  max %.3e rms %.3e (%.2e sigma)" % (mx, rms, mx / np.sqrt(1000)))
-        assert mx <= lowp_tol(precision)
+        assert mx <= TOL_MFMA
 
 
 @pytest.mark.parametrize("precision", ["fp16x3", "bf16x3"])
