@@ -77,7 +77,12 @@ enum svconv_precision {
  * D = sum_n c_n T_n - I.  REGROUPED: Kt_m = sum_n a[n][m] B_n (built on the
  * device per call), then D = sum_m P_m (Kt_m (x) R) - I, which needs M
  * instead of N filters because P_m depends only on the output pixel. */
-enum svconv_form { SVCONV_FORM_BASIS = 0, SVCONV_FORM_REGROUPED = 1, SVCONV_FORM_SEPARABLE = 2 };
+enum svconv_form {
+    SVCONV_FORM_BASIS = 0,
+    SVCONV_FORM_REGROUPED = 1,
+    SVCONV_FORM_SEPARABLE = 2,
+    SVCONV_FORM_SEPARABLE_REGROUPED = 3
+};
 /* SEPARABLE (Gaussian bases, 1 <= half_width <= 15): each Gaussian basis is a
  * product f_i(u) f_j(v) of one-dimensional factors (the L1 norm of the
  * product is the product of the norms), so T_n = f_j (x)_y (f_i (x)_x R): a
@@ -102,6 +107,18 @@ enum svconv_form { SVCONV_FORM_BASIS = 0, SVCONV_FORM_REGROUPED = 1, SVCONV_FORM
  * fit in LDS).  The adjoints in a sum with atomics, so repeated calls agree to
  * float64 rounding rather than bit for bit.  EUNSUPPORTED for delta-basis
  * plans. */
+
+/* SEPARABLE_REGROUPED (Gaussian bases, 1 <= half_width <= 12, spatial
+ * degree <= 2, precision SVCONV_FP16X3, SVCONV_BF16X3 or SVCONV_FP16X2; other
+ * precisions return EUNSUPPORTED): the coefficients are folded into per-call
+ * column filters, sum_n c_n T_n = sum_m P_m Z_m with
+ * Z_m = sum_r g_{r,m} (x)_y (f_r (x)_x R) and g_{r,m} = sum_j a[n(r,j)][m] f_j
+ * over the column factors j of row factor r's family (exact, since P_m
+ * depends only on the output pixel).  One row pass per row factor and one
+ * column pass per row factor and spatial term, both as Toeplitz products of
+ * hi/lo parts on the matrix cores with float32 accumulation; no per-basis
+ * work outside the matrix cores.  svconv_backward and the fit entry points
+ * take the same paths as in the SEPARABLE form. */
 
 /*
  * Create a plan for images of height x width with a (2 half_width + 1)^2

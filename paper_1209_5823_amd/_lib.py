@@ -12,11 +12,12 @@ LIB_PATH = os.path.join(_HERE, "libsvconv.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ENOTSPD = 0, -1, -2, -3, -4, -5
 FP32, BF16, FP16, BF16X3, FP16X2, FP16X3 = 0, 1, 2, 3, 4, 5
-FORM_BASIS, FORM_REGROUPED, FORM_SEPARABLE = 0, 1, 2
+FORM_BASIS, FORM_REGROUPED, FORM_SEPARABLE, FORM_SEPARABLE_REGROUPED = 0, 1, 2, 3
 
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16, "bf16x3": BF16X3,
               "fp16x2": FP16X2, "fp16x3": FP16X3}
-FORMS = {"basis": FORM_BASIS, "regrouped": FORM_REGROUPED, "separable": FORM_SEPARABLE}
+FORMS = {"basis": FORM_BASIS, "regrouped": FORM_REGROUPED, "separable": FORM_SEPARABLE,
+         "separable_regrouped": FORM_SEPARABLE_REGROUPED}
 
 _vp = ctypes.c_void_p
 _i = ctypes.c_int

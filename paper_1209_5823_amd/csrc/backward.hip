@@ -193,7 +193,7 @@ __global__ void adjoint_a_final(const double* __restrict__ F64, const double* __
 int launch_adjoint_a(svconv_plan* p, const float* R, const float* gD, double* ga) {
     // a plan in the separable form takes the adjoint through the same factors
     // (when its per-round moments fit in LDS; otherwise the product below)
-    if (p->form == SVCONV_FORM_SEPARABLE && sep_adjoint_supported(p))
+    if (sep_form(p) && sep_adjoint_supported(p))
         return launch_adjoint_a_sep(p, R, gD, ga);
     const AdjointQGeometry g = aq_geometry(p->H, p->W, p->k, p->M);
     if (!p->dQpart) return fail(SVCONV_ENOMEM, "adjoint scratch missing");

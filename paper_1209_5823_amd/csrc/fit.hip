@@ -296,7 +296,7 @@ int launch_normal_matrix(svconv_plan* p, const float* R, const unsigned char* ma
         const int rows = (y0 + band <= p->H) ? band : p->H - y0;
         c.y_begin = y0;
         c.n_rows = rows;
-        if (p->form == SVCONV_FORM_SEPARABLE) {
+        if (sep_form(p)) {
             // basis responses through the separable factors
             SepArgs sa{};
             sa.X = R;

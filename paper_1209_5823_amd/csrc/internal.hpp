@@ -94,6 +94,41 @@ struct SepArgs {
     double* mom;                // adjoint in a on the matrix cores: [kSepMomCopies][N + 1][M] sums
 };
 
+// Regrouped separable form (separable_z.hip): the coefficients folded into
+// per-call column filters g_{r,m} = sum_j a[n(r,j)][m] f_j, one row pass per
+// row factor r and one column pass per (r, m) on the matrix cores.
+constexpr int kSepZMaxHalfWidth = 12;
+struct SepZArgs {
+    const float* X;             // [H][W]
+    const float* I;             // nullable
+    float* out;                 // [H][W]
+    int H, W, h;
+    float ped;
+    int R;                      // row factors of all families
+    int M;                      // spatial terms (<= 6)
+    double sx, ox, sy, oy;
+    int tiles_x, n_tiles;
+    int y_begin, n_rows;
+    const int* rinfo;           // [2 R]: family, factor index
+    const uint16_t* rtab;       // row-pass tap fragments of the precision
+    const uint16_t* ztab;       // [R][3] per-call column-pass fragments
+    const float* zinv;          // [6] 1 / (tap scale x data scale) per spatial term
+    const double* gam;          // [kSepCoefPad] sum_n a[n][m] beta_n, zero-padded
+};
+
+// Regrouped contraction of small kernels on the vector units (direct.hip).
+constexpr int kDirectMaxHalfWidth = 4;
+struct DirectArgs {
+    const float* X;             // [H][W]
+    const float* I;             // nullable
+    float* out;                 // [H][W]
+    int H, W, h, d_s, M;
+    float ped;
+    const float* taps;          // Dirac delta basis: a [k^2][M]; otherwise Kt [M][k][k] (correlation order)
+    double sx, ox, sy, oy;
+    int tiles_x;
+};
+
 }  // namespace svc
 
 struct svconv_plan {
@@ -117,6 +152,12 @@ struct svconv_plan {
                                         // the coefficients again in float32 (same layout)
     uint16_t* dSepFrag = nullptr;       // matrix-core Toeplitz fragments of the factors (fp16, bf16)
     double* dSepMom = nullptr;          // moment sums of the matrix-core adjoint in a
+    int sepR = 0;                       // row factors of all families
+    int* dSepRinfo = nullptr;           // [2 sepR] family, factor index of each row factor
+    uint16_t* dSepZRow = nullptr;       // regrouped separable form: row-pass fragments (fp16, bf16)
+    uint16_t* dSepZTab = nullptr;       // per-call column-pass fragments
+    float* dSepZInv = nullptr;          // [8] per-call inverse scales
+    double* dSepZGam = nullptr;         // [kSepCoefPad] per-call pedestal sums
 
     // device tables (basis form, fixed per plan)
     float* dF32 = nullptr;              // [N][k][k] correlation-oriented basis, float32
@@ -182,6 +223,26 @@ int launch_adjoint_a_sep_mma(SepArgs a, const uint16_t* frag, int precision, con
 int launch_adjoint_a_sep(svconv_plan* p, const float* R, const float* G, double* ga);
 bool sep_adjoint_supported(const svconv_plan* p);
 int launch_adjoint_r_sep(svconv_plan* p, const float* a32, const float* G, float* gR);
+
+// separable_z.hip
+size_t sepz_rtab_entries(int R);    // both precisions
+size_t sepz_ztab_entries(int R);
+// only: -1 builds both precisions (fp16 then bf16), 0 only fp16, 1 only bf16
+int build_sepz_rtab(const double* f1d, const int* rinfo, int R, int h, uint16_t* rtab, hipStream_t s,
+                    int only = -1);
+int launch_sepz_prep(const SepZArgs& z, const float* a, const double* f1d, const int* fam, const double* beta, int N,
+                     bool fp16, hipStream_t s);
+int launch_contract_sepz(SepZArgs a, int precision, hipStream_t s);
+
+// direct.hip
+bool direct_supported(int h, int d_s);
+int launch_contract_direct(DirectArgs a, bool dfb, hipStream_t s);
+
+// Both separable forms go through the one-dimensional factors in the adjoints
+// and the fit.
+inline bool sep_form(const svconv_plan* p) {
+    return p->form == SVCONV_FORM_SEPARABLE || p->form == SVCONV_FORM_SEPARABLE_REGROUPED;
+}
 
 // plan.hip
 int run_forward(svconv_plan* p, const float* R, const float* I, const float* a, float* out);

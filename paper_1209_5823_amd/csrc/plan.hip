@@ -71,7 +71,8 @@ static int dalloc(T** p, size_t count, const char* what) {
 }
 
 static void free_plan(svconv_plan* p) {
-    void* ptrs[] = {p->dSep1d, p->dSepFam, p->dSepCoef, p->dSepFrag, p->dSepMom,
+    void* ptrs[] = {p->dSep1d, p->dSepFam, p->dSepCoef, p->dSepFrag, p->dSepMom, p->dSepRinfo,
+                    p->dSepZRow, p->dSepZTab, p->dSepZInv, p->dSepZGam,
                     p->dF32,   p->dF64,   p->dBeta,   p->dFragF32, p->dFragLoB, p->dFragLoH,
                     p->dScaleB, p->dScaleH, p->dFt32, p->dBetaT, p->dFragT32, p->dFragTB,  p->dFragTH,
                     p->dScaleT, p->dQpart, p->dQ,    p->dGrad,    p->dVec,     p->dStatus,
@@ -205,6 +206,24 @@ static int finish_plan(svconv_plan* p, svconv_plan** out) {
             if (!st) st = build_sep_mma_fragments(p->dSep1d, G, h, p->dSepFrag, nullptr);
             if (!st) st = dalloc(&p->dSepMom, (size_t)kSepMomCopies * (p->N + 1) * p->M, "separable moments");
         }
+        if (!st && h <= kSepZMaxHalfWidth && p->d_s <= 2) {
+            // the regrouped separable form: row factors of all families in order
+            std::vector<int> rinfo;
+            for (int g = 0; g < G; ++g)
+                for (int i = 0; i <= p->degrees[g]; ++i) {
+                    rinfo.push_back(g);
+                    rinfo.push_back(i);
+                }
+            p->sepR = (int)(rinfo.size() / 2);
+            st = dalloc(&p->dSepRinfo, rinfo.size(), "row factors");
+            if (!st) st = hip_status(hipMemcpy(p->dSepRinfo, rinfo.data(), rinfo.size() * 4, hipMemcpyHostToDevice),
+                                     "upload");
+            if (!st) st = dalloc(&p->dSepZRow, sepz_rtab_entries(p->sepR), "row-pass fragments");
+            if (!st) st = dalloc(&p->dSepZTab, sepz_ztab_entries(p->sepR), "column-pass fragments");
+            if (!st) st = dalloc(&p->dSepZInv, (size_t)8, "column-pass scales");
+            if (!st) st = dalloc(&p->dSepZGam, (size_t)kSepCoefPad, "pedestal sums");
+            if (!st) st = build_sepz_rtab(p->dSep1d, p->dSepRinfo, p->sepR, h, p->dSepZRow, nullptr);
+        }
     }
     if (!st && p->N <= kMaxFilters) {
         st = build_f32_fragments(p->dF32, p->N, k, p->dFragF32, nullptr);
@@ -236,6 +255,35 @@ int run_forward(svconv_plan* p, const float* R, const float* I, const float* a, 
     c.n_rows = p->H;
     coords(p, c);
     const bool lowp = is_lowp(p->precision);
+    if (p->form == SVCONV_FORM_SEPARABLE_REGROUPED) {
+        const bool split = p->precision == SVCONV_FP16X3 || p->precision == SVCONV_BF16X3 ||
+                           p->precision == SVCONV_FP16X2;
+        if (!split) return fail(SVCONV_EUNSUPPORTED, "regrouped separable form needs a split 16-bit precision");
+        if (!p->dSepZRow) return fail(SVCONV_EUNSUPPORTED, "regrouped separable form needs 1 <= half-width <= 12 "
+                                                          "and spatial degree <= 2");
+        SepZArgs z{};
+        z.X = R;
+        z.I = I;
+        z.out = out;
+        z.H = p->H;
+        z.W = p->W;
+        z.h = p->h;
+        z.ped = p->pedestal;
+        z.R = p->sepR;
+        z.M = p->M;
+        z.sx = c.sx; z.ox = c.ox; z.sy = c.sy; z.oy = c.oy;
+        z.y_begin = 0;
+        z.n_rows = p->H;
+        z.rinfo = p->dSepRinfo;
+        const bool h16 = is_fp16(p->precision);
+        z.rtab = p->dSepZRow + (h16 ? 0 : sepz_rtab_entries(p->sepR) / 2);
+        z.ztab = p->dSepZTab;
+        z.zinv = p->dSepZInv;
+        z.gam = p->dSepZGam;
+        int st = launch_sepz_prep(z, a, p->dSep1d, p->dSepFam, p->dBeta, p->N, h16, p->stream);
+        if (st) return st;
+        return launch_contract_sepz(z, p->precision, p->stream);
+    }
     if (p->form == SVCONV_FORM_SEPARABLE) {
         SepArgs sa{};
         sa.X = R;
@@ -284,7 +332,29 @@ int run_forward(svconv_plan* p, const float* R, const float* I, const float* a, 
         return launch_contract_lowp(c, is_fp16(p->precision) ? p->dFragLoH : p->dFragLoB, nb,
                                     p->precision, p->stream);
     }
-    // regrouped: Kt_m built on the device for this call
+    // regrouped: Kt_m built on the device for this call (the delta basis' Kt_m
+    // is a itself); small kernels in float32 on the vector units
+    if (!lowp && direct_supported(p->h, p->d_s)) {
+        DirectArgs d{};
+        d.X = R;
+        d.I = I;
+        d.out = out;
+        d.H = p->H;
+        d.W = p->W;
+        d.h = p->h;
+        d.d_s = p->d_s;
+        d.M = p->M;
+        d.ped = p->pedestal;
+        d.sx = c.sx; d.ox = c.ox; d.sy = c.sy; d.oy = c.oy;
+        if (p->dfb) {
+            d.taps = a;
+            return launch_contract_direct(d, true, p->stream);
+        }
+        int st = regroup_filters(p->dF64, p->dBeta, a, p->N, p->M, p->k, p->dFt32, p->dBetaT, p->stream);
+        if (st) return st;
+        d.taps = p->dFt32;
+        return launch_contract_direct(d, false, p->stream);
+    }
     if (p->M > 32) return fail(SVCONV_EUNSUPPORTED, "regrouped form needs M <= 32");
     int st = regroup_filters(p->dF64, p->dBeta, a, p->N, p->M, p->k, p->dFt32, p->dBetaT, p->stream);
     if (st) return st;
@@ -431,8 +501,12 @@ int svconv_plan_set_precision(svconv_plan* p, int precision) {
 
 int svconv_plan_set_form(svconv_plan* p, int form) {
     if (!p) return fail(SVCONV_EINVAL, "plan is NULL");
-    if (form != SVCONV_FORM_BASIS && form != SVCONV_FORM_REGROUPED && form != SVCONV_FORM_SEPARABLE)
+    if (form != SVCONV_FORM_BASIS && form != SVCONV_FORM_REGROUPED && form != SVCONV_FORM_SEPARABLE &&
+        form != SVCONV_FORM_SEPARABLE_REGROUPED)
         return fail(SVCONV_EINVAL, "unknown form");
+    if (form == SVCONV_FORM_SEPARABLE_REGROUPED && !p->dSepZRow)
+        return fail(SVCONV_EUNSUPPORTED, "regrouped separable form needs Gaussian bases, 1 <= half-width <= 12 "
+                                         "and spatial degree <= 2");
     if (form == SVCONV_FORM_SEPARABLE && (!p->dSep1d || p->h > 15))
         return fail(SVCONV_EUNSUPPORTED, "separable form needs Gaussian bases and 1 <= half-width <= 15");
     if (form == SVCONV_FORM_BASIS && p->N > kMaxFilters)
@@ -484,7 +558,7 @@ int svconv_difference(svconv_plan* p, const float* R, const float* I, const floa
 // matrix-core passes with moment sums in place of the epilogue; otherwise the
 // float64 separable kernel or the dense product.
 static int run_adjoint_a(svconv_plan* p, const float* R, const float* gD, double* ga) {
-    if (p->form == SVCONV_FORM_SEPARABLE && (p->precision == SVCONV_FP16X3 || p->precision == SVCONV_BF16X3) &&
+    if (sep_form(p) && (p->precision == SVCONV_FP16X3 || p->precision == SVCONV_BF16X3) &&
         p->dSepFrag && p->dSepMom) {
         ContractArgs c{};
         coords(p, c);
@@ -516,7 +590,7 @@ int svconv_backward(svconv_plan* p, const float* R, const float* a, const float*
         return fail(SVCONV_EINVAL, "gR aliases R or gD");
     if (p->M > 32) return fail(SVCONV_EUNSUPPORTED, "adjoint in R needs M <= 32");
     int st = SVCONV_OK;
-    if (gR && p->form == SVCONV_FORM_SEPARABLE &&
+    if (gR && sep_form(p) &&
         (p->precision == SVCONV_FP16X3 || p->precision == SVCONV_BF16X3) && p->dSepFrag) {
         // through the separable factors on the matrix cores (bf16x3 for both split
         // precisions: bf16 keeps the float32 range of c_n gD)
@@ -540,7 +614,7 @@ int svconv_backward(svconv_plan* p, const float* R, const float* a, const float*
         sa.coefpf = reinterpret_cast<const float*>(p->dSepCoef + (size_t)(p->N + 1) * kSepCoefPad);
         st = launch_adjoint_r_sep_mma(sa, p->dSepFrag, p->stream);
         if (st) return st;
-    } else if (gR && p->form == SVCONV_FORM_SEPARABLE) {
+    } else if (gR && sep_form(p)) {
         // through the separable factors (E_n = c_n gD correlated with B_n)
         st = launch_adjoint_r_sep(p, a, gD, gR);
         if (st) return st;

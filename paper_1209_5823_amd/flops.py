@@ -89,3 +89,26 @@ def separable_mma_executed_flops_per_pixel(degrees, passes, tile=64, row_pass_ro
     row = n_factors * window * 2 * passes * row_pass_rows / tile
     col = N * window * 2 * passes
     return int(round(row + col))
+
+
+def separable_regrouped_flops_per_pixel(degrees, M, k):
+    """FLOP per pixel of the regrouped separable form taken tap by tap: a row
+    pass per row factor (sum_g (d_g + 1) of them), a column pass per row
+    factor and spatial term with the per-call filters
+    g_{r,m} = sum_j a[n(r,j)][m] f_j, then sum_m P_m Z_m and the subtraction."""
+    n_factors = sum(d + 1 for d in degrees)
+    return 2 * n_factors * k + 2 * n_factors * M * k + 2 * M + 1
+
+
+def separable_regrouped_executed_flops_per_pixel(degrees, M, passes, tile_rows=64, row_blocks=6):
+    """Matrix-core FLOP issued per output pixel by the regrouped separable
+    kernel: per 16-column strip of `tile_rows` rows, the row pass takes
+    `row_blocks` 16-row blocks x 2 eight-column groups per pair of row factors
+    and the column pass 8 output blocks of 8 rows per row factor and pair of
+    spatial terms, each product of 16 x 16 x 32 (16384 FLOP) issued `passes`
+    times."""
+    n_factors = sum(d + 1 for d in degrees)
+    pairs = (n_factors + 1) // 2
+    mpairs = (M + 1) // 2
+    per_strip = (pairs * row_blocks * 2 + n_factors * mpairs * (tile_rows // 8)) * passes * 16384
+    return int(round(per_strip / (16 * tile_rows)))
