@@ -39,11 +39,13 @@
 // by a power of two (largest |tap| in [1, 2)), undone in the epilogue; the
 // pedestal restore s sum_m gamma_m P_m and the subtraction of I in float64.
 //
-// Workgroup: 4 waves; output tile 64 x 64; wave w owns the 16-column strip
+// Workgroup: 4 waves; output tile 64 x 48; wave w owns the 16-column strip
 // w and every row of the tile.  LDS holds the staged tile (hi / lo rows
-// [96][88]) and, per wave, the second factor's row responses while the
+// [80][88]) and, per wave, the second factor's row responses while the
 // first one's column passes run (written and read by the same lanes, so no
-// barrier); the one barrier is the end of staging.
+// barrier).  Workgroups are persistent, two per compute unit: the loads of
+// the next tile are issued before the current tile's passes and staged after
+// them, so the only barriers are the ends of staging.
 #include "internal.hpp"
 #include "sep_fold.hpp"
 
@@ -56,8 +58,14 @@ typedef __bf16 sz_b8 __attribute__((ext_vector_type(8)));
 constexpr int SZ_NW = 4;                  // waves per workgroup (16-column strips)
 constexpr int SZ_NT = 64 * SZ_NW;
 constexpr int SZ_TW = 16 * SZ_NW;         // tile width
-constexpr int SZ_TH = 64;                 // tile height
-constexpr int SZ_RB = 6;                  // 16-row blocks of row responses (96 >= 64 + 2h)
+constexpr int SZ_OB = 6;                  // 8-row output blocks of a strip (even)
+constexpr int SZ_MINW = 2;                // waves per SIMD the registers allow
+constexpr int SZ_RG = 2;                  // row blocks whose row-pass products are issued together
+// the next tile's loads in flight during the current tile's passes (costs the
+// registers of the loaded samples)
+constexpr bool SZ_PREFETCH = true;
+constexpr int SZ_TH = 8 * SZ_OB;          // tile height
+constexpr int SZ_RB = SZ_OB / 2 + 2;      // 16-row blocks of row responses (16 SZ_RB >= SZ_TH + 2h for h <= 12)
 constexpr int SZ_XR = 16 * SZ_RB;         // staged rows
 constexpr int SZ_XC = SZ_TW + 24;         // staged columns the windows reach (88)
 constexpr int SZ_P = SZ_XC;               // pitch in 16-bit elements: 11 x 16 B (odd)
@@ -305,18 +313,9 @@ __device__ __forceinline__ uint32_t sz_sel_low(uint32_t lo, uint32_t hi) {
 // rows 16 b + 8.., phase 1).  Uh / Ul: the lane's row responses, two packed
 // registers per 16-row block; zt: the factor's column-pass fragments.
 template <bool FP16, int NT, int MP>
-__device__ __forceinline__ void sz_colpass(sz_f4 (&Z)[MP][8], const uint32_t (&Uh)[2 * SZ_RB],
+__device__ __forceinline__ void sz_colpass(sz_f4 (&Z)[MP][SZ_OB], const uint32_t (&Uh)[2 * SZ_RB],
                                            const uint32_t (&Ul)[2 * SZ_RB], const uint16_t* __restrict__ zt,
                                            int lane) {
-    // phase-1 windows: lane groups 0, 1 take blocks b + 1, b + 2, groups 2, 3 blocks b, b + 1
-    uint4 w1h[4], w1l[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        w1h[b] = make_uint4(sz_sel_low(Uh[2 * b + 2], Uh[2 * b]), sz_sel_low(Uh[2 * b + 3], Uh[2 * b + 1]),
-                            sz_sel_low(Uh[2 * b + 4], Uh[2 * b + 2]), sz_sel_low(Uh[2 * b + 5], Uh[2 * b + 3]));
-        w1l[b] = make_uint4(sz_sel_low(Ul[2 * b + 2], Ul[2 * b]), sz_sel_low(Ul[2 * b + 3], Ul[2 * b + 1]),
-                            sz_sel_low(Ul[2 * b + 4], Ul[2 * b + 2]), sz_sel_low(Ul[2 * b + 5], Ul[2 * b + 3]));
-    }
 #pragma unroll
     for (int mp = 0; mp < MP; ++mp) {
         uint4 za[2][2];   // [phase][hi/lo]
@@ -326,238 +325,306 @@ __device__ __forceinline__ void sz_colpass(sz_f4 (&Z)[MP][8], const uint32_t (&U
             for (int hl = 0; hl < 2; ++hl)
                 za[ph][hl] = *reinterpret_cast<const uint4*>(zt + (size_t)mp * SZ_FRAG + ((ph * 2 + hl) * 64 + lane) * 8);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
+        for (int b = 0; b < SZ_OB / 2; ++b) {
+            // phase 0 window: blocks b, b + 1; phase 1 window: lane groups 0, 1
+            // take blocks b + 1, b + 2, groups 2, 3 blocks b, b + 1 (formed here
+            // rather than kept across the spatial terms, to save registers)
             const uint4 w0h = make_uint4(Uh[2 * b], Uh[2 * b + 1], Uh[2 * b + 2], Uh[2 * b + 3]);
+            const uint4 w0l = make_uint4(Ul[2 * b], Ul[2 * b + 1], Ul[2 * b + 2], Ul[2 * b + 3]);
+            const uint4 w1h = make_uint4(sz_sel_low(Uh[2 * b + 2], Uh[2 * b]), sz_sel_low(Uh[2 * b + 3], Uh[2 * b + 1]),
+                                         sz_sel_low(Uh[2 * b + 4], Uh[2 * b + 2]), sz_sel_low(Uh[2 * b + 5], Uh[2 * b + 3]));
+            const uint4 w1l = make_uint4(sz_sel_low(Ul[2 * b + 2], Ul[2 * b]), sz_sel_low(Ul[2 * b + 3], Ul[2 * b + 1]),
+                                         sz_sel_low(Ul[2 * b + 4], Ul[2 * b + 2]), sz_sel_low(Ul[2 * b + 5], Ul[2 * b + 3]));
             Z[mp][2 * b] = sz_mfma<FP16>(za[0][0], w0h, Z[mp][2 * b]);
-            Z[mp][2 * b + 1] = sz_mfma<FP16>(za[1][0], w1h[b], Z[mp][2 * b + 1]);
-        }
-        if (NT >= 2)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const uint4 w0l = make_uint4(Ul[2 * b], Ul[2 * b + 1], Ul[2 * b + 2], Ul[2 * b + 3]);
+            Z[mp][2 * b + 1] = sz_mfma<FP16>(za[1][0], w1h, Z[mp][2 * b + 1]);
+            if (NT >= 2) {
                 Z[mp][2 * b] = sz_mfma<FP16>(za[0][0], w0l, Z[mp][2 * b]);
-                Z[mp][2 * b + 1] = sz_mfma<FP16>(za[1][0], w1l[b], Z[mp][2 * b + 1]);
+                Z[mp][2 * b + 1] = sz_mfma<FP16>(za[1][0], w1l, Z[mp][2 * b + 1]);
             }
-        if (NT >= 3)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const uint4 w0h = make_uint4(Uh[2 * b], Uh[2 * b + 1], Uh[2 * b + 2], Uh[2 * b + 3]);
+            if (NT >= 3) {
                 Z[mp][2 * b] = sz_mfma<FP16>(za[0][1], w0h, Z[mp][2 * b]);
-                Z[mp][2 * b + 1] = sz_mfma<FP16>(za[1][1], w1h[b], Z[mp][2 * b + 1]);
+                Z[mp][2 * b + 1] = sz_mfma<FP16>(za[1][1], w1h, Z[mp][2 * b + 1]);
             }
+        }
     }
 }
 
+// Loads of one tile's staged samples into registers: the pairs of columns
+// (c, c + 1) of row r for q = tid + i NT.  R = 0 outside the image; entries
+// past the halo are not needed.
+template <int SITER>
+__device__ __forceinline__ void sz_load_tile(const SepZArgs& a, int t, int tid, float (&sv)[SITER][2]) {
+    const int h = a.h;
+    const int X0 = (t % a.tiles_x) * SZ_TW, Y0 = a.y_begin + (t / a.tiles_x) * SZ_TH;
+    const int RA = SZ_TH + 2 * h, CA = SZ_TW + 2 * h;
+#pragma unroll
+    for (int i = 0; i < SITER; ++i) {
+        const int q = tid + i * SZ_NT;
+        const int r = q / (SZ_XC / 2), c = 2 * (q - r * (SZ_XC / 2));
+        const int gy = Y0 - h + r, gx = X0 - h + c;
+        sv[i][0] = 0.f;
+        sv[i][1] = 0.f;
+        if (q < SZ_XR * (SZ_XC / 2) && r < RA && gy >= 0 && gy < a.H) {
+            const float* src = a.X + (size_t)gy * a.W;
+            if (c < CA && gx >= 0 && gx < a.W) sv[i][0] = src[gx];
+            if (c + 1 < CA && gx + 1 >= 0 && gx + 1 < a.W) sv[i][1] = src[gx + 1];
+        }
+    }
+}
+
+// The loaded samples as (R - s) xscale split into hi / lo rows of the staged
+// tile; 0 past the halo (zero taps meet it).
+template <bool FP16, int SITER>
+__device__ __forceinline__ void sz_store_tile(const SepZArgs& a, int tid, const float (&sv)[SITER][2],
+                                              uint16_t* xs) {
+    const float xscale = FP16 ? 0.25f : 1.f;
+    const int RA = SZ_TH + 2 * a.h, CA = SZ_TW + 2 * a.h;
+#pragma unroll
+    for (int i = 0; i < SITER; ++i) {
+        const int q = tid + i * SZ_NT;
+        if (q < SZ_XR * (SZ_XC / 2)) {
+            const int r = q / (SZ_XC / 2), c = 2 * (q - r * (SZ_XC / 2));
+            float v[2];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) v[e] = (r < RA && c + e < CA) ? (sv[i][e] - a.ped) * xscale : 0.f;
+            uint32_t hi2, lo2;
+            sz_split2<FP16>(v[0], v[1], hi2, lo2);
+            *reinterpret_cast<uint32_t*>(xs + r * SZ_P + c) = hi2;
+            *reinterpret_cast<uint32_t*>(xs + (SZ_XR + r) * SZ_P + c) = lo2;
+        }
+    }
+}
+
+// Persistent workgroups: workgroup b takes tiles b, b + G, b + 2G, ... (G =
+// the grid) in the XCD-aware order, and the loads of its next tile are in
+// flight while it computes the current one.
 template <bool FP16, int NT, int MP>
-__global__ __launch_bounds__(SZ_NT, 2) void contract_sepz_kernel(SepZArgs a) {
+__global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs a) {
     extern __shared__ uint4 sz_lds[];
     uint16_t* xs = reinterpret_cast<uint16_t*>(sz_lds);   // [2][SZ_XR][SZ_P]
+    constexpr int SITER = (SZ_XR * (SZ_XC / 2) + SZ_NT - 1) / SZ_NT;
 
-    const int h = a.h;
-    const float xscale = FP16 ? 0.25f : 1.f;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int g4 = lane >> 4, j16 = lane & 15;
-    const int t = sep_xcd_remap(blockIdx.x, a.n_tiles);
-    const int X0 = (t % a.tiles_x) * SZ_TW;
-    const int Y0 = a.y_begin + (t / a.tiles_x) * SZ_TH;
     const int y_end = min(a.H, a.y_begin + a.n_rows);
-    const int RA = SZ_TH + 2 * h, CA = SZ_TW + 2 * h;
-
-    // stage (R - s) xscale as hi / lo, two columns per thread; R = 0 outside the
-    // image (so R - s = -s there), 0 past the halo (zero taps meet it)
-    for (int q = tid; q < SZ_XR * (SZ_XC / 2); q += SZ_NT) {
-        const int r = q / (SZ_XC / 2), c = 2 * (q - r * (SZ_XC / 2));
-        float v[2];
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            v[e] = 0.f;
-            const int gy = Y0 - h + r, gx = X0 - h + c + e;
-            if (r < RA && c + e < CA) {
-                const float x = (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) ? a.X[(size_t)gy * a.W + gx] : 0.f;
-                v[e] = (x - a.ped) * xscale;
-            }
-        }
-        uint32_t hi2, lo2;
-        sz_split2<FP16>(v[0], v[1], hi2, lo2);
-        *reinterpret_cast<uint32_t*>(xs + r * SZ_P + c) = hi2;
-        *reinterpret_cast<uint32_t*>(xs + (SZ_XR + r) * SZ_P + c) = lo2;
-    }
-    __syncthreads();
-
-    sz_f4 Z[MP][8];
-#pragma unroll
-    for (int s = 0; s < MP; ++s)
-#pragma unroll
-        for (int b = 0; b < 8; ++b) Z[s][b] = sz_f4{0.f, 0.f, 0.f, 0.f};
-
+    const int G = gridDim.x;
+    // data offset of the second 8-column group's reduction entries in this lane
+    const int off1 = g4 == 0 ? 32 : 8 * g4;
     const uint16_t* xrow = xs + j16 * SZ_P + 16 * w;   // this lane's staged row in block 0, strip start
     // this wave's area for the second factor's row responses: [SZ_RB][64 lanes] uint4
     uint4* ubw = sz_lds + SZ_XLDS / 16 + (size_t)w * SZ_RB * 64 + lane;
     const int n_pairs = (a.R + 1) / 2;
-    for (int pp = 0; pp < n_pairs; ++pp) {
-        // the staged rows are re-read for every pair rather than held in registers
-        // across the loop (they would cost 48 registers per lane)
-        const uint16_t* xr = xrow;
-        asm volatile("" : "+v"(xr));
-        // ---- row pass: two row factors x two 8-column groups, 6 row blocks
-        uint4 tb[2][2];
-        {
-            const uint16_t* rt = a.rtab + (size_t)pp * SZ_FRAG;
+
+    float sv[SITER][2];
+    int it = blockIdx.x;
+    if (it < a.n_tiles) {
+        sz_load_tile(a, sep_xcd_remap(it, a.n_tiles), tid, sv);
+        sz_store_tile<FP16>(a, tid, sv, xs);
+    }
+    __syncthreads();
+    for (; it < a.n_tiles; it += G) {
+        const int t = sep_xcd_remap(it, a.n_tiles);
+        const int X0 = (t % a.tiles_x) * SZ_TW;
+        const int Y0 = a.y_begin + (t / a.tiles_x) * SZ_TH;
+        const bool more = it + G < a.n_tiles;
+        if (SZ_PREFETCH && more) sz_load_tile(a, sep_xcd_remap(it + G, a.n_tiles), tid, sv);
+
+        sz_f4 Z[MP][SZ_OB];
 #pragma unroll
-            for (int cg = 0; cg < 2; ++cg)
+        for (int s = 0; s < MP; ++s)
 #pragma unroll
-                for (int hl = 0; hl < 2; ++hl)
-                    tb[cg][hl] = *reinterpret_cast<const uint4*>(rt + ((cg * 2 + hl) * 64 + lane) * 8);
-        }
-        uint32_t UAh[2 * SZ_RB], UAl[2 * SZ_RB];
+            for (int b = 0; b < SZ_OB; ++b) Z[s][b] = sz_f4{0.f, 0.f, 0.f, 0.f};
+
+        for (int pp = 0; pp < n_pairs; ++pp) {
+            // the staged rows are re-read for every pair rather than held in
+            // registers across the loop (they would cost 48 registers per lane)
+            const uint16_t* xr = xrow;
+            asm volatile("" : "+v"(xr));
+            // ---- row pass: two row factors x two 8-column groups, 6 row blocks
+            uint4 tb[2][2];
+            {
+                const uint16_t* rt = a.rtab + (size_t)pp * SZ_FRAG;
 #pragma unroll
-        for (int r2 = 0; r2 < SZ_RB; r2 += 2) {
-            sz_f4 acc[2][2];   // [rb][cg]
-            uint4 dh[2], dl[2];
+                for (int cg = 0; cg < 2; ++cg)
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const uint16_t* rp = xr + (16 * (r2 + q)) * SZ_P;
-                dh[q] = *reinterpret_cast<const uint4*>(rp + 8 * g4);
-                dl[q] = *reinterpret_cast<const uint4*>(rp + SZ_XR * SZ_P + 8 * g4);
-#pragma unroll
-                for (int cg = 0; cg < 2; ++cg) acc[q][cg] = sz_f4{0.f, 0.f, 0.f, 0.f};
+                    for (int hl = 0; hl < 2; ++hl)
+                        tb[cg][hl] = *reinterpret_cast<const uint4*>(rt + ((cg * 2 + hl) * 64 + lane) * 8);
             }
-            // the two 8-column groups: the second reuses the data of lane groups
-            // 1..3 and loads samples 32..39 into lane group 0
+            uint32_t UAh[2 * SZ_RB], UAl[2 * SZ_RB];
 #pragma unroll
-            for (int cg = 0; cg < 2; ++cg) {
-                if (cg == 1 && g4 == 0) {
+            for (int r2 = 0; r2 < SZ_RB; r2 += SZ_RG) {
+                sz_f4 acc[SZ_RG][2];   // [rb][cg]
+                uint4 dh[SZ_RG][2], dl[SZ_RG][2];   // [rb][cg]
+                // the second 8-column group reuses the samples of lane groups 1..3 and
+                // reads samples 32..39 in lane group 0: one load per lane and group,
+                // from a per-lane address, so both groups' loads are in flight at once
 #pragma unroll
-                    for (int q = 0; q < 2; ++q) {
-                        const uint16_t* rp = xr + (16 * (r2 + q)) * SZ_P;
-                        dh[q] = *reinterpret_cast<const uint4*>(rp + 32);
-                        dl[q] = *reinterpret_cast<const uint4*>(rp + SZ_XR * SZ_P + 32);
-                    }
+                for (int q = 0; q < SZ_RG; ++q) {
+                    if (r2 + q >= SZ_RB) continue;
+                    const uint16_t* rp = xr + (16 * (r2 + q)) * SZ_P;
+                    dh[q][0] = *reinterpret_cast<const uint4*>(rp + 8 * g4);
+                    dl[q][0] = *reinterpret_cast<const uint4*>(rp + SZ_XR * SZ_P + 8 * g4);
+                    dh[q][1] = *reinterpret_cast<const uint4*>(rp + off1);
+                    dl[q][1] = *reinterpret_cast<const uint4*>(rp + SZ_XR * SZ_P + off1);
+#pragma unroll
+                    for (int cg = 0; cg < 2; ++cg) acc[q][cg] = sz_f4{0.f, 0.f, 0.f, 0.f};
                 }
 #pragma unroll
-                for (int q = 0; q < 2; ++q) acc[q][cg] = sz_mfma<FP16>(dh[q], tb[cg][0], acc[q][cg]);
+                for (int cg = 0; cg < 2; ++cg)
+#pragma unroll
+                    for (int q = 0; q < SZ_RG; ++q)
+                        if (r2 + q < SZ_RB) acc[q][cg] = sz_mfma<FP16>(dh[q][cg], tb[cg][0], acc[q][cg]);
                 if (NT >= 2)
 #pragma unroll
-                    for (int q = 0; q < 2; ++q) acc[q][cg] = sz_mfma<FP16>(dl[q], tb[cg][0], acc[q][cg]);
+                    for (int cg = 0; cg < 2; ++cg)
+#pragma unroll
+                        for (int q = 0; q < SZ_RG; ++q)
+                            if (r2 + q < SZ_RB) acc[q][cg] = sz_mfma<FP16>(dl[q][cg], tb[cg][0], acc[q][cg]);
                 if (NT >= 3)
 #pragma unroll
-                    for (int q = 0; q < 2; ++q) acc[q][cg] = sz_mfma<FP16>(dh[q], tb[cg][1], acc[q][cg]);
-            }
-            // split, then move the two factors into the 16-column layout: factor A
-            // holds lanes 0..7 of group 0 and (rotated) lanes 0..7 of group 1,
-            // factor B (rotated) lanes 8..15 of group 0 and lanes 8..15 of group 1;
-            // factor B waits in this wave's LDS area until its column pass
+                    for (int cg = 0; cg < 2; ++cg)
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int rb = r2 + q;
-                uint32_t c0h[2], c0l[2], c1h[2], c1l[2];
-                sz_split2<FP16>(acc[q][0][0], acc[q][0][1], c0h[0], c0l[0]);
-                sz_split2<FP16>(acc[q][0][2], acc[q][0][3], c0h[1], c0l[1]);
-                sz_split2<FP16>(acc[q][1][0], acc[q][1][1], c1h[0], c1l[0]);
-                sz_split2<FP16>(acc[q][1][2], acc[q][1][3], c1h[1], c1l[1]);
+                        for (int q = 0; q < SZ_RG; ++q)
+                            if (r2 + q < SZ_RB) acc[q][cg] = sz_mfma<FP16>(dh[q][cg], tb[cg][1], acc[q][cg]);
+                // split, then move the two factors into the 16-column layout: factor A
+                // holds lanes 0..7 of group 0 and (rotated) lanes 0..7 of group 1,
+                // factor B (rotated) lanes 8..15 of group 0 and lanes 8..15 of group 1;
+                // factor B waits in this wave's LDS area until its column pass
 #pragma unroll
-                for (int e = 0; e < 2; ++e) {
-                    UAh[2 * rb + e] = sz_ror8<0xc>(c0h[e], c1h[e]);
-                    UAl[2 * rb + e] = sz_ror8<0xc>(c0l[e], c1l[e]);
+                for (int q = 0; q < SZ_RG; ++q) {
+                    const int rb = r2 + q;
+                    if (rb >= SZ_RB) continue;
+                    uint32_t c0h[2], c0l[2], c1h[2], c1l[2];
+                    sz_split2<FP16>(acc[q][0][0], acc[q][0][1], c0h[0], c0l[0]);
+                    sz_split2<FP16>(acc[q][0][2], acc[q][0][3], c0h[1], c0l[1]);
+                    sz_split2<FP16>(acc[q][1][0], acc[q][1][1], c1h[0], c1l[0]);
+                    sz_split2<FP16>(acc[q][1][2], acc[q][1][3], c1h[1], c1l[1]);
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        UAh[2 * rb + e] = sz_ror8<0xc>(c0h[e], c1h[e]);
+                        UAl[2 * rb + e] = sz_ror8<0xc>(c0l[e], c1l[e]);
+                    }
+                    ubw[rb * 64] = make_uint4(sz_ror8<0x3>(c1h[0], c0h[0]), sz_ror8<0x3>(c1h[1], c0h[1]),
+                                              sz_ror8<0x3>(c1l[0], c0l[0]), sz_ror8<0x3>(c1l[1], c0l[1]));
                 }
-                ubw[rb * 64] = make_uint4(sz_ror8<0x3>(c1h[0], c0h[0]), sz_ror8<0x3>(c1h[1], c0h[1]),
-                                          sz_ror8<0x3>(c1l[0], c0l[0]), sz_ror8<0x3>(c1l[1], c0l[1]));
+            }
+
+            // ---- column passes: Z[s][ob] += g_{r, 2 mp + s} (x)_y U_r for both factors
+            sz_colpass<FP16, NT, MP>(Z, UAh, UAl, a.ztab + (size_t)(2 * pp) * 3 * SZ_FRAG, lane);
+            if (2 * pp + 1 < a.R) {
+                uint32_t UBh[2 * SZ_RB], UBl[2 * SZ_RB];
+#pragma unroll
+                for (int rb = 0; rb < SZ_RB; ++rb) {
+                    const uint4 v = ubw[rb * 64];
+                    UBh[2 * rb] = v.x;
+                    UBh[2 * rb + 1] = v.y;
+                    UBl[2 * rb] = v.z;
+                    UBl[2 * rb + 1] = v.w;
+                }
+                sz_colpass<FP16, NT, MP>(Z, UBh, UBl, a.ztab + (size_t)(2 * pp + 1) * 3 * SZ_FRAG, lane);
             }
         }
 
-        // ---- column passes: Z[s][ob] += g_{r, 2 mp + s} (x)_y U_r for both factors
-        sz_colpass<FP16, NT, MP>(Z, UAh, UAl, a.ztab + (size_t)(2 * pp) * 3 * SZ_FRAG, lane);
-        if (2 * pp + 1 < a.R) {
-            uint32_t UBh[2 * SZ_RB], UBl[2 * SZ_RB];
+        // ---- epilogue.  Lane (g4, j16) holds Z_m, m = 2 mp + g4 / 2, at rows
+        // 8 ob + 4 (g4 mod 2) + e of column j16 of its strip.
+        const int x = X0 + 16 * w + j16;
+        const double xh = a.sx * x + a.ox;
+        const float xf = (float)xh;
+        // per-lane weights of the spatial terms: P_m Z_m = (zinv_m xh^p) yh^q Z_m
+        float wq[MP][3];
 #pragma unroll
-            for (int rb = 0; rb < SZ_RB; ++rb) {
-                const uint4 v = ubw[rb * 64];
-                UBh[2 * rb] = v.x;
-                UBh[2 * rb + 1] = v.y;
-                UBl[2 * rb] = v.z;
-                UBl[2 * rb + 1] = v.w;
-            }
-            sz_colpass<FP16, NT, MP>(Z, UBh, UBl, a.ztab + (size_t)(2 * pp + 1) * 3 * SZ_FRAG, lane);
+        for (int mp = 0; mp < MP; ++mp) {
+            const int m = 2 * mp + (g4 >> 1);
+            // (p, q) of term m: total degree tt, q = m - tt (tt + 1) / 2, p = tt - q
+            const int tt = m >= 3 ? 2 : (m >= 1 ? 1 : 0);
+            const int q = m - tt * (tt + 1) / 2, p = tt - q;
+            const float c = (m < a.M) ? a.zinv[m] * (p == 0 ? 1.f : (p == 1 ? xf : xf * xf)) : 0.f;
+#pragma unroll
+            for (int qq = 0; qq < 3; ++qq) wq[mp][qq] = (q == qq) ? c : 0.f;
         }
-    }
-
-    // ---- epilogue.  Lane (g4, j16) holds Z_m, m = 2 mp + g4 / 2, at rows
-    // 8 ob + 4 (g4 mod 2) + e of column j16 of its strip.
-    const int x = X0 + 16 * w + j16;
-    const double xh = a.sx * x + a.ox;
-    const float xf = (float)xh;
-    // per-lane weights of the spatial terms: P_m Z_m = (zinv_m xh^p) yh^q Z_m
-    float wq[MP][3];
+        float part[SZ_OB][4];
 #pragma unroll
-    for (int mp = 0; mp < MP; ++mp) {
-        const int m = 2 * mp + (g4 >> 1);
-        // (p, q) of term m: total degree tt, q = m - tt (tt + 1) / 2, p = tt - q
-        const int tt = m >= 3 ? 2 : (m >= 1 ? 1 : 0);
-        const int q = m - tt * (tt + 1) / 2, p = tt - q;
-        const float c = (m < a.M) ? a.zinv[m] * (p == 0 ? 1.f : (p == 1 ? xf : xf * xf)) : 0.f;
-#pragma unroll
-        for (int qq = 0; qq < 3; ++qq) wq[mp][qq] = (q == qq) ? c : 0.f;
-    }
-    float part[8][4];
-#pragma unroll
-    for (int ob = 0; ob < 8; ++ob)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int y = Y0 + 8 * ob + 4 * (g4 & 1) + e;
-            const float yf = fmaf((float)a.sy, (float)y, (float)a.oy);
-            float v0 = 0.f, v1 = 0.f, v2 = 0.f;
-#pragma unroll
-            for (int mp = 0; mp < MP; ++mp) {
-                v0 = fmaf(wq[mp][0], Z[mp][ob][e], v0);
-                v1 = fmaf(wq[mp][1], Z[mp][ob][e], v1);
-                v2 = fmaf(wq[mp][2], Z[mp][ob][e], v2);
-            }
-            part[ob][e] = fmaf(fmaf(v2, yf, v1), yf, v0);
-        }
-    // lanes g4 and g4 ^ 2 hold the two halves of the same pixels: lane groups
-    // 0, 1 finish output blocks 0..3, groups 2, 3 blocks 4..7
-    const bool lowg = g4 < 2;
-    float fin[4][4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const float send = lowg ? part[q + 4][e] : part[q][e];
-            const float recv = __shfl_xor(send, 32);
-            fin[q][e] = (lowg ? part[q][e] : part[q + 4][e]) + recv;
-        }
-    if (x < a.W) {
-        // pedestal restore s sum_m gamma_m P_m (float64), then D = sum_m P_m Z_m - I
-        double xpow[3] = {1.0, xh, xh * xh};
-        double cy[3];
-        coef_in_x<2>(as_const(a.gam), xpow, cy);
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int ob = 0; ob < SZ_OB; ++ob)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int ob = q + (lowg ? 0 : 4);
                 const int y = Y0 + 8 * ob + 4 * (g4 & 1) + e;
-                if (y < y_end) {
-                    const double yh = a.sy * y + a.oy;
-                    const double pg = fma(fma(cy[2], yh, cy[1]), yh, cy[0]);
-                    const size_t idx = (size_t)y * a.W + x;
-                    const double iv = a.I ? (double)a.I[idx] : 0.0;
-                    a.out[idx] = (float)(fma((double)a.ped, pg, (double)fin[q][e]) - iv);
+                const float yf = fmaf((float)a.sy, (float)y, (float)a.oy);
+                float v0 = 0.f, v1 = 0.f, v2 = 0.f;
+#pragma unroll
+                for (int mp = 0; mp < MP; ++mp) {
+                    v0 = fmaf(wq[mp][0], Z[mp][ob][e], v0);
+                    v1 = fmaf(wq[mp][1], Z[mp][ob][e], v1);
+                    v2 = fmaf(wq[mp][2], Z[mp][ob][e], v2);
                 }
+                part[ob][e] = fmaf(fmaf(v2, yf, v1), yf, v0);
             }
+        // lanes g4 and g4 ^ 2 hold the two halves of the same pixels: lane groups
+        // 0, 1 finish the first half of the output blocks, groups 2, 3 the second
+        constexpr int HB = SZ_OB / 2;
+        const bool lowg = g4 < 2;
+        float fin[HB][4];
+#pragma unroll
+        for (int q = 0; q < HB; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float send = lowg ? part[q + HB][e] : part[q][e];
+                const float recv = __shfl_xor(send, 32);
+                fin[q][e] = (lowg ? part[q][e] : part[q + HB][e]) + recv;
+            }
+        if (x < a.W) {
+            // pedestal restore s sum_m gamma_m P_m (float64), then D = sum_m P_m Z_m - I
+            double xpow[3] = {1.0, xh, xh * xh};
+            double cy[3];
+            coef_in_x<2>(as_const(a.gam), xpow, cy);
+#pragma unroll
+            for (int q = 0; q < HB; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int ob = q + (lowg ? 0 : HB);
+                    const int y = Y0 + 8 * ob + 4 * (g4 & 1) + e;
+                    if (y < y_end) {
+                        const double yh = a.sy * y + a.oy;
+                        const double pg = fma(fma(cy[2], yh, cy[1]), yh, cy[0]);
+                        const size_t idx = (size_t)y * a.W + x;
+                        const double iv = a.I ? (double)a.I[idx] : 0.0;
+                        a.out[idx] = (float)(fma((double)a.ped, pg, (double)fin[q][e]) - iv);
+                    }
+                }
+        }
+
+        // every wave is done with the staged tile: stage the next one
+        if (!SZ_PREFETCH && more) sz_load_tile(a, sep_xcd_remap(it + G, a.n_tiles), tid, sv);
+        __syncthreads();
+        if (more) {
+            sz_store_tile<FP16>(a, tid, sv, xs);
+            __syncthreads();
+        }
     }
 }
 
 template <bool FP16, int NT>
-static int launch_sepz_p(const SepZArgs& a, hipStream_t s) {
+static int launch_sepz_p(const SepZArgs& a, int grid, hipStream_t s) {
     const int MP = (a.M + 1) / 2;
     if (MP <= 1)
-        hipLaunchKernelGGL((contract_sepz_kernel<FP16, NT, 1>), dim3(a.n_tiles), dim3(SZ_NT), SZ_LDS, s, a);
+        hipLaunchKernelGGL((contract_sepz_kernel<FP16, NT, 1>), dim3(grid), dim3(SZ_NT), SZ_LDS, s, a);
     else if (MP == 2)
-        hipLaunchKernelGGL((contract_sepz_kernel<FP16, NT, 2>), dim3(a.n_tiles), dim3(SZ_NT), SZ_LDS, s, a);
+        hipLaunchKernelGGL((contract_sepz_kernel<FP16, NT, 2>), dim3(grid), dim3(SZ_NT), SZ_LDS, s, a);
     else
-        hipLaunchKernelGGL((contract_sepz_kernel<FP16, NT, 3>), dim3(a.n_tiles), dim3(SZ_NT), SZ_LDS, s, a);
+        hipLaunchKernelGGL((contract_sepz_kernel<FP16, NT, 3>), dim3(grid), dim3(SZ_NT), SZ_LDS, s, a);
     return hip_status(hipGetLastError(), "contract_sepz_kernel");
+}
+
+// Compute units of the current device (cached per device).
+static int device_cus() {
+    static int cus[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cus[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cus[dev] = n;
+    }
+    return cus[dev];
 }
 
 int launch_contract_sepz(SepZArgs a, int precision, hipStream_t s) {
@@ -567,10 +634,14 @@ int launch_contract_sepz(SepZArgs a, int precision, hipStream_t s) {
     a.tiles_x = (a.W + SZ_TW - 1) / SZ_TW;
     a.n_tiles = a.tiles_x * ((a.n_rows + SZ_TH - 1) / SZ_TH);
     if (a.n_tiles == 0) return SVCONV_OK;
+    // persistent workgroups: SZ_MINW per compute unit (one 4-wave workgroup per
+    // wave slot of a SIMD the registers allow), each walking its share of the tiles
+    const int slots = SZ_MINW * device_cus();
+    const int grid = a.n_tiles < slots ? a.n_tiles : slots;
     switch (precision) {
-        case SVCONV_FP16X3: return launch_sepz_p<true, 3>(a, s);
-        case SVCONV_BF16X3: return launch_sepz_p<false, 3>(a, s);
-        case SVCONV_FP16X2: return launch_sepz_p<true, 2>(a, s);
+        case SVCONV_FP16X3: return launch_sepz_p<true, 3>(a, grid, s);
+        case SVCONV_BF16X3: return launch_sepz_p<false, 3>(a, grid, s);
+        case SVCONV_FP16X2: return launch_sepz_p<true, 2>(a, grid, s);
         default: return fail(SVCONV_EUNSUPPORTED, "regrouped separable form needs a split 16-bit precision");
     }
 }
