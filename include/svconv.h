@@ -230,6 +230,33 @@ int svconv_gn_step(svconv_plan* plan, const float* R, const float* I, const unsi
                    const double* L, double* a64, float* a32, float* D, double* host_stats);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one
+ * difference image D = (R (x) K) - I in the SEPARABLE_REGROUPED form without
+ * a plan.  The arguments are those of svconv_plan_create and
+ * svconv_difference together: image size, half-width, Gaussian families (HOST
+ * arrays sigmas[n_gauss], degrees[n_gauss]), spatial degree, precision
+ * (SVCONV_FP16X3, SVCONV_BF16X3 or SVCONV_FP16X2), pedestal, the device images
+ * R, I, D (float32 [height][width]), a (float32 [N][M]) and the stream
+ * (a hipStream_t; NULL = default).  Spatial terms are taken over the image
+ * itself (no crop frame).  The call allocates nothing: every table (the
+ * one-dimensional factors, the basis sums, the row- and column-pass
+ * fragments) is built on the device, on `stream`, in one static 512 KiB
+ * scratch array per GPU, which holds its contents until the process ends.
+ * Limits: 1 <= half_width <= 12, spatial_degree <= 2, n_gauss <= 8, every
+ * sigma > 0, degree <= 9, N <= 64 and sum_g (degree_g + 1) <= 32; beyond
+ * them EUNSUPPORTED, before any HIP call (as are the EINVAL checks).  Calls
+ * on one GPU share that GPU's scratch array: calls that overlap in time
+ * (from several threads, or on streams that run concurrently) race and must
+ * be serialised by the caller.  D may alias I but not R.  Asynchronous like
+ * svconv_difference.
+ */
+int svconv_difference_noalloc(int height, int width, int half_width, int n_gauss,
+                              const double* sigmas, const int* degrees, int spatial_degree,
+                              int precision, float pedestal, const float* R, const float* I,
+                              const float* a, float* D, void* stream);
+
+/*
  * Optimal Image Subtraction on isolated stars (Sec. 2: the least-squares
  * kernel fit takes isolated stars of the reference as its source).
  */

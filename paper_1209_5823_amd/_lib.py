@@ -55,6 +55,9 @@ SIGNATURES = {
     "svconv_pipeline_run": (_i, [_vp, _i, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                  ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
     "svconv_pipeline_destroy": (_i, [_vp]),
+    "svconv_difference_noalloc": (_i, [_i, _i, _i, _i, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(_i), _i, _i, ctypes.c_float, _vp, _vp, _vp, _vp,
+                                       _vp]),
     "svconv_strerror": (ctypes.c_char_p, [_i]),
     "svconv_last_error": (ctypes.c_char_p, []),
 }

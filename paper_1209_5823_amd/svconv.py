@@ -332,6 +332,33 @@ def difference(plan, R, I, a):
     return SVConvDifference.apply(plan, R, I, a)
 
 
+def difference_noalloc(R, I, a, half_width, sigmas, degrees, spatial_degree, precision="fp16x3",
+                       pedestal=0.0, out=None):
+    """D = (R (x) K(x,y)) - I without a plan and without any allocation in the
+    library (svconv_difference_noalloc): the regrouped separable form, every
+    table built on the device in the library's static scratch array, on
+    torch's current stream.  R, I, out: float32 [H][W]; a: float32 [N][M]."""
+    lib = _lib.load()
+    H, W = R.shape
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.float32, device=R.device)
+    if len(sigmas) != len(degrees):
+        raise ValueError("sigmas and degrees differ in length")
+    N = sum((int(d) + 1) * (int(d) + 2) // 2 for d in degrees)
+    M = (int(spatial_degree) + 1) * (int(spatial_degree) + 2) // 2
+    sig = (ctypes.c_double * len(sigmas))(*[float(x) for x in sigmas])
+    deg = (ctypes.c_int * len(degrees))(*[int(d) for d in degrees])
+    s = torch.cuda.current_stream().cuda_stream
+    check(lib.svconv_difference_noalloc(int(H), int(W), int(half_width), len(sigmas), sig, deg,
+                                        int(spatial_degree), PRECISIONS[precision], float(pedestal),
+                                        _dev_ptr(R, torch.float32, (H, W), "R"),
+                                        _dev_ptr(I, torch.float32, (H, W), "I"),
+                                        _dev_ptr(a, torch.float32, (N, M), "a"),
+                                        _dev_ptr(out, torch.float32, (H, W), "D"), ctypes.c_void_p(s)),
+          "svconv_difference_noalloc")
+    return out
+
+
 def _host_ptr(t, shape, name):
     """Address of a contiguous float32 CPU tensor or numpy array."""
     if isinstance(t, torch.Tensor):

@@ -135,3 +135,29 @@ def test_ois_entry_points_reject_before_any_device_call(lib):
     assert lib.svconv_plan_set_background(None, 1) == E
     assert lib.svconv_add_background(None, None, None) == E
     assert lib.svconv_pcg_fit(None, None, None, None, None, 1, None, None, None, None) == E
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(h=13), _lib.EUNSUPPORTED),
+    (dict(h=0), _lib.EUNSUPPORTED),
+    (dict(d_s=3), _lib.EUNSUPPORTED),
+    (dict(precision=0), _lib.EUNSUPPORTED),
+    (dict(degrees=(9, 9, 9, 9)), _lib.EUNSUPPORTED),     # 220 bases, 40 row factors
+    (dict(degrees=(6, 6, 6, 6, 6)), _lib.EUNSUPPORTED),  # 35 row factors > 32
+    (dict(sigmas=(0.0,), degrees=(0,)), _lib.EUNSUPPORTED),
+    (dict(H=0), _lib.EINVAL),
+    (dict(precision=9), _lib.EINVAL),
+    (dict(sigmas=(-1.0,), degrees=(1,)), _lib.EINVAL),
+])
+def test_noalloc_rejects_before_any_device_call(lib, kw, status):
+    H, W = kw.get("H", 16), 16
+    deg = kw.get("degrees", (1,))
+    sig = kw.get("sigmas", (1.5,) * len(deg))
+    s = (ctypes.c_double * len(sig))(*sig)
+    d = (ctypes.c_int * len(deg))(*deg)
+    dummy = ctypes.c_void_p(16)   # never dereferenced: validation fails first
+    rc = lib.svconv_difference_noalloc(H, W, kw.get("h", 3), len(sig), s, d, kw.get("d_s", 2),
+                                       kw.get("precision", 5), 0.0, dummy, dummy, dummy,
+                                       ctypes.c_void_p(32), None)
+    assert rc == status
+    assert lib.svconv_last_error().decode() != ""
