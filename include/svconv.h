@@ -206,6 +206,16 @@ int svconv_loss_grad(svconv_plan* plan, const float* D, const unsigned char* mas
 int svconv_normal_matrix(svconv_plan* plan, const float* R, const unsigned char* mask,
                          double* JtJ);
 
+/* Normal equations of the fit (OIS least squares, Sec. 2; D is linear in a
+ * by Eq. 2 - Eq. 3, D = J a - I with columns J_(n,m) = P_m T_n):
+ *   JtJ as svconv_normal_matrix, and rhs[(n,m)] = sum_{p in mask} P_m T_n I,
+ * both float64 device arrays ([NM][NM] and [NM], NM = (N + bg) M), from the
+ * same float32 basis-response planes in one pass over the image.  I: float32
+ * [H][W] device.  Needs N + bg + 1 <= 64 (SVCONV_EUNSUPPORTED otherwise).
+ * Allocates its band scratch on the first call, as svconv_normal_matrix. */
+int svconv_normal_equations(svconv_plan* plan, const float* R, const float* I,
+                            const unsigned char* mask, double* JtJ, double* rhs);
+
 /* In-place Cholesky factorisation A = L L^T of an n x n float64 device
  * matrix (lower triangle of A is overwritten with L; the strict upper
  * triangle is zeroed).  Synchronises the plan's stream; returns
@@ -228,6 +238,18 @@ int svconv_cholesky_solve(svconv_plan* plan, const double* L, const double* rhs,
  * synchronises the plan's stream. */
 int svconv_gn_step(svconv_plan* plan, const float* R, const float* I, const unsigned char* mask,
                    const double* L, double* a64, float* a32, float* D, double* host_stats);
+
+/* One Newton step of the least-squares fit on the normal equations from
+ * svconv_normal_equations: D and its loss at the current a (as
+ * svconv_gn_step), then g = JtJ a - rhs (= J^T D, float64), delta = (L L^T)^-1 g,
+ * a -= delta.  D is linear in a, so the first step reaches the solution of
+ * the normal equations and later steps are iterative refinement in float64,
+ * independent of the forward pass's precision.  A: JtJ (unfactored), L: its
+ * Cholesky factor, rhs: J^T I, all float64 device.  Other arguments and
+ * host_stats as in svconv_gn_step. */
+int svconv_ls_step(svconv_plan* plan, const float* R, const float* I, const unsigned char* mask,
+                   const double* A, const double* L, const double* rhs, double* a64, float* a32,
+                   float* D, double* host_stats);
 
 /*
  * For callers that cannot allocate device memory (code under HIP graph

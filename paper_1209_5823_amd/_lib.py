@@ -43,6 +43,8 @@ SIGNATURES = {
     "svconv_cholesky_factor": (_i, [_vp, _vp, _i]),
     "svconv_cholesky_solve": (_i, [_vp, _vp, _vp, _vp, _i]),
     "svconv_gn_step": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
+    "svconv_normal_equations": (_i, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "svconv_ls_step": (_i, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]),
     "svconv_stamp_mask": (_i, [_vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _i, _i,
                                _i, _vp, ctypes.POINTER(_i)]),
     "svconv_plan_set_background": (_i, [_vp, _i]),

@@ -229,17 +229,40 @@ __global__ void fill_ones_kernel(float* __restrict__ v, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) v[i] = 1.f;
 }
 
+__global__ void copy_plane_kernel(const float* __restrict__ src, float* __restrict__ dst, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
+// rhs[(n,m)] = S[mu(i_m, j_m)][n][q] = sum_{p in mask} P_m T_n I, where plane q
+// of the band held I (column q of the Gram sums, q >= n, so the entry is formed)
+__global__ void assemble_rhs(const double* __restrict__ S, int N, int M, int q, double* __restrict__ rhs) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= N * M) return;
+    const int n = idx / M, m = idx % M;
+    int t = 0;
+    while ((t + 1) * (t + 2) / 2 <= m) ++t;
+    const int j = m - t * (t + 1) / 2;
+    rhs[idx] = S[(size_t)(t * (t + 1) / 2 + j) * 4096 + n * 64 + q];
+}
+
 // With a background polynomial the fit has one more "basis" whose response
 // is the constant 1 (bg = sum_m b_m P_m * 1), so the same Gram sums give the
 // background rows and columns of the normal matrix: plane N of the band is
-// filled with ones.
-int launch_normal_matrix(svconv_plan* p, const float* R, const unsigned char* mask, double* JtJ) {
+// filled with ones.  With I and rhs given, one more plane holds I, and the
+// Gram sums of the basis planes with it are the right-hand side
+// rhs[(n,m)] = sum_p P_m T_n I of the normal equations.
+int launch_normal_matrix(svconv_plan* p, const float* R, const float* I, const unsigned char* mask,
+                         double* JtJ, double* rhs) {
     const int NF = p->N + p->bg;
-    if (NF > 64) return fail(SVCONV_EUNSUPPORTED, "normal matrix needs N (+1 with a background) <= 64");
+    const bool want_rhs = (I != nullptr && rhs != nullptr);
+    const int planes = NF + (want_rhs ? 1 : 0);
+    if (planes > 64)
+        return fail(SVCONV_EUNSUPPORTED,
+                    "normal equations need N (+1 with a background, +1 with the right-hand side) <= 64");
     const int n_mu = (2 * p->d_s + 1) * (2 * p->d_s + 2) / 2;
     const int n_a = 2 * p->d_s + 1;                       // powers of xh
     const int cpr = (p->W + NM_PIX_CHUNK - 1) / NM_PIX_CHUNK;   // segments per row
-    const size_t row_bytes = (size_t)NF * p->W * sizeof(float);
+    const size_t row_bytes = (size_t)planes * p->W * sizeof(float);
     int band = (int)(NM_BAND_BYTES / row_bytes);
     if (band < 8) band = 8;
     if (band > p->H) band = p->H;
@@ -329,8 +352,14 @@ int launch_normal_matrix(svconv_plan* p, const float* R, const unsigned char* ma
             st = hip_status(hipGetLastError(), "fill_ones_kernel");
             if (st) return st;
         }
+        if (want_rhs) {
+            hipLaunchKernelGGL(copy_plane_kernel, dim3(1024), dim3(256), 0, p->stream,
+                               I + (size_t)y0 * p->W, p->dTband + (size_t)NF * band_px, band_px);
+            st = hip_status(hipGetLastError(), "copy_plane_kernel");
+            if (st) return st;
+        }
         const int segs = rows * cpr;
-        hipLaunchKernelGGL(gram_kernel, dim3(n_a, segs), dim3(256), 0, p->stream, p->dTband, NF,
+        hipLaunchKernelGGL(gram_kernel, dim3(n_a, segs), dim3(256), 0, p->stream, p->dTband, planes,
                            band_px, y0, p->W, p->H, p->h, cpr, mask, sx, ox, n_a, p->dNMpart);
         st = hip_status(hipGetLastError(), "gram_kernel");
         if (st) return st;
@@ -342,7 +371,10 @@ int launch_normal_matrix(svconv_plan* p, const float* R, const unsigned char* ma
     const int NM = NF * p->M;
     hipLaunchKernelGGL(assemble_jtj, dim3((NM * NM + 255) / 256), dim3(256), 0, p->stream, S, NF,
                        p->M, JtJ);
-    return hip_status(hipGetLastError(), "assemble_jtj");
+    st = hip_status(hipGetLastError(), "assemble_jtj");
+    if (st || !want_rhs) return st;
+    hipLaunchKernelGGL(assemble_rhs, dim3((NM + 255) / 256), dim3(256), 0, p->stream, S, NF, p->M, NF, rhs);
+    return hip_status(hipGetLastError(), "assemble_rhs");
 }
 
 // -------------------------------------------------------- Cholesky ----
@@ -439,8 +471,11 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(double* __restrict__ A,
         const int r = q / nb, c = q - r * nb;
         A[(size_t)(k0 + r) * n + k0 + c] = (c <= r) ? L[r][c] : 0.0;
     }
-    // panel rows below: x L11^T = a, forward substitution over the block's columns
+    // panel rows below: x L11^T = a, forward substitution over the block's
+    // columns on the row held in registers; the empty asm with a memory clobber
+    // keeps the compiler from hoisting all of L11 into registers across rows
     for (int i = k0 + nb + tid; i < n; i += 256) {
+        asm volatile("" ::: "memory");
         double x[CH_NB];
         double* row = A + (size_t)i * n + k0;
 #pragma unroll
@@ -534,28 +569,75 @@ int launch_cholesky(svconv_plan* p, double* A, int n) {
     return SVCONV_OK;
 }
 
-// x = L^-T L^-1 rhs, one workgroup, column-oriented substitutions.
+// x = L^-T L^-1 rhs by blocked substitutions in one workgroup of 1024
+// threads: per block of 32 unknowns, the contributions of the unknowns already
+// solved are summed by all threads (each row or column of L read as coalesced
+// 256-byte runs), then one wave solves the 32 x 32 triangle, broadcasting each
+// unknown across the lanes.  v holds the right-hand side, then the solution.
+constexpr int CS_B = 32;
+
 __global__ __launch_bounds__(1024) void chol_solve_kernel(const double* __restrict__ L,
                                                           const double* __restrict__ rhs,
                                                           double* __restrict__ x, int n) {
     extern __shared__ double v[];   // n doubles
-    const int tid = threadIdx.x;
+    __shared__ double part[CS_B][CS_B + 1];
+    __shared__ double psum[CS_B];
+    const int tid = threadIdx.x, r = tid >> 5, c = tid & 31;
     for (int i = tid; i < n; i += 1024) v[i] = rhs[i];
     __syncthreads();
+    const int nblk = (n + CS_B - 1) / CS_B;
     // forward: L y = b
-    for (int jc = 0; jc < n; ++jc) {
-        const double yj = v[jc] / L[(size_t)jc * n + jc];
+    for (int kb = 0; kb < nblk; ++kb) {
+        const int j0 = kb * CS_B, nb = min(CS_B, n - j0);
+        // psum[r] = sum_{i < j0} L[j0 + r][i] y_i: 32 threads per row, then a
+        // reduction over the 32 lanes of the row
+        double sacc = 0.0;
+        if (r < nb)
+            for (int i = c; i < j0; i += CS_B) sacc = fma(L[(size_t)(j0 + r) * n + i], v[i], sacc);
+#pragma unroll
+        for (int o = 16; o > 0; o >>= 1) sacc += __shfl_xor(sacc, o, 32);
+        if (c == 0 && r < nb) psum[r] = sacc;
         __syncthreads();
-        if (tid == 0) v[jc] = yj;
-        for (int i = jc + 1 + tid; i < n; i += 1024) v[i] -= L[(size_t)i * n + jc] * yj;
+        if (tid < 64) {
+            // lane t < nb: row j0 + t of the triangle
+            const int t = tid;
+            double acc = (t < nb) ? v[j0 + t] - psum[t] : 0.0;
+            for (int j = 0; j < nb; ++j) {
+                const double yj = __shfl(acc, j) / L[(size_t)(j0 + j) * n + j0 + j];
+                if (t > j && t < nb) acc = fma(-L[(size_t)(j0 + t) * n + j0 + j], yj, acc);
+                if (t == j) acc = yj;
+            }
+            if (t < nb) v[j0 + t] = acc;
+        }
         __syncthreads();
     }
     // backward: L^T x = y
-    for (int jc = n - 1; jc >= 0; --jc) {
-        const double xj = v[jc] / L[(size_t)jc * n + jc];
+    for (int kb = nblk - 1; kb >= 0; --kb) {
+        const int j0 = kb * CS_B, nb = min(CS_B, n - j0);
+        // part[r][c] = sum over rows i >= j0 + nb with i = j0 + nb + r (mod 32) of
+        // L[i][j0 + c] x_i: 32 consecutive columns per row read together
+        double sacc = 0.0;
+        if (c < nb)
+            for (int i = j0 + nb + r; i < n; i += CS_B) sacc = fma(L[(size_t)i * n + j0 + c], v[i], sacc);
+        part[r][c] = sacc;
         __syncthreads();
-        if (tid == 0) v[jc] = xj;
-        for (int i = tid; i < jc; i += 1024) v[i] -= L[(size_t)jc * n + i] * xj;
+        if (tid < CS_B) {
+            double sum = 0.0;
+#pragma unroll 8
+            for (int rr = 0; rr < CS_B; ++rr) sum += part[rr][tid];
+            psum[tid] = sum;
+        }
+        __syncthreads();
+        if (tid < 64) {
+            const int t = tid;
+            double acc = (t < nb) ? v[j0 + t] - psum[t] : 0.0;
+            for (int j = nb - 1; j >= 0; --j) {
+                const double xj = __shfl(acc, j) / L[(size_t)(j0 + j) * n + j0 + j];
+                if (t < j) acc = fma(-L[(size_t)(j0 + j) * n + j0 + t], xj, acc);
+                if (t == j) acc = xj;
+            }
+            if (t < nb) v[j0 + t] = acc;
+        }
         __syncthreads();
     }
     for (int i = tid; i < n; i += 1024) x[i] = v[i];
@@ -610,6 +692,26 @@ int launch_scale(svconv_plan* p, double* v, double s, int n) {
 int launch_copy_a(svconv_plan* p, const double* a64, float* a32, int n) {
     hipLaunchKernelGGL(copy_a_kernel, dim3((n + 255) / 256), dim3(256), 0, p->stream, a64, a32, n);
     return hip_status(hipGetLastError(), "copy_a_kernel");
+}
+
+// g = A a - rhs (the half-gradient of the loss, J^T D, from the normal
+// equations): one wave per row of the symmetric A, lanes over its columns
+__global__ __launch_bounds__(256) void ls_grad_kernel(const double* __restrict__ A,
+                                                      const double* __restrict__ a,
+                                                      const double* __restrict__ rhs, int n,
+                                                      double* __restrict__ g) {
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (row >= n) return;
+    const double* Ar = A + (size_t)row * n;
+    double s = 0.0;
+    for (int c = lane; c < n; c += 64) s = fma(Ar[c], a[c], s);
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) g[row] = s - rhs[row];
+}
+
+int launch_ls_grad(svconv_plan* p, const double* A, const double* a64, const double* rhs, double* g, int n) {
+    hipLaunchKernelGGL(ls_grad_kernel, dim3((n + 3) / 4), dim3(256), 0, p->stream, A, a64, rhs, n, g);
+    return hip_status(hipGetLastError(), "ls_grad_kernel");
 }
 
 int launch_gn_update(svconv_plan* p, const double* delta, double* a64, float* a32, int n) {

@@ -59,8 +59,8 @@ constexpr int F32_TW = 64;   // output tile width: 4 waves x 16 columns
 
 // Output rows per tile (= 16-pixel blocks per wave): fewer rows for more
 // filter blocks so that the float32 sub-chain and float64 total fit in 256
-// registers (two waves per SIMD).
-constexpr int f32_tile_h(int nb) { return nb >= 2 ? 4 : 8; }
+// registers (two waves per SIMD) without spilling.
+constexpr int f32_tile_h(int nb) { return nb >= 4 ? 3 : nb >= 2 ? 4 : 8; }
 
 F32Geometry f32_geometry(int k, int nb) {
     F32Geometry g;

@@ -254,7 +254,9 @@ int launch_adjoint_a(svconv_plan* p, const float* R, const float* gD, double* ga
 // fit.hip
 int launch_loss_grad(svconv_plan* p, const float* D, const unsigned char* mask, float* gD,
                      double* loss);
-int launch_normal_matrix(svconv_plan* p, const float* R, const unsigned char* mask, double* JtJ);
+int launch_normal_matrix(svconv_plan* p, const float* R, const float* I, const unsigned char* mask,
+                         double* JtJ, double* rhs);
+int launch_ls_grad(svconv_plan* p, const double* A, const double* a64, const double* rhs, double* g, int n);
 int launch_cholesky(svconv_plan* p, double* A, int n);
 int launch_cholesky_solve(svconv_plan* p, const double* L, const double* rhs, double* x, int n);
 int launch_gn_update(svconv_plan* p, const double* delta, double* a64, float* a32, int n);

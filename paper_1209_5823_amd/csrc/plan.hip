@@ -654,7 +654,13 @@ int svconv_loss_grad(svconv_plan* p, const float* D, const unsigned char* mask, 
 
 int svconv_normal_matrix(svconv_plan* p, const float* R, const unsigned char* mask, double* JtJ) {
     if (!p || !R || !JtJ) return fail(SVCONV_EINVAL, "NULL argument");
-    return launch_normal_matrix(p, R, mask, JtJ);
+    return launch_normal_matrix(p, R, nullptr, mask, JtJ, nullptr);
+}
+
+int svconv_normal_equations(svconv_plan* p, const float* R, const float* I, const unsigned char* mask,
+                            double* JtJ, double* rhs) {
+    if (!p || !R || !I || !JtJ || !rhs) return fail(SVCONV_EINVAL, "NULL argument");
+    return launch_normal_matrix(p, R, I, mask, JtJ, rhs);
 }
 
 int svconv_cholesky_factor(svconv_plan* p, double* A, int n) {
@@ -696,6 +702,39 @@ int svconv_gn_step(svconv_plan* p, const float* R, const float* I, const unsigne
                         "copy loss");
         if (!st) st = hip_status(hipMemcpyAsync(&stats[1], p->dVec + 2 * NM + 1, sizeof(double),
                                                 hipMemcpyDeviceToHost, p->stream), "copy step norm");
+        if (!st) st = hip_status(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
+        if (st) return st;
+        host_stats[0] = stats[0];
+        host_stats[1] = stats[1];
+    }
+    return SVCONV_OK;
+}
+
+int svconv_ls_step(svconv_plan* p, const float* R, const float* I, const unsigned char* mask,
+                   const double* A, const double* L, const double* rhs, double* a64, float* a32,
+                   float* D, double* host_stats) {
+    if (!p || !R || !I || !A || !L || !rhs || !a64 || !a32 || !D)
+        return fail(SVCONV_EINVAL, "NULL argument");
+    if ((const void*)D == (const void*)R) return fail(SVCONV_EINVAL, "D aliases R");
+    const int NK = p->N * p->M;
+    const int NM = NK + p->bg * p->M;
+    double* g = p->dVec;             // [NM]
+    double* delta = p->dVec + NM;    // [NM]
+    double* loss = p->dVec + 2 * NM; // scalar
+    // the residual and its loss at the current coefficients
+    int st = launch_copy_a(p, a64, a32, NM);
+    if (!st) st = run_forward(p, R, I, a32, D);
+    if (!st && p->bg) st = launch_add_background(p, a32 + NK, D);
+    if (!st) st = launch_loss_grad(p, D, mask, p->dGrad, loss);
+    // J^T D = JtJ a - J^T I in float64, then the Newton step of the quadratic loss
+    if (!st) st = launch_ls_grad(p, A, a64, rhs, g, NM);
+    if (!st) st = launch_cholesky_solve(p, L, g, delta, NM);
+    if (!st) st = launch_gn_update(p, delta, a64, a32, NM);
+    if (st) return st;
+    if (host_stats) {
+        double stats[2] = {0.0, 0.0};
+        st = hip_status(hipMemcpyAsync(stats, loss, 2 * sizeof(double), hipMemcpyDeviceToHost, p->stream),
+                        "copy loss and step norm");
         if (!st) st = hip_status(hipStreamSynchronize(p->stream), "hipStreamSynchronize");
         if (st) return st;
         host_stats[0] = stats[0];

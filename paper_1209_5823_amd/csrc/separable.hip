@@ -45,7 +45,11 @@ namespace svc {
 constexpr int SEP_NW = SEP_WAVES;          // waves per workgroup
 constexpr int SEP_RPT = SEP_ROWS;          // output rows per thread (phase B)
 constexpr int SEP_APT = SEP_AOUT;          // row-pass outputs per task (phase A)
-constexpr int SEP_TW = 64, SEP_TH = SEP_RPT * SEP_NW;
+constexpr int SEP_TW = 64;
+// Rows per thread of an instance: the T-only instances of wide kernels take
+// half as many, because their basis-response stores and folded column
+// factors would not fit the registers of SEP_RPT rows without spilling.
+constexpr int sep_rpt(int h, bool tonly) { return (tonly && h > 10) ? SEP_RPT / 2 : SEP_RPT; }
 #ifndef SEP_ROUND
 #define SEP_ROUND 4
 #endif
@@ -54,21 +58,21 @@ constexpr int SEP_CHUNK = SEP_ROUND;       // row factors per phase A / phase B 
 // a round folds at most 4 factors together
 static_assert(SEP_CHUNK == 2 || SEP_CHUNK == 4, "SEP_ROUND must be 2 or 4");
 
-// One basis response T_n on a thread's SEP_RPT rows: in the T-only mode
+// One basis response T_n on a thread's RPT rows: in the T-only mode
 // written out as T_n + s beta_n, else D += c_n T_n with
 // c_n(x, y) = sum_q Cy[q] yh^q (Horner in yh; DSM bounds the spatial degree
 // of the kernel instance).  The pedestal term s beta_n c_n is summed once per
 // pixel at the end.
-template <bool TONLY, int DSM>
-__device__ __forceinline__ void sep_basis_out(const SepArgs& a, int n, const double (&tv)[SEP_RPT],
+template <bool TONLY, int DSM, int RPT>
+__device__ __forceinline__ void sep_basis_out(const SepArgs& a, int n, const double (&tv)[RPT],
                                               int x, int y0, int y_end, int d_s,
                                               const double (&xpow)[DSM + 1],
-                                              const double (&yh)[SEP_RPT], double (&dacc)[SEP_RPT]) {
+                                              const double (&yh)[RPT], double (&dacc)[RPT]) {
     if (TONLY) {
         const double pbt = (double)a.ped * as_const(a.beta)[n];
         if (x < a.W) {
 #pragma unroll
-            for (int o = 0; o < SEP_RPT; ++o) {
+            for (int o = 0; o < RPT; ++o) {
                 const int y = y0 + o;
                 if (y < y_end) a.tout[((size_t)n * a.n_rows + (y - a.y_begin)) * a.W + x] = (float)(tv[o] + pbt);
             }
@@ -78,7 +82,7 @@ __device__ __forceinline__ void sep_basis_out(const SepArgs& a, int n, const dou
     double cy[DSM + 1];
     coef_in_x<DSM>(as_const(a.coefp) + (size_t)n * kSepCoefPad, xpow, cy);
 #pragma unroll
-    for (int o = 0; o < SEP_RPT; ++o) {
+    for (int o = 0; o < RPT; ++o) {
         double cn = cy[DSM];
 #pragma unroll
         for (int q = DSM - 1; q >= 0; --q) cn = fma(cn, yh[o], cy[q]);
@@ -89,13 +93,15 @@ __device__ __forceinline__ void sep_basis_out(const SepArgs& a, int n, const dou
 template <int H, bool TONLY, int DSM>
 __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
     constexpr int NT = 64 * SEP_NW;
+    constexpr int RPT = sep_rpt(H, TONLY);     // output rows per thread
+    constexpr int TH = RPT * SEP_NW;            // output rows per tile
     constexpr int K = 2 * H + 1;
-    constexpr int RA = SEP_TH + 2 * H;          // staged rows
+    constexpr int RA = TH + 2 * H;              // staged rows
     constexpr int CA = SEP_TW + 2 * H;          // staged columns
     constexpr int TP = CA | 1;                  // tile pitch (floats), odd: rows hit distinct banks
     constexpr int RP = SEP_TW + 1;              // row-response pitch, odd for the same reason
     constexpr int WA = SEP_APT + 2 * H;         // phase-A window
-    constexpr int WB = SEP_RPT + 2 * H;         // phase-B window
+    constexpr int WB = RPT + 2 * H;             // phase-B window
     constexpr int NTASK = RA * (SEP_TW / SEP_APT);
     extern __shared__ float sep_lds[];
     float* tile = sep_lds;                      // [RA][TP]
@@ -107,7 +113,7 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
     const int tid = threadIdx.x;
     const int t = sep_xcd_remap(blockIdx.x, a.n_tiles);
     const int X0 = (t % a.tiles_x) * SEP_TW;
-    const int Y0 = a.y_begin + (t / a.tiles_x) * SEP_TH;
+    const int Y0 = a.y_begin + (t / a.tiles_x) * TH;
     const int y_end = min(a.H, a.y_begin + a.n_rows);
 
     // stage R - s; outside the image R is 0, so the staged value is -s there
@@ -126,10 +132,10 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
     xpow[0] = 1.0;
 #pragma unroll
     for (int q = 1; q <= DSM; ++q) xpow[q] = xpow[q - 1] * xh;
-    double yh[SEP_RPT], dacc[SEP_RPT];
+    double yh[RPT], dacc[RPT];
 #pragma unroll
-    for (int rr = 0; rr < SEP_RPT; ++rr) {
-        yh[rr] = a.sy * (Y0 + SEP_RPT * w + rr) + a.oy;
+    for (int rr = 0; rr < RPT; ++rr) {
+        yh[rr] = a.sy * (Y0 + RPT * w + rr) + a.oy;
         dacc[rr] = 0.0;
     }
     const int d_s = a.d_s;
@@ -178,7 +184,7 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
                 const int i = i0 + c;
                 double col[WB];
 #pragma unroll
-                for (int s = 0; s < WB; ++s) col[s] = (double)rc[((size_t)c * RA + SEP_RPT * w + s) * RP + lane];
+                for (int s = 0; s < WB; ++s) col[s] = (double)rc[((size_t)c * RA + RPT * w + s) * RP + lane];
                 // the column factors of row factor i in two groups of one
                 // parity, f_0, f_2, ... and f_1, f_3, ..., up to 4 folded together
                 // (a degree above 7 leaves f_8 or f_9, applied unfolded)
@@ -189,21 +195,21 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
                     const int nf = min(cnt, 4);
                     with_nf(nf, [&](auto nf_c) {
                         constexpr int NF = decltype(nf_c)::value;
-                        double tv[NF][SEP_RPT];
-                        fold_conv<H, NF, SEP_RPT, par == 1>(col, fg + (size_t)par * K, tv);
+                        double tv[NF][RPT];
+                        fold_conv<H, NF, RPT, par == 1>(col, fg + (size_t)par * K, tv);
 #pragma unroll
                         for (int jj = 0; jj < NF; ++jj) {
                             const int j = par + 2 * jj;
-                            sep_basis_out<TONLY, DSM>(a, base + (i + j) * (i + j + 1) / 2 + j, tv[jj], x,
-                                                 Y0 + SEP_RPT * w, y_end, d_s, xpow, yh, dacc);
+                            sep_basis_out<TONLY, DSM, RPT>(a, base + (i + j) * (i + j + 1) / 2 + j, tv[jj], x,
+                                                      Y0 + RPT * w, y_end, d_s, xpow, yh, dacc);
                         }
                     });
                     if (cnt > 4) {
                         const int j = par + 8;
-                        double tv1[SEP_RPT];
-                        direct_conv<H, SEP_RPT>(col, fg + (size_t)j * K, tv1);
-                        sep_basis_out<TONLY, DSM>(a, base + (i + j) * (i + j + 1) / 2 + j, tv1, x,
-                                         Y0 + SEP_RPT * w, y_end, d_s, xpow, yh, dacc);
+                        double tv1[RPT];
+                        direct_conv<H, RPT>(col, fg + (size_t)j * K, tv1);
+                        sep_basis_out<TONLY, DSM, RPT>(a, base + (i + j) * (i + j + 1) / 2 + j, tv1, x,
+                                              Y0 + RPT * w, y_end, d_s, xpow, yh, dacc);
                     }
                 };
                 group(std::false_type{});
@@ -216,8 +222,8 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
         double cy[DSM + 1];
         coef_in_x<DSM>(as_const(a.gammap), xpow, cy);
 #pragma unroll
-        for (int o = 0; o < SEP_RPT; ++o) {
-            const int y = Y0 + SEP_RPT * w + o;
+        for (int o = 0; o < RPT; ++o) {
+            const int y = Y0 + RPT * w + o;
             if (y < y_end) {
                 double pg = cy[DSM];
 #pragma unroll
@@ -271,26 +277,27 @@ int launch_sep_prep(const float* coef, const double* beta, int N, int M, double*
     return hip_status(hipGetLastError(), "sep_prep_kernel");
 }
 
-template <int H>
-static int launch_sep_t(const SepArgs& a, hipStream_t s) {
-    constexpr int RA = SEP_TH + 2 * H, CA = SEP_TW + 2 * H;
+template <int H, bool TONLY, int DSM>
+static int launch_sep_i(SepArgs a, hipStream_t s) {
+    constexpr int TH = sep_rpt(H, TONLY) * SEP_NW;
+    constexpr int RA = TH + 2 * H, CA = SEP_TW + 2 * H;
     const size_t lds = ((size_t)RA * (CA | 1) + (size_t)SEP_CHUNK * RA * (SEP_TW + 1)) * sizeof(float);
-    // TONLY: write the basis responses T_n + s beta_n instead of D; spatial
-    // degrees up to 2 take the instance with the short polynomial in yh
-    if (a.tout)
-        hipLaunchKernelGGL((contract_sep_kernel<H, true, 0>), dim3(a.n_tiles), dim3(64 * SEP_NW), lds, s, a);
-    else if (a.d_s <= 2)
-        hipLaunchKernelGGL((contract_sep_kernel<H, false, 2>), dim3(a.n_tiles), dim3(64 * SEP_NW), lds, s, a);
-    else
-        hipLaunchKernelGGL((contract_sep_kernel<H, false, kMaxSpatialDegree>), dim3(a.n_tiles),
-                           dim3(64 * SEP_NW), lds, s, a);
+    a.tiles_x = (a.W + SEP_TW - 1) / SEP_TW;
+    a.n_tiles = a.tiles_x * ((a.n_rows + TH - 1) / TH);
+    hipLaunchKernelGGL((contract_sep_kernel<H, TONLY, DSM>), dim3(a.n_tiles), dim3(64 * SEP_NW), lds, s, a);
     return hip_status(hipGetLastError(), "contract_sep_kernel");
 }
 
+template <int H>
+static int launch_sep_t(const SepArgs& a, hipStream_t s) {
+    // TONLY: write the basis responses T_n + s beta_n instead of D; spatial
+    // degrees up to 2 take the instance with the short polynomial in yh
+    if (a.tout) return launch_sep_i<H, true, 0>(a, s);
+    if (a.d_s <= 2) return launch_sep_i<H, false, 2>(a, s);
+    return launch_sep_i<H, false, kMaxSpatialDegree>(a, s);
+}
+
 int launch_contract_sep(SepArgs a, hipStream_t s) {
-    a.tiles_x = (a.W + SEP_TW - 1) / SEP_TW;
-    const int tiles_y = (a.n_rows + SEP_TH - 1) / SEP_TH;
-    a.n_tiles = a.tiles_x * tiles_y;
     switch (a.h) {
         case 1: return launch_sep_t<1>(a, s);
         case 2: return launch_sep_t<2>(a, s);

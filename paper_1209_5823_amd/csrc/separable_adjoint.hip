@@ -373,8 +373,12 @@ struct SepRArgs {
 #ifndef SR_WG_PER_CU
 #define SR_WG_PER_CU 4          // minimum waves per SIMD (launch bounds)
 #endif
+// At h = 15 the two column tasks of a thread, their 38-sample windows and the
+// row-pass sums do not fit 128 registers: that instance takes 3 waves per SIMD.
+constexpr int sr_waves_per_simd(int h) { return h >= 15 ? 3 : SR_WG_PER_CU; }
+
 template <int H>
-__global__ __launch_bounds__(SR_NT, SR_WG_PER_CU) void adjoint_r_sep_kernel(SepRArgs a) {
+__global__ __launch_bounds__(SR_NT, sr_waves_per_simd(H)) void adjoint_r_sep_kernel(SepRArgs a) {
     constexpr int K = 2 * H + 1;
     constexpr int RA = SR_TH + 2 * H, CA = SR_TW + 2 * H, CP = CA | 1;
     constexpr int WB = SR_RPT + 2 * H;                  // window of a column task / row task

@@ -182,8 +182,13 @@ __device__ __forceinline__ void smm_load_frag(const uint16_t* tab, int lane, uin
 // the column's powers of xh, over the 16 columns of the wave) and adds them to
 // one of kSepMomCopies copies of the sums (float64 atomics); slot N holds
 // sum_p G P_m for the pedestal term.
+// The adjoint instances at spatial degree above 3 hold the moments of
+// (d + 1) powers across the column pass: they take 3 waves per SIMD (one
+// workgroup per CU) so that their registers do not spill.
+constexpr int smm_waves_per_simd(bool adj, int dsm) { return (adj && dsm > 3) ? 3 : SM_MINW; }
+
 template <bool FP16, int NT, int DSM, bool ADJ = false>
-__global__ __launch_bounds__(SM_NT, SM_MINW) void contract_sepmm_kernel(SepArgs a, const uint16_t* __restrict__ frag) {
+__global__ __launch_bounds__(SM_NT, smm_waves_per_simd(ADJ, DSM)) void contract_sepmm_kernel(SepArgs a, const uint16_t* __restrict__ frag) {
     extern __shared__ uint4 smm_lds[];
     uint16_t* xs = reinterpret_cast<uint16_t*>(smm_lds);   // [2][SM_XR][SM_P]
     uint16_t* ut = xs + 2 * SM_XR * SM_P;                     // [SM_SLOTS][2][64][SM_P]

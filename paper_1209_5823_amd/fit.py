@@ -38,6 +38,29 @@ def gauss_newton_fit(plan, R, I, a0, iters=4, mask=None, timings=False):
     return a64, D, hist, t_setup
 
 
+def least_squares_fit(plan, R, I, a0, iters=3, mask=None, timings=False):
+    """Fit a from a0 on the normal equations (JtJ, J^T I) built in one pass:
+    each iteration forms D and its loss at the current a, then the float64
+    Newton step (JtJ)^-1 (JtJ a - J^T I).  Same returns as gauss_newton_fit.
+    """
+    t0 = time.perf_counter()
+    A, rhs = plan.normal_equations(R, I, mask)
+    L = A.clone()
+    plan.cholesky_factor(L)            # synchronises the plan's stream
+    t_setup = time.perf_counter() - t0
+    a64 = a0.to(torch.float64).contiguous().clone()
+    a32 = torch.empty(a64.shape, dtype=torch.float32, device=a64.device)
+    D = torch.empty_like(R)
+    hist = []
+    for _ in range(iters):
+        t = time.perf_counter()
+        loss, step = plan.ls_step(R, I, A, L, rhs, a64, a32, D, mask)   # synchronises
+        hist.append((loss, step, time.perf_counter() - t if timings else None))
+    a32.copy_(a64.to(torch.float32))
+    plan.difference(R, I, a32, out=D)
+    return a64, D, hist, t_setup
+
+
 def stamp_preconditioned_fit(plan, R, I, a0, sky, threshold, frac=0.1, iters=8, mask=None,
                              stamp_iters=1, rounds=1, timings=False):
     """Optimal Image Subtraction on isolated stars, then the whole image.

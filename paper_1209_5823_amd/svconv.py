@@ -194,6 +194,20 @@ class Plan:
               "svconv_normal_matrix")
         return JtJ
 
+    def normal_equations(self, R, I, mask=None):
+        """(Phi^T Phi, Phi^T I) over the mask in one pass; float64."""
+        nm = self._fit_coef[0] * self._fit_coef[1]
+        JtJ = torch.empty((nm, nm), dtype=torch.float64, device=R.device)
+        rhs = torch.empty((nm,), dtype=torch.float64, device=R.device)
+        self._sync_stream()
+        check(self._lib.svconv_normal_equations(self._p, _dev_ptr(R, torch.float32, self._img, "R"),
+                                                _dev_ptr(I, torch.float32, self._img, "I"),
+                                                _opt_ptr(mask, torch.uint8, self._img, "mask"),
+                                                _dev_ptr(JtJ, torch.float64, (nm, nm), "JtJ"),
+                                                _dev_ptr(rhs, torch.float64, (nm,), "rhs")),
+              "svconv_normal_equations")
+        return JtJ, rhs
+
     def cholesky_factor(self, A):
         """In-place Cholesky factor (lower) of a float64 SPD matrix."""
         n = A.shape[0]
@@ -227,6 +241,25 @@ class Plan:
                                        _dev_ptr(a32, torch.float32, fc, "a32"),
                                        _dev_ptr(D, torch.float32, self._img, "D"), st),
               "svconv_gn_step")
+        return (st[0], st[1]) if stats else None
+
+    def ls_step(self, R, I, A, L, rhs, a64, a32, D, mask=None, stats=True):
+        """One Newton step on the normal equations (A = JtJ, L its factor,
+        rhs = J^T I); returns (loss before the step, ||delta||)."""
+        fc = self._fit_coef
+        nm = fc[0] * fc[1]
+        st = (ctypes.c_double * 2)() if stats else None
+        self._sync_stream()
+        check(self._lib.svconv_ls_step(self._p, _dev_ptr(R, torch.float32, self._img, "R"),
+                                       _dev_ptr(I, torch.float32, self._img, "I"),
+                                       _opt_ptr(mask, torch.uint8, self._img, "mask"),
+                                       _dev_ptr(A, torch.float64, (nm, nm), "A"),
+                                       _dev_ptr(L, torch.float64, (nm, nm), "L"),
+                                       _dev_ptr(rhs, torch.float64, (nm,), "rhs"),
+                                       _dev_ptr(a64, torch.float64, fc, "a64"),
+                                       _dev_ptr(a32, torch.float32, fc, "a32"),
+                                       _dev_ptr(D, torch.float32, self._img, "D"), st),
+              "svconv_ls_step")
         return (st[0], st[1]) if stats else None
 
     def pcg_fit(self, R, I, L, a64, a32, D, iters, mask=None, residuals=True):

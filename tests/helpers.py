@@ -55,3 +55,15 @@ def sample_pixels(H, W, n, seed, R=None, h=0):
         ys += list(flat // W)
         xs += list(flat % W)
     return np.array(xs, dtype=np.int32), np.array(ys, dtype=np.int32)
+
+
+_INPUTS = {}
+
+
+def workload_images(name):
+    """(R, a, I) of a workload (synth recipe), generated once per test session."""
+    if name not in _INPUTS:
+        wl = synth.WORKLOADS[name]
+        R, a = synth.workload_inputs(wl)
+        _INPUTS[name] = (R, a, synth.second_image(wl))
+    return _INPUTS[name]

@@ -83,6 +83,8 @@ def test_null_plan_and_null_pointers(lib):
     assert lib.svconv_cholesky_factor(None, None, 4) == E
     assert lib.svconv_cholesky_solve(None, None, None, None, 4) == E
     assert lib.svconv_gn_step(None, None, None, None, None, None, None, None, None) == E
+    assert lib.svconv_normal_equations(None, None, None, None, None, None) == E
+    assert lib.svconv_ls_step(None, None, None, None, None, None, None, None, None, None, None) == E
     assert lib.svconv_plan_destroy(None) == _lib.OK
 
 

@@ -1,6 +1,8 @@
 """GPU parity of the least-squares fit pieces: loss and gradient, normal
-matrix, Cholesky factor and solve, and Gauss-Newton recovery of noiseless
-coefficients; all against the FP64 oracle or numpy's FP64 linear algebra."""
+matrix and normal equations, Cholesky factor and solve, Gauss-Newton recovery
+of noiseless coefficients, and the Newton steps on the normal equations
+reaching the oracle's least-squares solution; all against the FP64 oracle or
+numpy's FP64 linear algebra."""
 
 import numpy as np
 import pytest
@@ -102,3 +104,59 @@ def test_gauss_newton_recovers_noiseless_coefficients(svc, orc, precision):
     tol = 2e-5 if precision == "fp32" else 2e-3
     assert err <= tol
     assert hist[-1][0] < 1e-3 * hist[0][0]
+
+
+@pytest.mark.parametrize("form,precision,with_mask", [("basis", "fp32", False),
+                                                      ("separable", "fp32", True),
+                                                      ("separable_regrouped", "fp16x3", False)])
+def test_normal_equations_vs_oracle(svc, orc, form, precision, with_mask):
+    R, C, a_star, B, (H, W, h, sig, deg, d_s) = small_case(orc)
+    I = synth.poisson_noise(C, seed=12)
+    mask = None
+    if with_mask:
+        mask = (synth.uniform_image(H, W, seed=11) > -0.5).astype(np.uint8)
+    JtJ_ref, rhs_ref = orc.normal_equations(R, I, h, B, d_s, mask=mask)
+    say("normal equations", form, precision, with_mask)
+    with svc.Plan(H, W, h, sig, deg, d_s, precision=precision, form=form) as plan:
+        JtJ, rhs = plan.normal_equations(to_dev(R), to_dev(I), None if mask is None else to_dev(mask))
+        JtJ, rhs = to_host(JtJ), to_host(rhs)
+        JtJ_only = to_host(plan.normal_matrix(to_dev(R), None if mask is None else to_dev(mask)))
+    e_m = np.abs(JtJ - JtJ_ref).max() / np.abs(JtJ_ref).max()
+    e_r = np.abs(rhs - rhs_ref).max() / np.abs(rhs_ref).max()
+    say("  rel err JtJ %.3e rhs %.3e" % (e_m, e_r))
+    # float32 basis responses, float64 sums
+    assert e_m <= 2e-6 and e_r <= 2e-6
+    # the extra plane of I changes no entry of the matrix
+    assert np.array_equal(JtJ, JtJ_only)
+
+
+@pytest.mark.parametrize("form,precision", [("separable", "fp32"), ("basis", "bf16x3"),
+                                            ("separable_regrouped", "fp16x3")])
+def test_least_squares_steps_reach_oracle_solution(svc, orc, form, precision):
+    import torch
+    from paper_1209_5823_amd.fit import least_squares_fit
+    R, C, a_star, B, (H, W, h, sig, deg, d_s) = small_case(orc, H=96, W=112)
+    I = synth.poisson_noise(C, seed=13)
+    JtJ_ref, rhs_ref = orc.normal_equations(R, I, h, B, d_s)
+    a_ls = orc.cholesky_solve(JtJ_ref, rhs_ref).reshape(a_star.shape)
+    inner = orc.interior_mask(H, W, h)
+    L_ls = float(np.sum(orc.difference(R, I, h, B, d_s, a_ls)[inner] ** 2))
+    r = np.random.default_rng(3)
+    a0 = (a_star + r.uniform(-0.02, 0.02, a_star.shape)).astype(np.float32)
+    say("least-squares steps", form, precision)
+    with svc.Plan(H, W, h, sig, deg, d_s, precision=precision, form=form, pedestal=1000.0) as plan:
+        a64, D, hist, _ = least_squares_fit(plan, to_dev(R), to_dev(I), to_dev(a0), iters=4)
+        a_fit = to_host(a64)
+    for k, (L, step, _) in enumerate(hist):
+        say("  it %d loss %.9e step %.3e" % (k, L, step))
+    da = (a_fit - a_ls).ravel()
+    q = float(da @ JtJ_ref @ da)
+    L_fit = float(np.sum(orc.difference(R, I, h, B, d_s, a_fit)[inner] ** 2))
+    say("  loss %.9e (oracle %.9e), (a - a_ls)^T JtJ (a - a_ls) = %.3e" % (L_fit, L_ls, q))
+    # the loss is quadratic with minimum L_ls at a_ls: L(a) - L_ls = q, and the
+    # float32 basis responses in JtJ and rhs move the solution by far less
+    # than the noise
+    assert q <= 1e-6 * L_ls
+    assert abs(L_fit - L_ls) <= 1e-6 * L_ls
+    # float64 refinement: the steps fall by orders of magnitude
+    assert hist[-1][1] <= 1e-6 * hist[0][1]

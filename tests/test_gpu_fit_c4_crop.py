@@ -1,9 +1,10 @@
 """The fit with the survey-scale basis (49 bases, 31 x 31 kernel, spatial
 degree 4: 735 coefficients) on a crop of the 8192 x 8192 frame, against the
-FP64 oracle: the normal matrix element by element, and the Gauss-Newton fit's
-loss against the loss at the oracle's least-squares solution (OIS least
-squares, Sec. 2; D is linear in a, Eq. 2 - Eq. 3, so the loss is quadratic and
-its minimiser unique)."""
+FP64 oracle: the normal equations (matrix and right-hand side) element by
+element, and the loss of the Gauss-Newton fit and of the Newton steps on the
+normal equations against the loss at the oracle's least-squares solution (OIS
+least squares, Sec. 2; D is linear in a, Eq. 2 - Eq. 3, so the loss is
+quadratic and its minimiser unique)."""
 
 import numpy as np
 import pytest
@@ -36,27 +37,31 @@ def test_normal_matrix_c4_basis_vs_oracle(svc, orc):
     H, W = CROP
     frame = (ORIGIN[0], ORIGIN[1], C4.width, C4.height)
     R, I, a_hidden, B = crop_inputs(orc, frame)
-    say("c4 crop normal matrix (oracle)")
-    JtJ_ref, _ = orc.normal_equations(R, None, C4.half_width, B, C4.spatial_degree, frame=frame)
+    say("c4 crop normal equations (oracle)")
+    JtJ_ref, rhs_ref = orc.normal_equations(R, I, C4.half_width, B, C4.spatial_degree, frame=frame)
     scale = np.abs(JtJ_ref).max()
     for form in ("separable", "basis"):
-        say("c4 crop normal matrix", form, JtJ_ref.shape)
+        say("c4 crop normal equations", form, JtJ_ref.shape)
         with svc.Plan(H, W, C4.half_width, C4.sigmas, C4.degrees, C4.spatial_degree, form=form,
                       frame=frame) as plan:
-            JtJ = to_host(plan.normal_matrix(to_dev(R)))
+            JtJ, rhs = plan.normal_equations(to_dev(R), to_dev(I))
+            JtJ, rhs = to_host(JtJ), to_host(rhs)
         err = np.abs(JtJ - JtJ_ref).max() / scale
-        say("  max |dJtJ| / max |JtJ| = %.3e" % err)
-        # float32 basis responses (basis form) or float64 passes (separable form),
-        # float64 sums: elementwise agreement to float32 rounding of the largest entry
-        assert err <= 2e-6
+        err_r = np.abs(rhs - rhs_ref).max() / np.abs(rhs_ref).max()
+        say("  max |dJtJ| / max |JtJ| = %.3e, max |drhs| / max |rhs| = %.3e" % (err, err_r))
+        # float32 basis responses (float64 passes in the separable form), float64
+        # sums: elementwise agreement to float32 rounding of the largest entry
+        assert err <= 2e-6 and err_r <= 2e-6
         assert np.allclose(JtJ, JtJ.T, rtol=0, atol=1e-12 * scale)
 
 
-def test_fit_loss_reaches_oracle_least_squares(svc, orc):
+@pytest.mark.parametrize("method", ["gauss_newton", "normal_equations"])
+def test_fit_loss_reaches_oracle_least_squares(svc, orc, method):
     # the crop as its own frame (spatial terms over [-1, 1]): the normal matrix
     # is invertible in float64, though with a condition number near 1e14, so
     # the coefficients are poorly determined while the loss is not
-    from paper_1209_5823_amd.fit import gauss_newton_fit
+    from paper_1209_5823_amd.fit import gauss_newton_fit, least_squares_fit
+    fit = gauss_newton_fit if method == "gauss_newton" else least_squares_fit
     H, W = CROP
     R, I, a_hidden, B = crop_inputs(orc, None)
     say("c4 crop least squares (oracle)")
@@ -68,10 +73,10 @@ def test_fit_loss_reaches_oracle_least_squares(svc, orc):
     ev = np.linalg.eigvalsh(JtJ_ref)
     r = np.random.default_rng(43)
     a0 = (a_hidden + r.uniform(-0.01, 0.01, a_hidden.shape)).astype(np.float32)
-    say("c4 crop Gauss-Newton fit; cond(JtJ) = %.3e" % (ev[-1] / ev[0]))
+    say("c4 crop fit (%s); cond(JtJ) = %.3e" % (method, ev[-1] / ev[0]))
     with svc.Plan(H, W, C4.half_width, C4.sigmas, C4.degrees, C4.spatial_degree, form="separable",
                   pedestal=synth.SKY_LEVEL) as plan:
-        a64, D, hist, _ = gauss_newton_fit(plan, to_dev(R), to_dev(I), to_dev(a0), iters=6)
+        a64, D, hist, _ = fit(plan, to_dev(R), to_dev(I), to_dev(a0), iters=6)
         a_fit = to_host(a64)
         L_fit = float(to_host(plan.loss_grad(D)[0]))
     for k, (L, step, _) in enumerate(hist):

@@ -3,9 +3,11 @@ bases, spatial degree 4 (735 coefficients).  I = float32(Poisson(C(R;
 a_hidden))) with C from the oracle's FFT regrouping; the coefficients are
 fitted by Gauss-Newton with the bf16x3 and FP32 matrix-core forwards and with
 the separable form (forward and adjoint through the Gaussian factors; the
-forward in float64 or on the matrix cores in fp16x3).  Reports the
-recovered-coefficient error, the final D RMS in sigma_sky and the Mpix/s of
-one iteration."""
+forward in float64 or on the matrix cores in fp16x3), and by Newton steps on
+the normal equations (matrix and right-hand side from one pass over the
+image; per iteration the forward, the loss, J^T D = JtJ a - J^T I in float64
+and the two triangular solves).  Reports the recovered-coefficient error, the
+final D RMS in sigma_sky and the Mpix/s of one iteration."""
 
 import numpy as np
 import pytest
@@ -62,3 +64,31 @@ def test_fit_survey_scale(svc, c4_case, precision, form):
     # Poisson noise of the sky and stars sets D's floor: rms just above 1 sigma
     assert 0.95 < rms < 1.6
     assert hist[-1][1] < 1e-2 * hist[0][1]
+
+
+@pytest.mark.parametrize("precision,form", [("fp16x3", "separable_regrouped"), ("fp32", "separable")])
+def test_least_squares_fit_survey_scale(svc, c4_case, precision, form):
+    from paper_1209_5823_amd.fit import least_squares_fit
+    wl, R, I, a_hidden, a0 = c4_case
+    say("c4 least-squares fit", precision, form)
+    with svc.plan_for(wl, precision=precision, form=form, pedestal=synth.SKY_LEVEL) as plan:
+        Rd, Id = to_dev(R), to_dev(I)
+        a64, D, hist, t_setup = least_squares_fit(plan, Rd, Id, to_dev(a0), iters=4, timings=True)
+        Dh = to_host(D)
+        L_fit = float(to_host(plan.loss_grad(D)[0]))
+        L_true = float(to_host(plan.loss_grad(plan.difference(Rd, Id, to_dev(a_hidden)))[0]))
+    h = wl.half_width
+    rms = float(np.sqrt(np.mean(Dh[h:-h, h:-h].astype(np.float64) ** 2)) / synth.sky_sigma())
+    it_s = sorted(t for _, _, t in hist)[len(hist) // 2]
+    say("  setup (normal equations + Cholesky) %.3f s" % t_setup)
+    for k, (L, step, t) in enumerate(hist):
+        say("  it %d loss %.6e step %.3e  %.2f ms" % (k, L, step, 1e3 * t))
+    say("  D rms %.4f sigma_sky; loss at the fit %.9e, at the hidden coefficients %.9e; "
+        "median iteration %.2f ms (%.0f Mpix/s)" % (rms, L_fit, L_true, 1e3 * it_s,
+                                                     wl.height * wl.width / it_s / 1e6))
+    assert L_fit <= L_true * (1 + 1e-6)
+    assert 0.95 < rms < 1.6
+    # float64 refinement on the normal equations: the last step is at most
+    # 1e-4 of the first, at a median iteration of at most 8 ms
+    assert hist[-1][1] <= 1e-4 * hist[0][1]
+    assert it_s <= 8e-3

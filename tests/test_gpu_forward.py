@@ -12,7 +12,8 @@ import numpy as np
 import pytest
 
 import synth
-from tests.helpers import (TOL_FP32, TOL_MFMA, say, to_dev, to_host, err_stats, sample_pixels)
+from tests.helpers import (TOL_FP32, TOL_MFMA, say, to_dev, to_host, err_stats, sample_pixels,
+                           workload_images)
 
 pytestmark = pytest.mark.gpu
 
@@ -115,13 +116,14 @@ def test_delta_kernel_identity(svc):
     assert np.array_equal(D, (R.astype(np.float64) - I).astype(np.float32))
 
 
+@pytest.mark.parametrize("form", ["basis", "regrouped"])
 @pytest.mark.parametrize("wl_name", ["c1", "c3", "c4"])
-def test_full_size_sampled_fp32(svc, orc, wl_name):
+def test_full_size_sampled_fp32(svc, orc, wl_name, form):
     wl = synth.WORKLOADS[wl_name]
-    R, a = synth.workload_inputs(wl)
-    I = synth.second_image(wl)
-    say("full size sampled", wl_name, R.shape)
-    D = run_difference(svc, R, I, a, wl.half_width, wl.sigmas, wl.degrees, wl.spatial_degree)
+    R, a, I = workload_images(wl_name)
+    say("full size sampled", wl_name, form, R.shape)
+    D = run_difference(svc, R, I, a, wl.half_width, wl.sigmas, wl.degrees, wl.spatial_degree,
+                       form=form)
     B = orc.basis(wl.half_width, wl.sigmas, wl.degrees)
     xs, ys = sample_pixels(wl.height, wl.width, 1500, seed=3, R=R, h=wl.half_width)
     Dref = orc.convolve_at(R, wl.half_width, B, wl.spatial_degree, a, xs, ys) - I[ys, xs]
@@ -212,14 +214,14 @@ def test_lowp_rejects_half_width_above_15(svc):
         assert ei.value.status == EUNSUPPORTED
 
 
+@pytest.mark.parametrize("form", ["basis", "regrouped"])
 @pytest.mark.parametrize("precision", LOWP)
-def test_full_size_sampled_lowp(svc, orc, precision):
+def test_full_size_sampled_lowp(svc, orc, precision, form):
     wl = synth.WORKLOADS["c1"]
-    R, a = synth.workload_inputs(wl)
-    I = synth.second_image(wl)
-    say("full size sampled", precision)
+    R, a, I = workload_images("c1")
+    say("full size sampled", precision, form)
     D = run_difference(svc, R, I, a, wl.half_width, wl.sigmas, wl.degrees, wl.spatial_degree,
-                       precision=precision, pedestal=synth.SKY_LEVEL)
+                       precision=precision, form=form, pedestal=synth.SKY_LEVEL)
     B = orc.basis(wl.half_width, wl.sigmas, wl.degrees)
     xs, ys = sample_pixels(wl.height, wl.width, 1500, seed=4, R=R, h=wl.half_width)
     Dref = orc.convolve_at(R, wl.half_width, B, wl.spatial_degree, a, xs, ys) - I[ys, xs]

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests.helpers import TOL_MFMA, say, err_stats, sample_pixels, to_dev, to_host
+from tests.helpers import TOL_MFMA, say, err_stats, sample_pixels, to_dev, to_host, workload_images
 from tests.test_gpu_forward import EDGE_CASES, _edge_inputs, run_difference, LOWP
 from tests.test_gpu_separable import FOLD_CASES
 
@@ -89,17 +89,20 @@ def test_high_degree_families(svc, orc, name):
 
 
 @pytest.mark.parametrize("precision", ["fp16x3", "bf16x3"])
-def test_full_chip_sampled(svc, orc, precision):
-    # the 2048 x 4096 chip at full size in the launch configuration the bench
-    # times, checked on sampled pixels (and the brightest ones) against the oracle
-    wl = synth.WORKLOADS["c1"]
-    R, a = synth.workload_inputs(wl)
-    I = synth.second_image(wl)
+@pytest.mark.parametrize("wl_name", ["c1", "c3", "c4"])
+def test_full_size_sampled(svc, orc, precision, wl_name):
+    # full-size frames in the launch configurations the bench and the fit time
+    # (the 2048 x 4096 chip; 4096^2 with a 31 x 31 kernel and spatial degree 3;
+    # 8192^2 with spatial degree 4), checked on sampled pixels (and the brightest
+    # ones) against the oracle
+    wl = synth.WORKLOADS[wl_name]
+    R, a, I = workload_images(wl_name)
     B = orc.basis(wl.half_width, wl.sigmas, wl.degrees)
-    say("separable mma c1 full size", precision)
+    say("separable mma full size", wl_name, precision)
     D = run_difference(svc, R, I, a, wl.half_width, wl.sigmas, wl.degrees, wl.spatial_degree,
                        precision=precision, form="separable", pedestal=synth.SKY_LEVEL)
-    xs, ys = sample_pixels(wl.height, wl.width, 20000, seed=5, R=R, h=wl.half_width)
+    n = 20000 if wl_name == "c1" else 6000
+    xs, ys = sample_pixels(wl.height, wl.width, n, seed=5, R=R, h=wl.half_width)
     Dref = orc.convolve_at(R, wl.half_width, B, wl.spatial_degree, a, xs, ys) - I[ys, xs]
     e = np.abs(D[ys, xs] - Dref)
     say("  max %.3e (%.2e sigma) over %d pixels" % (e.max(), e.max() / np.sqrt(1000), len(ys)))
