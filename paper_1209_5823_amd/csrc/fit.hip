@@ -695,18 +695,52 @@ int launch_copy_a(svconv_plan* p, const double* a64, float* a32, int n) {
 }
 
 // g = A a - rhs (the half-gradient of the loss, J^T D, from the normal
-// equations): one wave per row of the symmetric A, lanes over its columns
+// equations): one wave per row of the symmetric A, lanes over its columns.
+// The dot product is compensated (error-free products and sums, Ogita, Rump
+// and Oishi's Dot2): g is then as accurate as if formed in twice the float64
+// precision and rounded once, which iterative refinement needs to converge
+// past cond(A) eps (A a and rhs nearly cancel at the solution).
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+#pragma clang fp contract(off)
+    s = a + b;
+    const double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+__device__ __forceinline__ void two_prod(double a, double b, double& p, double& e) {
+#pragma clang fp contract(off)
+    p = a * b;
+    e = fma(a, b, -p);
+}
+
 __global__ __launch_bounds__(256) void ls_grad_kernel(const double* __restrict__ A,
                                                       const double* __restrict__ a,
                                                       const double* __restrict__ rhs, int n,
                                                       double* __restrict__ g) {
+#pragma clang fp contract(off)
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (row >= n) return;
     const double* Ar = A + (size_t)row * n;
-    double s = 0.0;
-    for (int c = lane; c < n; c += 64) s = fma(Ar[c], a[c], s);
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) g[row] = s - rhs[row];
+    double s = 0.0, c = 0.0;   // sum and its accumulated error terms
+    for (int k = lane; k < n; k += 64) {
+        double p, pe, t, te;
+        two_prod(Ar[k], a[k], p, pe);
+        two_sum(s, p, t, te);
+        s = t;
+        c += te + pe;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const double so = __shfl_xor(s, o), co = __shfl_xor(c, o);
+        double t, te;
+        two_sum(s, so, t, te);
+        s = t;
+        c += co + te;
+    }
+    if (lane == 0) {
+        double t, te;
+        two_sum(s, -rhs[row], t, te);
+        g[row] = t + (c + te);
+    }
 }
 
 int launch_ls_grad(svconv_plan* p, const double* A, const double* a64, const double* rhs, double* g, int n) {

@@ -66,7 +66,7 @@ def test_fit_survey_scale(svc, c4_case, precision, form):
     assert hist[-1][1] < 1e-2 * hist[0][1]
 
 
-@pytest.mark.parametrize("precision,form", [("fp16x3", "separable_regrouped"), ("fp32", "separable")])
+@pytest.mark.parametrize("precision,form", [("fp16x3", "separable"), ("fp32", "separable")])
 def test_least_squares_fit_survey_scale(svc, c4_case, precision, form):
     from paper_1209_5823_amd.fit import least_squares_fit
     wl, R, I, a_hidden, a0 = c4_case
