@@ -71,6 +71,24 @@ enum svconv_precision {
     SVCONV_FP16X2 = 4,  /* R split hi+lo in fp16, B in fp16: hh + lh          */
     SVCONV_FP16X3 = 5   /* R and B split hi+lo in fp16: hh + lh + hl          */
 };
+/* Error of D against its float64 definition, max |dD| over the interior of
+ * star fields on a 1000 ADU sky (sigma_sky = sqrt(1000) = 31.6 ADU; the
+ * brightest stars near 1e5 ADU), with the pedestal at the sky level:
+ *   SVCONV_FP32    below 1e-4 sigma_sky in every form;
+ *   SVCONV_FP16X3  about 1e-4 sigma_sky;
+ *   SVCONV_BF16X3  up to 1.5e-3 sigma_sky;
+ *   SVCONV_FP16X2  up to 5e-2 sigma_sky (the taps keep 11 bits);
+ *   SVCONV_FP16    up to 5e-2 sigma_sky, and
+ *   SVCONV_BF16    up to 0.5 sigma_sky (one 16-bit part per operand).
+ * Only FP32, FP16X3 and BF16X3 stay within 1e-2 sigma_sky; FP16X2, FP16
+ * and BF16 are faster and miss that bound at bright stars.  A split value x
+ * is hi + lo with hi = x rounded to 16 bits and lo = (x - hi) rounded to 16
+ * bits (x - hi is exact in float32).  The basis and regrouped forms and every
+ * filter tap round to nearest even: |x - hi - lo| <= 2^-22 |x| (fp16) or
+ * 2^-16 |x| (bf16).  The separable forms round the fp16 parts of image data
+ * and row responses toward zero (one instruction for two values):
+ * |x - hi - lo| < 2^-20 |x|; the adjoint in R truncates the bf16 hi part:
+ * < 2^-15 |x|.  The measured errors above include these roundings. */
 
 /* How the per-pixel kernel is contracted (both give D of Eq. 1 exactly, up
  * to rounding).  BASIS: N basis responses T_n = B_n (x) R, then

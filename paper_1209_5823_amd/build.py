@@ -54,6 +54,9 @@ def _compile(src):
 
 def build(verbose=True):
     os.makedirs(BUILD, exist_ok=True)
+    # a failed build leaves no library behind, so nothing loads a stale one
+    if os.path.exists(LIB):
+        os.remove(LIB)
     srcs = sources()
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         results = list(ex.map(_compile, srcs))

@@ -134,10 +134,13 @@ __host__ __device__ __forceinline__ int sz_row_sample(int cg, int g, int t) {
 
 // Row-response row (relative to the first output row of an 8-row block) that
 // reduction entry (g, t) of the column pass stands for; phase 0 blocks start
-// on a 16-row block boundary (blocks b, b + 1), phase 1 blocks 8 rows into
-// one (lane groups 0, 1 take blocks b + 1, b + 2, groups 2, 3 blocks b, b + 1).
+// on a 16-row block boundary (entries t < 4 from block b, t >= 4 from block
+// b + 1), phase 1 blocks 8 rows into one (t < 4 from block b + 1 in every
+// lane group, t >= 4 from block b + 2 in lane groups 0, 1 and from block b
+// in groups 2, 3), so that only half of a phase 1 operand is chosen per lane.
 __host__ __device__ __forceinline__ int sz_col_row(int ph, int g, int t) {
-    return (t < 4 ? 0 : 16) + 4 * g + (t & 3) + (ph ? (g < 2 ? 8 : -8) : 0);
+    if (!ph) return (t < 4 ? 0 : 16) + 4 * g + (t & 3);
+    return (t < 4 ? 8 : (g < 2 ? 24 : -8)) + 4 * g + (t & 3);
 }
 
 // Row-pass tap tables, fp16 then bf16 (or only precision p0 when np = 1):
@@ -294,6 +297,14 @@ int launch_sepz_prep(const SepZArgs& z, const float* a, const double* f1d, const
     return hip_status(hipGetLastError(), "sepz_prep_kernel");
 }
 
+// 16 bytes of LDS through an LDS-space pointer.
+typedef const __attribute__((address_space(3))) uint16_t* lds_u16;
+typedef unsigned int sz_u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 sz_lds16(lds_u16 p) {
+    const sz_u32x4 v = *(const __attribute__((address_space(3))) sz_u32x4*)p;
+    return make_uint4(v[0], v[1], v[2], v[3]);
+}
+
 // DPP row rotation by 8 lanes written only into the banks of bank_mask (the
 // other lanes keep `old`).
 template <int BANKS>
@@ -316,6 +327,16 @@ template <bool FP16, int NT, int MP>
 __device__ __forceinline__ void sz_colpass(sz_f4 (&Z)[MP][SZ_OB], const uint32_t (&Uh)[2 * SZ_RB],
                                            const uint32_t (&Ul)[2 * SZ_RB], const uint16_t* __restrict__ zt,
                                            int lane) {
+    // phase 1 windows: block b + 1, then block b + 2 (lane groups 0, 1) or
+    // block b (groups 2, 3); formed once for every spatial term
+    uint4 w1h[SZ_OB / 2], w1l[SZ_OB / 2];
+#pragma unroll
+    for (int b = 0; b < SZ_OB / 2; ++b) {
+        w1h[b] = make_uint4(Uh[2 * b + 2], Uh[2 * b + 3], sz_sel_low(Uh[2 * b + 4], Uh[2 * b]),
+                            sz_sel_low(Uh[2 * b + 5], Uh[2 * b + 1]));
+        w1l[b] = make_uint4(Ul[2 * b + 2], Ul[2 * b + 3], sz_sel_low(Ul[2 * b + 4], Ul[2 * b]),
+                            sz_sel_low(Ul[2 * b + 5], Ul[2 * b + 1]));
+    }
 #pragma unroll
     for (int mp = 0; mp < MP; ++mp) {
         uint4 za[2][2];   // [phase][hi/lo]
@@ -326,24 +347,18 @@ __device__ __forceinline__ void sz_colpass(sz_f4 (&Z)[MP][SZ_OB], const uint32_t
                 za[ph][hl] = *reinterpret_cast<const uint4*>(zt + (size_t)mp * SZ_FRAG + ((ph * 2 + hl) * 64 + lane) * 8);
 #pragma unroll
         for (int b = 0; b < SZ_OB / 2; ++b) {
-            // phase 0 window: blocks b, b + 1; phase 1 window: lane groups 0, 1
-            // take blocks b + 1, b + 2, groups 2, 3 blocks b, b + 1 (formed here
-            // rather than kept across the spatial terms, to save registers)
+            // phase 0 window: blocks b, b + 1
             const uint4 w0h = make_uint4(Uh[2 * b], Uh[2 * b + 1], Uh[2 * b + 2], Uh[2 * b + 3]);
             const uint4 w0l = make_uint4(Ul[2 * b], Ul[2 * b + 1], Ul[2 * b + 2], Ul[2 * b + 3]);
-            const uint4 w1h = make_uint4(sz_sel_low(Uh[2 * b + 2], Uh[2 * b]), sz_sel_low(Uh[2 * b + 3], Uh[2 * b + 1]),
-                                         sz_sel_low(Uh[2 * b + 4], Uh[2 * b + 2]), sz_sel_low(Uh[2 * b + 5], Uh[2 * b + 3]));
-            const uint4 w1l = make_uint4(sz_sel_low(Ul[2 * b + 2], Ul[2 * b]), sz_sel_low(Ul[2 * b + 3], Ul[2 * b + 1]),
-                                         sz_sel_low(Ul[2 * b + 4], Ul[2 * b + 2]), sz_sel_low(Ul[2 * b + 5], Ul[2 * b + 3]));
             Z[mp][2 * b] = sz_mfma<FP16>(za[0][0], w0h, Z[mp][2 * b]);
-            Z[mp][2 * b + 1] = sz_mfma<FP16>(za[1][0], w1h, Z[mp][2 * b + 1]);
+            Z[mp][2 * b + 1] = sz_mfma<FP16>(za[1][0], w1h[b], Z[mp][2 * b + 1]);
             if (NT >= 2) {
                 Z[mp][2 * b] = sz_mfma<FP16>(za[0][0], w0l, Z[mp][2 * b]);
-                Z[mp][2 * b + 1] = sz_mfma<FP16>(za[1][0], w1l, Z[mp][2 * b + 1]);
+                Z[mp][2 * b + 1] = sz_mfma<FP16>(za[1][0], w1l[b], Z[mp][2 * b + 1]);
             }
             if (NT >= 3) {
                 Z[mp][2 * b] = sz_mfma<FP16>(za[0][1], w0h, Z[mp][2 * b]);
-                Z[mp][2 * b + 1] = sz_mfma<FP16>(za[1][1], w1h, Z[mp][2 * b + 1]);
+                Z[mp][2 * b + 1] = sz_mfma<FP16>(za[1][1], w1h[b], Z[mp][2 * b + 1]);
             }
         }
     }
@@ -410,7 +425,9 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
     const int G = gridDim.x;
     // data offset of the second 8-column group's reduction entries in this lane
     const int off1 = g4 == 0 ? 32 : 8 * g4;
-    const uint16_t* xrow = xs + j16 * SZ_P + 16 * w;   // this lane's staged row in block 0, strip start
+    // this lane's staged row in block 0 at the strip start, as an LDS-space
+    // pointer so that the row loads stay LDS loads through the asm barrier below
+    const lds_u16 xrow = (lds_u16)(xs + j16 * SZ_P + 16 * w);
     // this wave's area for the second factor's row responses: [SZ_RB][64 lanes] uint4
     uint4* ubw = sz_lds + SZ_XLDS / 16 + (size_t)w * SZ_RB * 64 + lane;
     const int n_pairs = (a.R + 1) / 2;
@@ -438,7 +455,7 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
         for (int pp = 0; pp < n_pairs; ++pp) {
             // the staged rows are re-read for every pair rather than held in
             // registers across the loop (they would cost 48 registers per lane)
-            const uint16_t* xr = xrow;
+            lds_u16 xr = xrow;
             asm volatile("" : "+v"(xr));
             // ---- row pass: two row factors x two 8-column groups, 6 row blocks
             uint4 tb[2][2];
@@ -461,11 +478,11 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
 #pragma unroll
                 for (int q = 0; q < SZ_RG; ++q) {
                     if (r2 + q >= SZ_RB) continue;
-                    const uint16_t* rp = xr + (16 * (r2 + q)) * SZ_P;
-                    dh[q][0] = *reinterpret_cast<const uint4*>(rp + 8 * g4);
-                    dl[q][0] = *reinterpret_cast<const uint4*>(rp + SZ_XR * SZ_P + 8 * g4);
-                    dh[q][1] = *reinterpret_cast<const uint4*>(rp + off1);
-                    dl[q][1] = *reinterpret_cast<const uint4*>(rp + SZ_XR * SZ_P + off1);
+                    const lds_u16 rp = xr + (16 * (r2 + q)) * SZ_P;
+                    dh[q][0] = sz_lds16(rp + 8 * g4);
+                    dl[q][0] = sz_lds16(rp + SZ_XR * SZ_P + 8 * g4);
+                    dh[q][1] = sz_lds16(rp + off1);
+                    dl[q][1] = sz_lds16(rp + SZ_XR * SZ_P + off1);
 #pragma unroll
                     for (int cg = 0; cg < 2; ++cg) acc[q][cg] = sz_f4{0.f, 0.f, 0.f, 0.f};
                 }

@@ -74,9 +74,11 @@ def test_least_squares_fit_survey_scale(svc, c4_case, precision, form):
     with svc.plan_for(wl, precision=precision, form=form, pedestal=synth.SKY_LEVEL) as plan:
         Rd, Id = to_dev(R), to_dev(I)
         a64, D, hist, t_setup = least_squares_fit(plan, Rd, Id, to_dev(a0), iters=4, timings=True)
+        a_fit = to_host(a64)
         Dh = to_host(D)
         L_fit = float(to_host(plan.loss_grad(D)[0]))
         L_true = float(to_host(plan.loss_grad(plan.difference(Rd, Id, to_dev(a_hidden)))[0]))
+        JtJ = to_host(plan.normal_matrix(Rd))
     h = wl.half_width
     rms = float(np.sqrt(np.mean(Dh[h:-h, h:-h].astype(np.float64) ** 2)) / synth.sky_sigma())
     it_s = sorted(t for _, _, t in hist)[len(hist) // 2]
@@ -88,6 +90,25 @@ def test_least_squares_fit_survey_scale(svc, c4_case, precision, form):
                                                      wl.height * wl.width / it_s / 1e6))
     assert L_fit <= L_true * (1 + 1e-6)
     assert 0.95 < rms < 1.6
+    # Recovery of the hidden coefficients.  The least-squares estimate has the
+    # error covariance (JtJ)^-1 J^T V J (JtJ)^-1 for pixel noise variances V,
+    # so its error is large along the eigenvectors of JtJ with small
+    # eigenvalues (cond(JtJ) is reported) and bounded in the JtJ norm:
+    # q = (a - a*)^T JtJ (a - a*) has expectation NM sigma^2 for white noise of
+    # variance sigma^2 (estimated by L_fit / pixels).  Poisson noise weights
+    # the bright stars more, so q is held to within a factor 10 of that.
+    ev = np.linalg.eigvalsh(JtJ)
+    da = (a_fit - a_hidden).ravel().astype(np.float64)
+    q = float(da @ JtJ @ da)
+    n_pix = (wl.height - 2 * h) * (wl.width - 2 * h)
+    q_white = da.size * L_fit / n_pix
+    say("  cond(JtJ) %.3e; max |a - a_hidden| %.3e, rms %.3e; (a - a*)^T JtJ (a - a*) = %.4e "
+        "= %.3f x the white-noise expectation %.4e; L_true - L_fit = %.4e"
+        % (ev[-1] / ev[0], np.abs(da).max(), np.sqrt(np.mean(da ** 2)), q, q / q_white, q_white,
+           L_true - L_fit))
+    assert 0.1 < q / q_white < 10
+    # the loss is quadratic with its minimum at the fit: L_true - L_fit = q
+    assert abs((L_true - L_fit) - q) <= 1e-2 * q + 1e-6 * L_true
     # float64 refinement on the normal equations: the last step is at most
     # 1e-4 of the first, at a median iteration of at most 8 ms
     assert hist[-1][1] <= 1e-4 * hist[0][1]
