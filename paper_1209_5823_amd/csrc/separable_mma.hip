@@ -79,15 +79,18 @@ __device__ __forceinline__ void smm_split(float x, uint32_t& hi, uint32_t& lo) {
     }
 }
 
-// Two values split into packed hi and lo parts.  fp16: the packed truncating
-// conversion, the lo part carrying the remainder x - hi (exact in float32);
-// bf16: rounded to nearest even one at a time.
+// Two values split into packed hi and lo parts.  fp16: hi by the packed
+// truncating conversion, lo the remainder x - hi (exact in float32) rounded to
+// nearest even by one mixed-precision FMA per value (into the low, then the
+// high half); bf16: rounded to nearest even one at a time.
 template <bool FP16>
 __device__ __forceinline__ void smm_split2(float x0, float x1, uint32_t& hi2, uint32_t& lo2) {
     if (FP16) {
-        const auto h = __builtin_amdgcn_cvt_pkrtz(x0, x1);
-        hi2 = __builtin_bit_cast(uint32_t, h);
-        lo2 = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(x0 - (float)h[0], x1 - (float)h[1]));
+        hi2 = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(x0, x1));
+        uint32_t lo;
+        asm("v_fma_mixlo_f16 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]" : "=v"(lo) : "v"(hi2), "v"(x0));
+        asm("v_fma_mixhi_f16 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "+v"(lo) : "v"(hi2), "v"(x1));
+        lo2 = lo;
     } else {
         uint32_t h0, l0, h1, l1;
         smm_split<false>(x0, h0, l0);

@@ -63,7 +63,7 @@ constexpr int SZ_MINW = 2;                // waves per SIMD the registers allow
 constexpr int SZ_RG = 2;                  // row blocks whose row-pass products are issued together
 // the next tile's loads in flight during the current tile's passes (costs the
 // registers of the loaded samples)
-constexpr bool SZ_PREFETCH = true;
+constexpr bool SZ_PREFETCH = false;
 constexpr int SZ_TH = 8 * SZ_OB;          // tile height
 constexpr int SZ_RB = SZ_OB / 2 + 2;      // 16-row blocks of row responses (16 SZ_RB >= SZ_TH + 2h for h <= 12)
 constexpr int SZ_XR = 16 * SZ_RB;         // staged rows
@@ -96,15 +96,24 @@ __device__ __forceinline__ void sz_split_tap(double v, uint16_t& hi, uint16_t& l
     }
 }
 
-// Two float32 values split into packed hi and lo parts.  fp16: the packed
-// truncating conversion, the lo part (also truncated) carrying the remainder
-// x - hi, which is exact in float32; bf16: rounded to nearest even.
+// lo parts of two float32 values whose fp16 hi parts are packed in hv:
+// (x - hi) formed exactly and rounded to fp16 (nearest even) in one
+// mixed-precision FMA per value, written into the low and the high half.
+__device__ __forceinline__ uint32_t sz_lo2_f16(uint32_t hv, float x0, float x1) {
+    uint32_t lo;
+    asm("v_fma_mixlo_f16 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]" : "=v"(lo) : "v"(hv), "v"(x0));
+    asm("v_fma_mixhi_f16 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "+v"(lo) : "v"(hv), "v"(x1));
+    return lo;
+}
+
+// Two float32 values split into packed hi and lo parts.  fp16: hi by the
+// packed truncating conversion, lo the remainder x - hi (exact in float32)
+// rounded to nearest even; bf16: both rounded to nearest even.
 template <bool FP16>
 __device__ __forceinline__ void sz_split2(float x0, float x1, uint32_t& hi2, uint32_t& lo2) {
     if (FP16) {
-        const auto hv = __builtin_amdgcn_cvt_pkrtz(x0, x1);
-        hi2 = __builtin_bit_cast(uint32_t, hv);
-        lo2 = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(x0 - (float)hv[0], x1 - (float)hv[1]));
+        hi2 = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(x0, x1));
+        lo2 = sz_lo2_f16(hi2, x0, x1);
     } else {
         const uint32_t h0 = sz_f2bf(x0), h1 = sz_f2bf(x1);
         const uint32_t l0 = sz_f2bf(x0 - sz_bf2f(h0)), l1 = sz_f2bf(x1 - sz_bf2f(h1));
@@ -319,17 +328,24 @@ __device__ __forceinline__ uint32_t sz_sel_low(uint32_t lo, uint32_t hi) {
     return (uint32_t)__builtin_amdgcn_update_dpp((int)hi, (int)lo, 0xe4, 0x3, 0xf, false);
 }
 
-// Column passes of one row factor r: Z[s][ob] += g_{r, 2 mp + s} (x)_y U_r for
-// the 8 output blocks of 8 rows (ob = 2 b: rows 16 b.., phase 0; ob = 2 b + 1:
-// rows 16 b + 8.., phase 1).  Uh / Ul: the lane's row responses, two packed
-// registers per 16-row block; zt: the factor's column-pass fragments.
-template <bool FP16, int NT, int MP>
-__device__ __forceinline__ void sz_colpass(sz_f4 (&Z)[MP][SZ_OB], const uint32_t (&Uh)[2 * SZ_RB],
-                                           const uint32_t (&Ul)[2 * SZ_RB], const uint16_t* __restrict__ zt,
-                                           int lane) {
-    // phase 1 windows: block b + 1, then block b + 2 (lane groups 0, 1) or
-    // block b (groups 2, 3); formed once for every spatial term
-    uint4 w1h[SZ_OB / 2], w1l[SZ_OB / 2];
+// One table entry (a row-pass pair or a column-pass spatial-term pair) for
+// this lane: [cg or phase][hi/lo], 16 bytes each.
+__device__ __forceinline__ void sz_load_tab(const uint16_t* __restrict__ tab, int lane, uint4 (&t)[2][2]) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int hl = 0; hl < 2; ++hl)
+            t[c][hl] = *reinterpret_cast<const uint4*>(tab + ((c * 2 + hl) * 64 + lane) * 8);
+    // keep the loads where they are issued: the scheduler would otherwise sink
+    // them next to their use and expose the L2 latency
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// Phase 1 column windows of one row factor, formed once for every spatial
+// term: block b + 1, then block b + 2 (lane groups 0, 1) or block b (groups
+// 2, 3).
+__device__ __forceinline__ void sz_phase1_windows(const uint32_t (&Uh)[2 * SZ_RB], const uint32_t (&Ul)[2 * SZ_RB],
+                                                  uint4 (&w1h)[SZ_OB / 2], uint4 (&w1l)[SZ_OB / 2]) {
 #pragma unroll
     for (int b = 0; b < SZ_OB / 2; ++b) {
         w1h[b] = make_uint4(Uh[2 * b + 2], Uh[2 * b + 3], sz_sel_low(Uh[2 * b + 4], Uh[2 * b]),
@@ -337,29 +353,32 @@ __device__ __forceinline__ void sz_colpass(sz_f4 (&Z)[MP][SZ_OB], const uint32_t
         w1l[b] = make_uint4(Ul[2 * b + 2], Ul[2 * b + 3], sz_sel_low(Ul[2 * b + 4], Ul[2 * b]),
                             sz_sel_low(Ul[2 * b + 5], Ul[2 * b + 1]));
     }
+}
+
+// Column passes of one row factor r for spatial terms 2 mp, 2 mp + 1:
+// Z[s][ob] += g_{r, 2 mp + s} (x)_y U_r for the output blocks of 8 rows
+// (ob = 2 b: rows 16 b.., phase 0, window blocks b, b + 1; ob = 2 b + 1:
+// rows 16 b + 8.., phase 1, window block b + 1, then block b + 2 in lane
+// groups 0, 1 or block b in groups 2, 3).  Uh / Ul: the lane's row responses,
+// two packed registers per 16-row block; za: the fragments [phase][hi/lo].
+template <bool FP16, int NT>
+__device__ __forceinline__ void sz_colpass(sz_f4 (&Z)[SZ_OB], const uint32_t (&Uh)[2 * SZ_RB],
+                                           const uint32_t (&Ul)[2 * SZ_RB], const uint4 (&W1h)[SZ_OB / 2],
+                                           const uint4 (&W1l)[SZ_OB / 2], const uint4 (&za)[2][2]) {
 #pragma unroll
-    for (int mp = 0; mp < MP; ++mp) {
-        uint4 za[2][2];   // [phase][hi/lo]
-#pragma unroll
-        for (int ph = 0; ph < 2; ++ph)
-#pragma unroll
-            for (int hl = 0; hl < 2; ++hl)
-                za[ph][hl] = *reinterpret_cast<const uint4*>(zt + (size_t)mp * SZ_FRAG + ((ph * 2 + hl) * 64 + lane) * 8);
-#pragma unroll
-        for (int b = 0; b < SZ_OB / 2; ++b) {
-            // phase 0 window: blocks b, b + 1
-            const uint4 w0h = make_uint4(Uh[2 * b], Uh[2 * b + 1], Uh[2 * b + 2], Uh[2 * b + 3]);
-            const uint4 w0l = make_uint4(Ul[2 * b], Ul[2 * b + 1], Ul[2 * b + 2], Ul[2 * b + 3]);
-            Z[mp][2 * b] = sz_mfma<FP16>(za[0][0], w0h, Z[mp][2 * b]);
-            Z[mp][2 * b + 1] = sz_mfma<FP16>(za[1][0], w1h[b], Z[mp][2 * b + 1]);
-            if (NT >= 2) {
-                Z[mp][2 * b] = sz_mfma<FP16>(za[0][0], w0l, Z[mp][2 * b]);
-                Z[mp][2 * b + 1] = sz_mfma<FP16>(za[1][0], w1l[b], Z[mp][2 * b + 1]);
-            }
-            if (NT >= 3) {
-                Z[mp][2 * b] = sz_mfma<FP16>(za[0][1], w0h, Z[mp][2 * b]);
-                Z[mp][2 * b + 1] = sz_mfma<FP16>(za[1][1], w1h[b], Z[mp][2 * b + 1]);
-            }
+    for (int b = 0; b < SZ_OB / 2; ++b) {
+        const uint4 w0h = make_uint4(Uh[2 * b], Uh[2 * b + 1], Uh[2 * b + 2], Uh[2 * b + 3]);
+        const uint4 w0l = make_uint4(Ul[2 * b], Ul[2 * b + 1], Ul[2 * b + 2], Ul[2 * b + 3]);
+        const uint4 w1h = W1h[b], w1l = W1l[b];
+        Z[2 * b] = sz_mfma<FP16>(za[0][0], w0h, Z[2 * b]);
+        Z[2 * b + 1] = sz_mfma<FP16>(za[1][0], w1h, Z[2 * b + 1]);
+        if (NT >= 2) {
+            Z[2 * b] = sz_mfma<FP16>(za[0][0], w0l, Z[2 * b]);
+            Z[2 * b + 1] = sz_mfma<FP16>(za[1][0], w1l, Z[2 * b + 1]);
+        }
+        if (NT >= 3) {
+            Z[2 * b] = sz_mfma<FP16>(za[0][1], w0h, Z[2 * b]);
+            Z[2 * b + 1] = sz_mfma<FP16>(za[1][1], w1h, Z[2 * b + 1]);
         }
     }
 }
@@ -372,17 +391,24 @@ __device__ __forceinline__ void sz_load_tile(const SepZArgs& a, int t, int tid, 
     const int h = a.h;
     const int X0 = (t % a.tiles_x) * SZ_TW, Y0 = a.y_begin + (t / a.tiles_x) * SZ_TH;
     const int RA = SZ_TH + 2 * h, CA = SZ_TW + 2 * h;
+    // the per-thread indices are formed anew for every tile rather than kept
+    // in registers across the tile loop
+    int t0 = tid;
+    asm volatile("" : "+v"(t0));
+    // every load reads a clamped, in-image address and is then masked, so the
+    // loop has no branches
 #pragma unroll
     for (int i = 0; i < SITER; ++i) {
-        const int q = tid + i * SZ_NT;
+        const int q = t0 + i * SZ_NT;
         const int r = q / (SZ_XC / 2), c = 2 * (q - r * (SZ_XC / 2));
         const int gy = Y0 - h + r, gx = X0 - h + c;
-        sv[i][0] = 0.f;
-        sv[i][1] = 0.f;
-        if (q < SZ_XR * (SZ_XC / 2) && r < RA && gy >= 0 && gy < a.H) {
-            const float* src = a.X + (size_t)gy * a.W;
-            if (c < CA && gx >= 0 && gx < a.W) sv[i][0] = src[gx];
-            if (c + 1 < CA && gx + 1 >= 0 && gx + 1 < a.W) sv[i][1] = src[gx + 1];
+        const bool rok = q < SZ_XR * (SZ_XC / 2) && r < RA && gy >= 0 && gy < a.H;
+        const float* src = a.X + (size_t)min(max(gy, 0), a.H - 1) * a.W;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int x = gx + e;
+            const float v = src[min(max(x, 0), a.W - 1)];
+            sv[i][e] = (rok && c + e < CA && x >= 0 && x < a.W) ? v : 0.f;
         }
     }
 }
@@ -394,9 +420,11 @@ __device__ __forceinline__ void sz_store_tile(const SepZArgs& a, int tid, const 
                                               uint16_t* xs) {
     const float xscale = FP16 ? 0.25f : 1.f;
     const int RA = SZ_TH + 2 * a.h, CA = SZ_TW + 2 * a.h;
+    int t0 = tid;
+    asm volatile("" : "+v"(t0));
 #pragma unroll
     for (int i = 0; i < SITER; ++i) {
-        const int q = tid + i * SZ_NT;
+        const int q = t0 + i * SZ_NT;
         if (q < SZ_XR * (SZ_XC / 2)) {
             const int r = q / (SZ_XC / 2), c = 2 * (q - r * (SZ_XC / 2));
             float v[2];
@@ -432,6 +460,14 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
     uint4* ubw = sz_lds + SZ_XLDS / 16 + (size_t)w * SZ_RB * 64 + lane;
     const int n_pairs = (a.R + 1) / 2;
 
+    // The tap tables are read one stage ahead: a stage is the row pass of a
+    // pair of row factors or the column passes of one row factor for one pair
+    // of spatial terms, and the next stage's entry is loaded into `nxt` while
+    // the current one computes (the tables are read from L2).  The stage after
+    // a tile's last is the first one of the next tile.
+    uint4 cur[2][2], nxt[2][2];
+    sz_load_tab(a.rtab, lane, cur);
+
     float sv[SITER][2];
     int it = blockIdx.x;
     if (it < a.n_tiles) {
@@ -453,20 +489,18 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
             for (int b = 0; b < SZ_OB; ++b) Z[s][b] = sz_f4{0.f, 0.f, 0.f, 0.f};
 
         for (int pp = 0; pp < n_pairs; ++pp) {
+            const bool has_b = 2 * pp + 1 < a.R;
+            const uint16_t* ztA = a.ztab + (size_t)(2 * pp) * 3 * SZ_FRAG;
+            const uint16_t* ztB = ztA + 3 * SZ_FRAG;
+            // the entry after the last column stage of this pair: the next pair's
+            // row-pass entry (the first one again after the last pair)
+            const uint16_t* rnext = a.rtab + (size_t)(pp + 1 < n_pairs ? pp + 1 : 0) * SZ_FRAG;
+            sz_load_tab(ztA, lane, nxt);
             // the staged rows are re-read for every pair rather than held in
             // registers across the loop (they would cost 48 registers per lane)
             lds_u16 xr = xrow;
             asm volatile("" : "+v"(xr));
             // ---- row pass: two row factors x two 8-column groups, 6 row blocks
-            uint4 tb[2][2];
-            {
-                const uint16_t* rt = a.rtab + (size_t)pp * SZ_FRAG;
-#pragma unroll
-                for (int cg = 0; cg < 2; ++cg)
-#pragma unroll
-                    for (int hl = 0; hl < 2; ++hl)
-                        tb[cg][hl] = *reinterpret_cast<const uint4*>(rt + ((cg * 2 + hl) * 64 + lane) * 8);
-            }
             uint32_t UAh[2 * SZ_RB], UAl[2 * SZ_RB];
 #pragma unroll
             for (int r2 = 0; r2 < SZ_RB; r2 += SZ_RG) {
@@ -490,19 +524,19 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
                 for (int cg = 0; cg < 2; ++cg)
 #pragma unroll
                     for (int q = 0; q < SZ_RG; ++q)
-                        if (r2 + q < SZ_RB) acc[q][cg] = sz_mfma<FP16>(dh[q][cg], tb[cg][0], acc[q][cg]);
+                        if (r2 + q < SZ_RB) acc[q][cg] = sz_mfma<FP16>(dh[q][cg], cur[cg][0], acc[q][cg]);
                 if (NT >= 2)
 #pragma unroll
                     for (int cg = 0; cg < 2; ++cg)
 #pragma unroll
                         for (int q = 0; q < SZ_RG; ++q)
-                            if (r2 + q < SZ_RB) acc[q][cg] = sz_mfma<FP16>(dl[q][cg], tb[cg][0], acc[q][cg]);
+                            if (r2 + q < SZ_RB) acc[q][cg] = sz_mfma<FP16>(dl[q][cg], cur[cg][0], acc[q][cg]);
                 if (NT >= 3)
 #pragma unroll
                     for (int cg = 0; cg < 2; ++cg)
 #pragma unroll
                         for (int q = 0; q < SZ_RG; ++q)
-                            if (r2 + q < SZ_RB) acc[q][cg] = sz_mfma<FP16>(dh[q][cg], tb[cg][1], acc[q][cg]);
+                            if (r2 + q < SZ_RB) acc[q][cg] = sz_mfma<FP16>(dh[q][cg], cur[cg][1], acc[q][cg]);
                 // split, then move the two factors into the 16-column layout: factor A
                 // holds lanes 0..7 of group 0 and (rotated) lanes 0..7 of group 1,
                 // factor B (rotated) lanes 8..15 of group 0 and lanes 8..15 of group 1;
@@ -527,8 +561,20 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
             }
 
             // ---- column passes: Z[s][ob] += g_{r, 2 mp + s} (x)_y U_r for both factors
-            sz_colpass<FP16, NT, MP>(Z, UAh, UAl, a.ztab + (size_t)(2 * pp) * 3 * SZ_FRAG, lane);
-            if (2 * pp + 1 < a.R) {
+            {
+                uint4 w1h[SZ_OB / 2], w1l[SZ_OB / 2];
+                sz_phase1_windows(UAh, UAl, w1h, w1l);
+#pragma unroll
+                for (int mp = 0; mp < MP; ++mp) {
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+#pragma unroll
+                        for (int hl = 0; hl < 2; ++hl) cur[c][hl] = nxt[c][hl];
+                    sz_load_tab(mp + 1 < MP ? ztA + (size_t)(mp + 1) * SZ_FRAG : (has_b ? ztB : rnext), lane, nxt);
+                    sz_colpass<FP16, NT>(Z[mp], UAh, UAl, w1h, w1l, cur);
+                }
+            }
+            if (has_b) {
                 uint32_t UBh[2 * SZ_RB], UBl[2 * SZ_RB];
 #pragma unroll
                 for (int rb = 0; rb < SZ_RB; ++rb) {
@@ -538,8 +584,22 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
                     UBl[2 * rb] = v.z;
                     UBl[2 * rb + 1] = v.w;
                 }
-                sz_colpass<FP16, NT, MP>(Z, UBh, UBl, a.ztab + (size_t)(2 * pp + 1) * 3 * SZ_FRAG, lane);
+                uint4 w1h[SZ_OB / 2], w1l[SZ_OB / 2];
+                sz_phase1_windows(UBh, UBl, w1h, w1l);
+#pragma unroll
+                for (int mp = 0; mp < MP; ++mp) {
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+#pragma unroll
+                        for (int hl = 0; hl < 2; ++hl) cur[c][hl] = nxt[c][hl];
+                    sz_load_tab(mp + 1 < MP ? ztB + (size_t)(mp + 1) * SZ_FRAG : rnext, lane, nxt);
+                    sz_colpass<FP16, NT>(Z[mp], UBh, UBl, w1h, w1l, cur);
+                }
             }
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int hl = 0; hl < 2; ++hl) cur[c][hl] = nxt[c][hl];
         }
 
         // ---- epilogue.  Lane (g4, j16) holds Z_m, m = 2 mp + g4 / 2, at rows
@@ -589,10 +649,13 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
                 fin[q][e] = (lowg ? part[q][e] : part[q + HB][e]) + recv;
             }
         if (x < a.W) {
-            // pedestal restore s sum_m gamma_m P_m (float64), then D = sum_m P_m Z_m - I
-            double xpow[3] = {1.0, xh, xh * xh};
-            double cy[3];
-            coef_in_x<2>(as_const(a.gam), xpow, cy);
+            // D = sum_m P_m Z_m - I + s sum_m gamma_m P_m (the pedestal restore),
+            // in float32: sum_m P_m Z_m - I is exact where both are large (they
+            // agree to a factor 2), and the rest is of the sky's size
+            const cptr<double> gam = as_const(a.gam);
+            const float cy0 = fmaf(fmaf((float)gam[3], xf, (float)gam[1]), xf, (float)gam[0]);
+            const float cy1 = fmaf((float)gam[4], xf, (float)gam[2]);
+            const float cy2 = (float)gam[5];
 #pragma unroll
             for (int q = 0; q < HB; ++q)
 #pragma unroll
@@ -600,11 +663,11 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
                     const int ob = q + (lowg ? 0 : HB);
                     const int y = Y0 + 8 * ob + 4 * (g4 & 1) + e;
                     if (y < y_end) {
-                        const double yh = a.sy * y + a.oy;
-                        const double pg = fma(fma(cy[2], yh, cy[1]), yh, cy[0]);
+                        const float yf = fmaf((float)a.sy, (float)y, (float)a.oy);
+                        const float pg = fmaf(fmaf(cy2, yf, cy1), yf, cy0);
                         const size_t idx = (size_t)y * a.W + x;
-                        const double iv = a.I ? (double)a.I[idx] : 0.0;
-                        a.out[idx] = (float)(fma((double)a.ped, pg, (double)fin[q][e]) - iv);
+                        const float iv = a.I ? a.I[idx] : 0.f;
+                        a.out[idx] = fmaf(a.ped, pg, fin[q][e] - iv);
                     }
                 }
         }
