@@ -80,6 +80,9 @@ def main():
                     help="skip the Dirac delta basis size sweep")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="skip the streamed host-tile pipeline measurement")
+    ap.add_argument("--dfb-only", action="store_true",
+                    help="only time the Dirac delta basis forms on the 4846 x 4868 tile and "
+                         "print that sweep (for profiling the paper's own case)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (steps times), the "
                          "reference for scaling HBM byte counters")
@@ -107,6 +110,11 @@ def main():
 
     import synth
     from paper_1209_5823_amd import svconv, flops
+
+    if args.dfb_only:
+        torch.cuda.set_device(0)
+        print(json.dumps({"dfb": dfb_sweep(args, torch.cuda.Stream(), sizes=DFB_SIZES[-1:])}), flush=True)
+        return
 
     wl = synth.WORKLOADS[args.workload]
     log("inputs: %s %dx%d" % (wl.name, wl.height, wl.width))
@@ -261,12 +269,17 @@ def main():
     # of Eq. 1 exactly up to rounding); the fastest form within the FP32
     # path's 1e-4 sigma, the fastest matrix-core form and the dense FP32
     # matrix-core basis form are reported beside it
-    def ok(r, tol):
-        return ("max_err_sigma" not in r) or r["max_err_sigma"] <= tol
+    # without the oracle's sampled errors (--no-cpu) a form qualifies by the
+    # bound its parity tests hold: 1e-4 sigma for the float32 / float64 paths,
+    # 1e-2 sigma for those and the fp16x3 / bf16x3 splits
+    def ok(key, r, tol):
+        if "max_err_sigma" in r:
+            return r["max_err_sigma"] <= tol
+        return key[1] in (("fp32", "f64") if tol <= 1e-4 else ("fp32", "f64", "fp16x3", "bf16x3"))
 
     def best(tol, forms=None, precs=None):
         c = [(r["mpix"], k) for k, r in results.items()
-             if ok(r, tol) and (forms is None or k[0] in forms) and (precs is None or k[1] in precs)]
+             if ok(k, r, tol) and (forms is None or k[0] in forms) and (precs is None or k[1] in precs)]
         return max(c)[1] if c else None
 
     head = best(1e-2)
@@ -439,7 +452,7 @@ DFB_FORMS = (("regrouped", "fp32"), ("regrouped", "bf16x3"), ("regrouped", "fp16
              ("basis", "fp16x3"))
 
 
-def dfb_sweep(args, stream):
+def dfb_sweep(args, stream, sizes=DFB_SIZES):
     """The paper's own benchmark case (Sec. 3): 7 x 7 Dirac delta basis
     (49 bases, one per kernel pixel), second-order spatial polynomial, image
     sizes from 256 x 256 up to one 4846 x 4868 camera tile.  Smaller sizes are
@@ -463,7 +476,7 @@ def dfb_sweep(args, stream):
     errs = {}
     with torch.cuda.stream(stream):
         a = torch.from_numpy(a_h).cuda()
-        for (H, W) in DFB_SIZES:
+        for (H, W) in sizes:
             R = torch.from_numpy(np.ascontiguousarray(tile[:H, :W])).cuda()
             I = R.clone()
             D = torch.empty_like(R)

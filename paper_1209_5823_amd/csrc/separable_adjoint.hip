@@ -373,12 +373,8 @@ struct SepRArgs {
 #ifndef SR_WG_PER_CU
 #define SR_WG_PER_CU 4          // minimum waves per SIMD (launch bounds)
 #endif
-// At h = 15 the two column tasks of a thread, their 38-sample windows and the
-// row-pass sums do not fit 128 registers: that instance takes 3 waves per SIMD.
-constexpr int sr_waves_per_simd(int h) { return h >= 15 ? 3 : SR_WG_PER_CU; }
-
 template <int H>
-__global__ __launch_bounds__(SR_NT, sr_waves_per_simd(H)) void adjoint_r_sep_kernel(SepRArgs a) {
+__global__ __launch_bounds__(SR_NT, SR_WG_PER_CU) void adjoint_r_sep_kernel(SepRArgs a) {
     constexpr int K = 2 * H + 1;
     constexpr int RA = SR_TH + 2 * H, CA = SR_TW + 2 * H, CP = CA | 1;
     constexpr int WB = SR_RPT + 2 * H;                  // window of a column task / row task
@@ -460,14 +456,26 @@ __global__ __launch_bounds__(SR_NT, sr_waves_per_simd(H)) void adjoint_r_sep_ker
                     const int task = tid + tk * SR_NT;
                     if (task < NTASK) {
                         const int c = task % CA, r0 = (task / CA) * SR_RPT;
-                        double win[WB];
+                        // the window stays in float32 and a rolling set of
+                        // SR_RPT samples is widened to float64 as the taps
+                        // advance, which keeps the registers of wide kernels
+                        // within the occupancy target
+                        float winf[WB];
 #pragma unroll
-                        for (int s = 0; s < WB; ++s) win[s] = (double)en[(r0 + s) * CP + c];
+                        for (int s = 0; s < WB; ++s) winf[s] = en[(r0 + s) * CP + c];
+                        double roll[SR_RPT];
+#pragma unroll
+                        for (int o = 0; o < SR_RPT; ++o) roll[o] = (double)winf[o];
 #pragma unroll
                         for (int v = 0; v < K; ++v) {
                             const double fv = f[v];
 #pragma unroll
-                            for (int o = 0; o < SR_RPT; ++o) cacc[tk][o] = fma(fv, win[o + v], cacc[tk][o]);
+                            for (int o = 0; o < SR_RPT; ++o) cacc[tk][o] = fma(fv, roll[o], cacc[tk][o]);
+                            if (v + 1 < K) {
+#pragma unroll
+                                for (int o = 0; o + 1 < SR_RPT; ++o) roll[o] = roll[o + 1];
+                                roll[SR_RPT - 1] = (double)winf[v + SR_RPT];
+                            }
                         }
                     }
                 }
