@@ -570,73 +570,103 @@ int launch_cholesky(svconv_plan* p, double* A, int n) {
 }
 
 // x = L^-T L^-1 rhs by blocked substitutions in one workgroup of 1024
-// threads: per block of 32 unknowns, the contributions of the unknowns already
-// solved are summed by all threads (each row or column of L read as coalesced
-// 256-byte runs), then one wave solves the 32 x 32 triangle, broadcasting each
-// unknown across the lanes.  v holds the right-hand side, then the solution.
+// threads.  Per block of 32 unknowns, one wave solves the 32 x 32 triangle
+// (each unknown broadcast across the lanes, the diagonal's reciprocals formed
+// first); then every thread folds the block's unknowns into the right-hand
+// side entries still to be solved (right-looking): one row of the panel per
+// thread in the forward pass (32 independent loads of contiguous doubles),
+// one column per thread in the backward pass (loads coalesced across the
+// wave).  So each block waits on memory once.  v holds the right-hand side,
+// then the solution.
 constexpr int CS_B = 32;
 
 __global__ __launch_bounds__(1024) void chol_solve_kernel(const double* __restrict__ L,
                                                           const double* __restrict__ rhs,
                                                           double* __restrict__ x, int n) {
     extern __shared__ double v[];   // n doubles
-    __shared__ double part[CS_B][CS_B + 1];
-    __shared__ double psum[CS_B];
-    const int tid = threadIdx.x, r = tid >> 5, c = tid & 31;
+    const int tid = threadIdx.x;
     for (int i = tid; i < n; i += 1024) v[i] = rhs[i];
     __syncthreads();
     const int nblk = (n + CS_B - 1) / CS_B;
     // forward: L y = b
     for (int kb = 0; kb < nblk; ++kb) {
         const int j0 = kb * CS_B, nb = min(CS_B, n - j0);
-        // psum[r] = sum_{i < j0} L[j0 + r][i] y_i: 32 threads per row, then a
-        // reduction over the 32 lanes of the row
-        double sacc = 0.0;
-        if (r < nb)
-            for (int i = c; i < j0; i += CS_B) sacc = fma(L[(size_t)(j0 + r) * n + i], v[i], sacc);
-#pragma unroll
-        for (int o = 16; o > 0; o >>= 1) sacc += __shfl_xor(sacc, o, 32);
-        if (c == 0 && r < nb) psum[r] = sacc;
-        __syncthreads();
         if (tid < 64) {
-            // lane t < nb: row j0 + t of the triangle
+            // lane t < nb: row j0 + t of the triangle, loaded into registers first
             const int t = tid;
-            double acc = (t < nb) ? v[j0 + t] - psum[t] : 0.0;
-            for (int j = 0; j < nb; ++j) {
-                const double yj = __shfl(acc, j) / L[(size_t)(j0 + j) * n + j0 + j];
-                if (t > j && t < nb) acc = fma(-L[(size_t)(j0 + t) * n + j0 + j], yj, acc);
-                if (t == j) acc = yj;
+            const bool live = t < nb;
+            const double* Lt = L + (size_t)(j0 + (live ? t : 0)) * n + j0;
+            double l[CS_B];
+#pragma unroll
+            for (int j = 0; j < CS_B; ++j) l[j] = (live && j < nb) ? Lt[j] : 0.0;
+            const double inv = live ? 1.0 / Lt[t] : 0.0;
+            double acc = live ? v[j0 + t] : 0.0;
+#pragma unroll
+            for (int j = 0; j < CS_B; ++j) {
+                if (j < nb) {
+                    const double yj = __shfl(acc, j) * __shfl(inv, j);
+                    if (t > j) acc = fma(-l[j], yj, acc);
+                    if (t == j) acc = yj;
+                }
             }
-            if (t < nb) v[j0 + t] = acc;
+            if (live) v[j0 + t] = acc;
+        }
+        __syncthreads();
+        // rows below the block: v[i] -= L[i][j0 .. j0 + nb) y
+        for (int i = j0 + nb + tid; i < n; i += 1024) {
+            const double* Li = L + (size_t)i * n + j0;
+            double s = 0.0;
+            if (nb == CS_B) {
+                // a full block: the row's loads issued together
+                double l[CS_B];
+#pragma unroll
+                for (int c = 0; c < CS_B; ++c) l[c] = Li[c];
+#pragma unroll
+                for (int c = 0; c < CS_B; ++c) s = fma(l[c], v[j0 + c], s);
+            } else {
+                for (int c = 0; c < nb; ++c) s = fma(Li[c], v[j0 + c], s);
+            }
+            v[i] -= s;
         }
         __syncthreads();
     }
     // backward: L^T x = y
     for (int kb = nblk - 1; kb >= 0; --kb) {
         const int j0 = kb * CS_B, nb = min(CS_B, n - j0);
-        // part[r][c] = sum over rows i >= j0 + nb with i = j0 + nb + r (mod 32) of
-        // L[i][j0 + c] x_i: 32 consecutive columns per row read together
-        double sacc = 0.0;
-        if (c < nb)
-            for (int i = j0 + nb + r; i < n; i += CS_B) sacc = fma(L[(size_t)i * n + j0 + c], v[i], sacc);
-        part[r][c] = sacc;
-        __syncthreads();
-        if (tid < CS_B) {
-            double sum = 0.0;
-#pragma unroll 8
-            for (int rr = 0; rr < CS_B; ++rr) sum += part[rr][tid];
-            psum[tid] = sum;
+        if (tid < 64) {
+            // lane t < nb: column j0 + t of the triangle, loaded into registers first
+            const int t = tid;
+            const bool live = t < nb;
+            const double* Lc = L + (size_t)j0 * n + j0 + (live ? t : 0);
+            double l[CS_B];
+#pragma unroll
+            for (int j = 0; j < CS_B; ++j) l[j] = (live && j < nb) ? Lc[(size_t)j * n] : 0.0;
+            const double inv = live ? 1.0 / Lc[(size_t)t * n] : 0.0;
+            double acc = live ? v[j0 + t] : 0.0;
+#pragma unroll
+            for (int j = CS_B - 1; j >= 0; --j) {
+                if (j < nb) {
+                    const double xj = __shfl(acc, j) * __shfl(inv, j);
+                    if (t < j) acc = fma(-l[j], xj, acc);
+                    if (t == j) acc = xj;
+                }
+            }
+            if (live) v[j0 + t] = acc;
         }
         __syncthreads();
-        if (tid < 64) {
-            const int t = tid;
-            double acc = (t < nb) ? v[j0 + t] - psum[t] : 0.0;
-            for (int j = nb - 1; j >= 0; --j) {
-                const double xj = __shfl(acc, j) / L[(size_t)(j0 + j) * n + j0 + j];
-                if (t < j) acc = fma(-L[(size_t)(j0 + j) * n + j0 + t], xj, acc);
-                if (t == j) acc = xj;
+        // columns left of the block: v[c] -= sum_r L[j0 + r][c] x[j0 + r]
+        for (int c = tid; c < j0; c += 1024) {
+            double s = 0.0;
+            if (nb == CS_B) {
+                double l[CS_B];
+#pragma unroll
+                for (int r = 0; r < CS_B; ++r) l[r] = L[(size_t)(j0 + r) * n + c];
+#pragma unroll
+                for (int r = 0; r < CS_B; ++r) s = fma(l[r], v[j0 + r], s);
+            } else {
+                for (int r = 0; r < nb; ++r) s = fma(L[(size_t)(j0 + r) * n + c], v[j0 + r], s);
             }
-            if (t < nb) v[j0 + t] = acc;
+            v[c] -= s;
         }
         __syncthreads();
     }
