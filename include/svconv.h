@@ -85,10 +85,11 @@ enum svconv_precision {
  * is hi + lo with hi = x rounded to 16 bits and lo = (x - hi) rounded to 16
  * bits (x - hi is exact in float32).  The basis and regrouped forms and every
  * filter tap round to nearest even: |x - hi - lo| <= 2^-22 |x| (fp16) or
- * 2^-16 |x| (bf16).  The separable forms round the fp16 parts of image data
- * and row responses toward zero (one instruction for two values):
- * |x - hi - lo| < 2^-20 |x|; the adjoint in R truncates the bf16 hi part:
- * < 2^-15 |x|.  The measured errors above include these roundings. */
+ * 2^-16 |x| (bf16).  The separable forms take the fp16 hi part of image data
+ * and row responses toward zero (one instruction for two values) and round
+ * lo to nearest even: |x - hi - lo| < 2^-21 |x|; the adjoint in R truncates
+ * the bf16 hi part: < 2^-15 |x|.  The measured errors above include these
+ * roundings. */
 
 /* How the per-pixel kernel is contracted (both give D of Eq. 1 exactly, up
  * to rounding).  BASIS: N basis responses T_n = B_n (x) R, then
