@@ -5,10 +5,16 @@
 Every csrc/*.hip is compiled to an object under _build/ (in parallel), then
 linked into paper_1209_5823_amd/libsvconv.so.  Importing the package loads
 that library; nothing is compiled at import time.
+
+The compiler's resource-usage report of every kernel is checked: a kernel
+that spills registers to scratch memory fails the build, and the report is
+kept in _build/resource_usage.json.
 """
 
 import concurrent.futures
+import json
 import os
+import re
 import subprocess
 import sys
 
@@ -41,15 +47,38 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
+def _resource_usage(stderr):
+    """{kernel: {"vgprs", "agprs", "scratch", "lds"}} from the resource-usage remarks."""
+    usage, name = {}, None
+    for line in stderr.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+            usage[name] = {}
+            continue
+        for key, pat in (("vgprs", r" VGPRs: (\d+)"), ("agprs", r" AGPRs: (\d+)"),
+                         ("scratch", r"ScratchSize \[bytes/lane\]: (\d+)"),
+                         ("lds", r"LDS Size \[bytes/block\]: (\d+)")):
+            m = re.search(pat, line)
+            if m and name:
+                usage[name][key] = int(m.group(1))
+    return usage
+
+
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + FLAGS + FILE_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj]
+    cmd = ([HIPCC] + FLAGS + FILE_FLAGS.get(os.path.basename(src), [])
+           + ["-Rpass-analysis=kernel-resource-usage", "-c", src, "-o", obj])
     r = subprocess.run(cmd, capture_output=True, text=True)
-    # the host pass does not know the packed-fp32 feature; that warning is expected
-    err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
+    usage = _resource_usage(r.stderr)
+    # the host pass does not know the packed-fp32 feature; that warning is
+    # expected, and the resource-usage remarks are parsed, not shown
+    err = "\n".join(l for l in r.stderr.splitlines()
+                    if "packed-fp32-ops" not in l and "kernel-resource-usage" not in l
+                    and not re.match(r"\s*\d+ \|", l) and not re.match(r"\s*\|\s*\^", l))
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s" % (src, err))
-    return obj, err
+    return obj, err, usage
 
 
 def build(verbose=True):
@@ -60,11 +89,18 @@ def build(verbose=True):
     srcs = sources()
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         results = list(ex.map(_compile, srcs))
-    for obj, err in results:
+    usage = {}
+    for obj, err, u in results:
         if err.strip() and verbose:
             print(err, file=sys.stderr)
+        usage.update(u)
+    with open(os.path.join(BUILD, "resource_usage.json"), "w") as f:
+        json.dump(usage, f, indent=1, sort_keys=True)
+    spills = {k: v["scratch"] for k, v in usage.items() if v.get("scratch", 0) > 0}
+    if spills:
+        raise RuntimeError("kernels spill registers to scratch memory (bytes per lane): %s" % spills)
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + [o for o, _ in results]
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + [o for o, _, _ in results]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stderr)

@@ -163,3 +163,17 @@ def test_noalloc_rejects_before_any_device_call(lib, kw, status):
                                        ctypes.c_void_p(32), None)
     assert rc == status
     assert lib.svconv_last_error().decode() != ""
+
+
+def test_build_reports_no_register_spills():
+    # build() records the compiler's resource-usage report of every kernel and
+    # fails on a spill; the report of the library in this tree must show none
+    import json
+    path = os.path.join(ROOT, "_build", "resource_usage.json")
+    if not os.path.exists(path):
+        pytest.skip("no resource-usage report: the library was not built in this tree")
+    with open(path) as f:
+        usage = json.load(f)
+    assert len(usage) > 100
+    spills = {k: v["scratch"] for k, v in usage.items() if v.get("scratch", 0)}
+    assert not spills, spills
