@@ -37,15 +37,16 @@
 // data R - s (scaled by 1/4 in fp16), of the row responses and of both tap
 // tables (Fh xh + Fh xl + Fl xh).  Each spatial term's column taps are scaled
 // by a power of two (largest |tap| in [1, 2)), undone in the epilogue; the
-// pedestal restore s sum_m gamma_m P_m and the subtraction of I in float64.
+// pedestal restore s sum_m gamma_m P_m and the subtraction of I in float32
+// (sum_m P_m Z_m - I first, which is exact where both are large).
 //
-// Workgroup: 4 waves; output tile 64 x 48; wave w owns the 16-column strip
+// Workgroup: 4 waves; output tile 64 x 64; wave w owns the 16-column strip
 // w and every row of the tile.  LDS holds the staged tile (hi / lo rows
-// [80][88]) and, per wave, the second factor's row responses while the
+// [96][88]) and, per wave, the second factor's row responses while the
 // first one's column passes run (written and read by the same lanes, so no
-// barrier).  Workgroups are persistent, two per compute unit: the loads of
-// the next tile are issued before the current tile's passes and staged after
-// them, so the only barriers are the ends of staging.
+// barrier).  Workgroups are persistent, two per compute unit (the chip's
+// 2048 tiles fall evenly on 512 workgroups); the only barriers are the ends
+// of staging.
 #include "internal.hpp"
 #include "sep_fold.hpp"
 
@@ -58,7 +59,7 @@ typedef __bf16 sz_b8 __attribute__((ext_vector_type(8)));
 constexpr int SZ_NW = 4;                  // waves per workgroup (16-column strips)
 constexpr int SZ_NT = 64 * SZ_NW;
 constexpr int SZ_TW = 16 * SZ_NW;         // tile width
-constexpr int SZ_OB = 6;                  // 8-row output blocks of a strip (even)
+constexpr int SZ_OB = 8;                  // 8-row output blocks of a strip (even)
 constexpr int SZ_MINW = 2;                // waves per SIMD the registers allow
 constexpr int SZ_RG = 2;                  // row blocks whose row-pass products are issued together
 // the next tile's loads in flight during the current tile's passes (costs the
@@ -462,9 +463,10 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
 
     // The tap tables are read one stage ahead: a stage is the row pass of a
     // pair of row factors or the column passes of one row factor for one pair
-    // of spatial terms, and the next stage's entry is loaded into `nxt` while
-    // the current one computes (the tables are read from L2).  The stage after
-    // a tile's last is the first one of the next tile.
+    // of spatial terms, and the next stage's entry is requested into `nxt`
+    // once the current stage's products are issued, so its latency overlaps
+    // their execution (the tables are read from L2).  The stage after a
+    // tile's last is the first one of the next tile.
     uint4 cur[2][2], nxt[2][2];
     sz_load_tab(a.rtab, lane, cur);
 
@@ -570,8 +572,8 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
                     for (int c = 0; c < 2; ++c)
 #pragma unroll
                         for (int hl = 0; hl < 2; ++hl) cur[c][hl] = nxt[c][hl];
-                    sz_load_tab(mp + 1 < MP ? ztA + (size_t)(mp + 1) * SZ_FRAG : (has_b ? ztB : rnext), lane, nxt);
                     sz_colpass<FP16, NT>(Z[mp], UAh, UAl, w1h, w1l, cur);
+                    sz_load_tab(mp + 1 < MP ? ztA + (size_t)(mp + 1) * SZ_FRAG : (has_b ? ztB : rnext), lane, nxt);
                 }
             }
             if (has_b) {
@@ -592,8 +594,8 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
                     for (int c = 0; c < 2; ++c)
 #pragma unroll
                         for (int hl = 0; hl < 2; ++hl) cur[c][hl] = nxt[c][hl];
-                    sz_load_tab(mp + 1 < MP ? ztB + (size_t)(mp + 1) * SZ_FRAG : rnext, lane, nxt);
                     sz_colpass<FP16, NT>(Z[mp], UBh, UBl, w1h, w1l, cur);
+                    sz_load_tab(mp + 1 < MP ? ztB + (size_t)(mp + 1) * SZ_FRAG : rnext, lane, nxt);
                 }
             }
 #pragma unroll

@@ -100,7 +100,7 @@ def separable_regrouped_flops_per_pixel(degrees, M, k):
     return 2 * n_factors * k + 2 * n_factors * M * k + 2 * M + 1
 
 
-def separable_regrouped_executed_flops_per_pixel(degrees, M, passes, tile_rows=48, row_blocks=5):
+def separable_regrouped_executed_flops_per_pixel(degrees, M, passes, tile_rows=64, row_blocks=6):
     """Matrix-core FLOP issued per output pixel by the regrouped separable
     kernel: per 16-column strip of `tile_rows` rows, the row pass takes
     `row_blocks` 16-row blocks x 2 eight-column groups per pair of row factors
