@@ -502,65 +502,55 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
             // registers across the loop (they would cost 48 registers per lane)
             lds_u16 xr = xrow;
             asm volatile("" : "+v"(xr));
-            // ---- row pass: two row factors x two 8-column groups, 6 row blocks
+            // ---- row pass: two row factors x two 8-column groups, SZ_RB row blocks.
+            // The products of row block rb + 1 are issued before the split of
+            // block rb, so the vector work of one block overlaps the matrix-core
+            // work of the next.
             uint32_t UAh[2 * SZ_RB], UAl[2 * SZ_RB];
+            sz_f4 acc[2][2];   // [rb parity][cg]
+            auto issue = [&](int rb, sz_f4 (&ac)[2]) {
+                // the second 8-column group reuses the samples of lane groups 1..3
+                // and reads samples 32..39 in lane group 0
+                const lds_u16 rp = xr + (16 * rb) * SZ_P;
+                uint4 dh[2], dl[2];
+                dh[0] = sz_lds16(rp + 8 * g4);
+                dl[0] = sz_lds16(rp + SZ_XR * SZ_P + 8 * g4);
+                dh[1] = sz_lds16(rp + off1);
+                dl[1] = sz_lds16(rp + SZ_XR * SZ_P + off1);
 #pragma unroll
-            for (int r2 = 0; r2 < SZ_RB; r2 += SZ_RG) {
-                sz_f4 acc[SZ_RG][2];   // [rb][cg]
-                uint4 dh[SZ_RG][2], dl[SZ_RG][2];   // [rb][cg]
-                // the second 8-column group reuses the samples of lane groups 1..3 and
-                // reads samples 32..39 in lane group 0: one load per lane and group,
-                // from a per-lane address, so both groups' loads are in flight at once
-#pragma unroll
-                for (int q = 0; q < SZ_RG; ++q) {
-                    if (r2 + q >= SZ_RB) continue;
-                    const lds_u16 rp = xr + (16 * (r2 + q)) * SZ_P;
-                    dh[q][0] = sz_lds16(rp + 8 * g4);
-                    dl[q][0] = sz_lds16(rp + SZ_XR * SZ_P + 8 * g4);
-                    dh[q][1] = sz_lds16(rp + off1);
-                    dl[q][1] = sz_lds16(rp + SZ_XR * SZ_P + off1);
-#pragma unroll
-                    for (int cg = 0; cg < 2; ++cg) acc[q][cg] = sz_f4{0.f, 0.f, 0.f, 0.f};
-                }
-#pragma unroll
-                for (int cg = 0; cg < 2; ++cg)
-#pragma unroll
-                    for (int q = 0; q < SZ_RG; ++q)
-                        if (r2 + q < SZ_RB) acc[q][cg] = sz_mfma<FP16>(dh[q][cg], cur[cg][0], acc[q][cg]);
+                for (int cg = 0; cg < 2; ++cg) ac[cg] = sz_mfma<FP16>(dh[cg], cur[cg][0], sz_f4{0.f, 0.f, 0.f, 0.f});
                 if (NT >= 2)
 #pragma unroll
-                    for (int cg = 0; cg < 2; ++cg)
-#pragma unroll
-                        for (int q = 0; q < SZ_RG; ++q)
-                            if (r2 + q < SZ_RB) acc[q][cg] = sz_mfma<FP16>(dl[q][cg], cur[cg][0], acc[q][cg]);
+                    for (int cg = 0; cg < 2; ++cg) ac[cg] = sz_mfma<FP16>(dl[cg], cur[cg][0], ac[cg]);
                 if (NT >= 3)
 #pragma unroll
-                    for (int cg = 0; cg < 2; ++cg)
+                    for (int cg = 0; cg < 2; ++cg) ac[cg] = sz_mfma<FP16>(dh[cg], cur[cg][1], ac[cg]);
+            };
+            // split, then move the two factors into the 16-column layout: factor A
+            // holds lanes 0..7 of group 0 and (rotated) lanes 0..7 of group 1,
+            // factor B (rotated) lanes 8..15 of group 0 and lanes 8..15 of group 1;
+            // factor B waits in this wave's LDS area until its column pass
+            auto split = [&](int rb, const sz_f4 (&ac)[2]) {
+                uint32_t c0h[2], c0l[2], c1h[2], c1l[2];
+                sz_split2<FP16>(ac[0][0], ac[0][1], c0h[0], c0l[0]);
+                sz_split2<FP16>(ac[0][2], ac[0][3], c0h[1], c0l[1]);
+                sz_split2<FP16>(ac[1][0], ac[1][1], c1h[0], c1l[0]);
+                sz_split2<FP16>(ac[1][2], ac[1][3], c1h[1], c1l[1]);
 #pragma unroll
-                        for (int q = 0; q < SZ_RG; ++q)
-                            if (r2 + q < SZ_RB) acc[q][cg] = sz_mfma<FP16>(dh[q][cg], cur[cg][1], acc[q][cg]);
-                // split, then move the two factors into the 16-column layout: factor A
-                // holds lanes 0..7 of group 0 and (rotated) lanes 0..7 of group 1,
-                // factor B (rotated) lanes 8..15 of group 0 and lanes 8..15 of group 1;
-                // factor B waits in this wave's LDS area until its column pass
-#pragma unroll
-                for (int q = 0; q < SZ_RG; ++q) {
-                    const int rb = r2 + q;
-                    if (rb >= SZ_RB) continue;
-                    uint32_t c0h[2], c0l[2], c1h[2], c1l[2];
-                    sz_split2<FP16>(acc[q][0][0], acc[q][0][1], c0h[0], c0l[0]);
-                    sz_split2<FP16>(acc[q][0][2], acc[q][0][3], c0h[1], c0l[1]);
-                    sz_split2<FP16>(acc[q][1][0], acc[q][1][1], c1h[0], c1l[0]);
-                    sz_split2<FP16>(acc[q][1][2], acc[q][1][3], c1h[1], c1l[1]);
-#pragma unroll
-                    for (int e = 0; e < 2; ++e) {
-                        UAh[2 * rb + e] = sz_ror8<0xc>(c0h[e], c1h[e]);
-                        UAl[2 * rb + e] = sz_ror8<0xc>(c0l[e], c1l[e]);
-                    }
-                    ubw[rb * 64] = make_uint4(sz_ror8<0x3>(c1h[0], c0h[0]), sz_ror8<0x3>(c1h[1], c0h[1]),
-                                              sz_ror8<0x3>(c1l[0], c0l[0]), sz_ror8<0x3>(c1l[1], c0l[1]));
+                for (int e = 0; e < 2; ++e) {
+                    UAh[2 * rb + e] = sz_ror8<0xc>(c0h[e], c1h[e]);
+                    UAl[2 * rb + e] = sz_ror8<0xc>(c0l[e], c1l[e]);
                 }
+                ubw[rb * 64] = make_uint4(sz_ror8<0x3>(c1h[0], c0h[0]), sz_ror8<0x3>(c1h[1], c0h[1]),
+                                          sz_ror8<0x3>(c1l[0], c0l[0]), sz_ror8<0x3>(c1l[1], c0l[1]));
+            };
+            issue(0, acc[0]);
+#pragma unroll
+            for (int rb = 1; rb < SZ_RB; ++rb) {
+                issue(rb, acc[rb & 1]);
+                split(rb - 1, acc[(rb - 1) & 1]);
             }
+            split(SZ_RB - 1, acc[(SZ_RB - 1) & 1]);
 
             // ---- column passes: Z[s][ob] += g_{r, 2 mp + s} (x)_y U_r for both factors
             {
