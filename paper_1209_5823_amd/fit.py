@@ -14,6 +14,18 @@ import time
 import torch
 
 
+def _final_residual(plan, R, I, a64, a32, D):
+    """D at the final coefficients (with the background polynomial, when the
+    plan fits one, in the last row of a)."""
+    a32.copy_(a64.to(torch.float32))
+    N = plan.n_basis
+    if a32.shape[0] > N:
+        plan.difference(R, I, a32[:N].contiguous(), out=D)
+        plan.add_background(a32[N].contiguous(), D)
+    else:
+        plan.difference(R, I, a32, out=D)
+
+
 def gauss_newton_fit(plan, R, I, a0, iters=4, mask=None, timings=False):
     """Fit a starting from a0 (float32/64 [N][M] on the GPU).
 
@@ -33,8 +45,7 @@ def gauss_newton_fit(plan, R, I, a0, iters=4, mask=None, timings=False):
         loss, step = plan.gn_step(R, I, JtJ, a64, a32, D, mask)   # synchronises
         hist.append((loss, step, time.perf_counter() - t if timings else None))
     # residual at the final coefficients
-    a32.copy_(a64.to(torch.float32))
-    plan.difference(R, I, a32, out=D)
+    _final_residual(plan, R, I, a64, a32, D)
     return a64, D, hist, t_setup
 
 
@@ -56,8 +67,7 @@ def least_squares_fit(plan, R, I, a0, iters=3, mask=None, timings=False):
         t = time.perf_counter()
         loss, step = plan.ls_step(R, I, A, L, rhs, a64, a32, D, mask)   # synchronises
         hist.append((loss, step, time.perf_counter() - t if timings else None))
-    a32.copy_(a64.to(torch.float32))
-    plan.difference(R, I, a32, out=D)
+    _final_residual(plan, R, I, a64, a32, D)
     return a64, D, hist, t_setup
 
 
