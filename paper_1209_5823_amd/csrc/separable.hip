@@ -21,10 +21,12 @@
 // e): each pair of taps +-w costs one add, shared by all factors of a parity,
 // and one FMA per factor (fold_conv below).
 //
-// Workgroup: SEP_NW waves, output tile 64 x SEP_ROWS SEP_NW.  Phase A (row
-// pass): each task is one staged row and SEP_AOUT consecutive columns,
-// computing up to SEP_CHUNK row factors from one register window.  Phase B
-// (column pass): thread (lane x, wave w) owns column x and SEP_ROWS rows; it
+// Workgroup: SEP_NW waves, output tile 64 x (RPT SEP_NW) with RPT = SEP_ROWS
+// rows per thread (half as many in the T-only instances of kernels wider than
+// 21 taps, sep_rpt).  Phase A (row pass): each task is one staged row and
+// SEP_AOUT consecutive columns, computing up to SEP_CHUNK row factors from one
+// register window.  Phase B (column pass): thread (lane x, wave w) owns
+// column x and RPT rows; it
 // reads the column of a row response into registers once and applies every
 // column factor of that row factor, four at a time, then folds T_n + s beta_n
 // into D with c_n(x,y) = sum_m a_nm P_m.
