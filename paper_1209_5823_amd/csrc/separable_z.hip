@@ -61,7 +61,6 @@ constexpr int SZ_NT = 64 * SZ_NW;
 constexpr int SZ_TW = 16 * SZ_NW;         // tile width
 constexpr int SZ_OB = 8;                  // 8-row output blocks of a strip (even)
 constexpr int SZ_MINW = 2;                // waves per SIMD the registers allow
-constexpr int SZ_RG = 2;                  // row blocks whose row-pass products are issued together
 // the next tile's loads in flight during the current tile's passes (costs the
 // registers of the loaded samples)
 constexpr bool SZ_PREFETCH = false;
