@@ -61,9 +61,6 @@ constexpr int SZ_NT = 64 * SZ_NW;
 constexpr int SZ_TW = 16 * SZ_NW;         // tile width
 constexpr int SZ_OB = 8;                  // 8-row output blocks of a strip (even)
 constexpr int SZ_MINW = 2;                // waves per SIMD the registers allow
-// the next tile's loads in flight during the current tile's passes (costs the
-// registers of the loaded samples)
-constexpr bool SZ_PREFETCH = false;
 constexpr int SZ_TH = 8 * SZ_OB;          // tile height
 constexpr int SZ_RB = SZ_OB / 2 + 2;      // 16-row blocks of row responses (16 SZ_RB >= SZ_TH + 2h for h <= 12)
 constexpr int SZ_XR = 16 * SZ_RB;         // staged rows
@@ -384,42 +381,39 @@ __device__ __forceinline__ void sz_colpass(sz_f4 (&Z)[SZ_OB], const uint32_t (&U
 }
 
 // Loads of one tile's staged samples into registers: the pairs of columns
-// (c, c + 1) of row r for q = tid + i NT.  R = 0 outside the image; entries
-// past the halo are not needed.
+// (c, c + 1) of row r for q = tid + i NT.  Every load reads a clamped,
+// in-image address and none is conditional, so that all of them are in flight
+// together; the samples outside the image or past the halo are masked when
+// they are stored.
 template <int SITER>
 __device__ __forceinline__ void sz_load_tile(const SepZArgs& a, int t, int tid, float (&sv)[SITER][2]) {
     const int h = a.h;
     const int X0 = (t % a.tiles_x) * SZ_TW, Y0 = a.y_begin + (t / a.tiles_x) * SZ_TH;
-    const int RA = SZ_TH + 2 * h, CA = SZ_TW + 2 * h;
     // the per-thread indices are formed anew for every tile rather than kept
     // in registers across the tile loop
     int t0 = tid;
     asm volatile("" : "+v"(t0));
-    // every load reads a clamped, in-image address and is then masked, so the
-    // loop has no branches
 #pragma unroll
     for (int i = 0; i < SITER; ++i) {
         const int q = t0 + i * SZ_NT;
         const int r = q / (SZ_XC / 2), c = 2 * (q - r * (SZ_XC / 2));
         const int gy = Y0 - h + r, gx = X0 - h + c;
-        const bool rok = q < SZ_XR * (SZ_XC / 2) && r < RA && gy >= 0 && gy < a.H;
         const float* src = a.X + (size_t)min(max(gy, 0), a.H - 1) * a.W;
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int x = gx + e;
-            const float v = src[min(max(x, 0), a.W - 1)];
-            sv[i][e] = (rok && c + e < CA && x >= 0 && x < a.W) ? v : 0.f;
-        }
+        for (int e = 0; e < 2; ++e) sv[i][e] = src[min(max(gx + e, 0), a.W - 1)];
     }
 }
 
-// The loaded samples as (R - s) xscale split into hi / lo rows of the staged
-// tile; 0 past the halo (zero taps meet it).
+// The loaded samples of tile t as (R - s) xscale split into hi / lo rows of
+// the staged tile, with R = 0 outside the image; 0 past the halo (zero taps
+// meet it).
 template <bool FP16, int SITER>
-__device__ __forceinline__ void sz_store_tile(const SepZArgs& a, int tid, const float (&sv)[SITER][2],
+__device__ __forceinline__ void sz_store_tile(const SepZArgs& a, int t, int tid, const float (&sv)[SITER][2],
                                               uint16_t* xs) {
     const float xscale = FP16 ? 0.25f : 1.f;
-    const int RA = SZ_TH + 2 * a.h, CA = SZ_TW + 2 * a.h;
+    const int h = a.h;
+    const int X0 = (t % a.tiles_x) * SZ_TW, Y0 = a.y_begin + (t / a.tiles_x) * SZ_TH;
+    const int RA = SZ_TH + 2 * h, CA = SZ_TW + 2 * h;
     int t0 = tid;
     asm volatile("" : "+v"(t0));
 #pragma unroll
@@ -427,9 +421,15 @@ __device__ __forceinline__ void sz_store_tile(const SepZArgs& a, int tid, const 
         const int q = t0 + i * SZ_NT;
         if (q < SZ_XR * (SZ_XC / 2)) {
             const int r = q / (SZ_XC / 2), c = 2 * (q - r * (SZ_XC / 2));
+            const int gy = Y0 - h + r, gx = X0 - h + c;
+            const bool yin = gy >= 0 && gy < a.H;
             float v[2];
 #pragma unroll
-            for (int e = 0; e < 2; ++e) v[e] = (r < RA && c + e < CA) ? (sv[i][e] - a.ped) * xscale : 0.f;
+            for (int e = 0; e < 2; ++e) {
+                // R is 0 outside the image
+                const float x = (yin & (gx + e >= 0) & (gx + e < a.W)) ? sv[i][e] : 0.f;
+                v[e] = (r < RA && c + e < CA) ? (x - a.ped) * xscale : 0.f;
+            }
             uint32_t hi2, lo2;
             sz_split2<FP16>(v[0], v[1], hi2, lo2);
             *reinterpret_cast<uint32_t*>(xs + r * SZ_P + c) = hi2;
@@ -439,8 +439,8 @@ __device__ __forceinline__ void sz_store_tile(const SepZArgs& a, int tid, const 
 }
 
 // Persistent workgroups: workgroup b takes tiles b, b + G, b + 2G, ... (G =
-// the grid) in the XCD-aware order, and the loads of its next tile are in
-// flight while it computes the current one.
+// the grid) in the XCD-aware order; the loads of its next tile are in flight
+// during the current tile's epilogue.
 template <bool FP16, int NT, int MP>
 __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs a) {
     extern __shared__ uint4 sz_lds[];
@@ -469,11 +469,17 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
     uint4 cur[2][2], nxt[2][2];
     sz_load_tab(a.rtab, lane, cur);
 
+    // the per-call epilogue constants in LDS: zinv (zero for m >= M) and the
+    // pedestal sums gamma_m as float32
+    __shared__ float ep[16];
+    if (tid < 16) ep[tid] = tid < 6 ? (tid < a.M ? a.zinv[tid] : 0.f) : (tid >= 8 && tid < 14 ? (float)a.gam[tid - 8] : 0.f);
+
     float sv[SITER][2];
     int it = blockIdx.x;
     if (it < a.n_tiles) {
-        sz_load_tile(a, sep_xcd_remap(it, a.n_tiles), tid, sv);
-        sz_store_tile<FP16>(a, tid, sv, xs);
+        const int t = sep_xcd_remap(it, a.n_tiles);
+        sz_load_tile(a, t, tid, sv);
+        sz_store_tile<FP16>(a, t, tid, sv, xs);
     }
     __syncthreads();
     for (; it < a.n_tiles; it += G) {
@@ -481,7 +487,7 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
         const int X0 = (t % a.tiles_x) * SZ_TW;
         const int Y0 = a.y_begin + (t / a.tiles_x) * SZ_TH;
         const bool more = it + G < a.n_tiles;
-        if (SZ_PREFETCH && more) sz_load_tile(a, sep_xcd_remap(it + G, a.n_tiles), tid, sv);
+        const int tn = more ? sep_xcd_remap(it + G, a.n_tiles) : t;
 
         sz_f4 Z[MP][SZ_OB];
 #pragma unroll
@@ -594,8 +600,30 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
         }
 
         // ---- epilogue.  Lane (g4, j16) holds Z_m, m = 2 mp + g4 / 2, at rows
-        // 8 ob + 4 (g4 mod 2) + e of column j16 of its strip.
+        // 8 ob + 4 (g4 mod 2) + e of column j16 of its strip.  Lanes g4 and
+        // g4 ^ 2 hold the two halves of the same pixels: lane groups 0, 1 finish
+        // the first half of the output blocks, groups 2, 3 the second.
+        constexpr int HB = SZ_OB / 2;
+        const bool lowg = g4 < 2;
         const int x = X0 + 16 * w + j16;
+        // I at the pixels this lane finishes and the next tile's samples are
+        // requested together before the vector work below, all from clamped
+        // addresses (values past the image are loaded but never used), so that
+        // their latency overlaps it; without I, R stands in for the loads
+        float iv[HB][4];
+        {
+            const float* ip = a.I ? a.I : a.X;
+            const int xc = min(x, a.W - 1);
+#pragma unroll
+            for (int q = 0; q < HB; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int y = Y0 + 8 * (q + (lowg ? 0 : HB)) + 4 * (g4 & 1) + e;
+                    iv[q][e] = ip[(size_t)min(y, a.H - 1) * a.W + xc];
+                }
+        }
+        if (more) sz_load_tile(a, tn, tid, sv);
+
         const double xh = a.sx * x + a.ox;
         const float xf = (float)xh;
         // per-lane weights of the spatial terms: P_m Z_m = (zinv_m xh^p) yh^q Z_m
@@ -606,7 +634,7 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
             // (p, q) of term m: total degree tt, q = m - tt (tt + 1) / 2, p = tt - q
             const int tt = m >= 3 ? 2 : (m >= 1 ? 1 : 0);
             const int q = m - tt * (tt + 1) / 2, p = tt - q;
-            const float c = (m < a.M) ? a.zinv[m] * (p == 0 ? 1.f : (p == 1 ? xf : xf * xf)) : 0.f;
+            const float c = ep[m] * (p == 0 ? 1.f : (p == 1 ? xf : xf * xf));
 #pragma unroll
             for (int qq = 0; qq < 3; ++qq) wq[mp][qq] = (q == qq) ? c : 0.f;
         }
@@ -626,10 +654,6 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
                 }
                 part[ob][e] = fmaf(fmaf(v2, yf, v1), yf, v0);
             }
-        // lanes g4 and g4 ^ 2 hold the two halves of the same pixels: lane groups
-        // 0, 1 finish the first half of the output blocks, groups 2, 3 the second
-        constexpr int HB = SZ_OB / 2;
-        const bool lowg = g4 < 2;
         float fin[HB][4];
 #pragma unroll
         for (int q = 0; q < HB; ++q)
@@ -643,10 +667,10 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
             // D = sum_m P_m Z_m - I + s sum_m gamma_m P_m (the pedestal restore),
             // in float32: sum_m P_m Z_m - I is exact where both are large (they
             // agree to a factor 2), and the rest is of the sky's size
-            const cptr<double> gam = as_const(a.gam);
-            const float cy0 = fmaf(fmaf((float)gam[3], xf, (float)gam[1]), xf, (float)gam[0]);
-            const float cy1 = fmaf((float)gam[4], xf, (float)gam[2]);
-            const float cy2 = (float)gam[5];
+            const float cy0 = fmaf(fmaf(ep[8 + 3], xf, ep[8 + 1]), xf, ep[8 + 0]);
+            const float cy1 = fmaf(ep[8 + 4], xf, ep[8 + 2]);
+            const float cy2 = ep[8 + 5];
+            const bool has_i = a.I != nullptr;
 #pragma unroll
             for (int q = 0; q < HB; ++q)
 #pragma unroll
@@ -656,18 +680,15 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
                     if (y < y_end) {
                         const float yf = fmaf((float)a.sy, (float)y, (float)a.oy);
                         const float pg = fmaf(fmaf(cy2, yf, cy1), yf, cy0);
-                        const size_t idx = (size_t)y * a.W + x;
-                        const float iv = a.I ? a.I[idx] : 0.f;
-                        a.out[idx] = fmaf(a.ped, pg, fin[q][e] - iv);
+                        a.out[(size_t)y * a.W + x] = fmaf(a.ped, pg, fin[q][e] - (has_i ? iv[q][e] : 0.f));
                     }
                 }
         }
 
         // every wave is done with the staged tile: stage the next one
-        if (!SZ_PREFETCH && more) sz_load_tile(a, sep_xcd_remap(it + G, a.n_tiles), tid, sv);
         __syncthreads();
         if (more) {
-            sz_store_tile<FP16>(a, tid, sv, xs);
+            sz_store_tile<FP16>(a, tn, tid, sv, xs);
             __syncthreads();
         }
     }
