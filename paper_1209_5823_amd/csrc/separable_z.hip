@@ -380,61 +380,68 @@ __device__ __forceinline__ void sz_colpass(sz_f4 (&Z)[SZ_OB], const uint32_t (&U
     }
 }
 
-// Loads of one tile's staged samples into registers: the pairs of columns
-// (c, c + 1) of row r for q = tid + i NT.  Every load reads a clamped,
-// in-image address and none is conditional, so that all of them are in flight
-// together; the samples outside the image or past the halo are masked when
-// they are stored.
-template <int SITER>
-__device__ __forceinline__ void sz_load_tile(const SepZArgs& a, int t, int tid, float (&sv)[SITER][2]) {
+// Staging of one tile, row by row: wave w stages rows w, w + 4, ... of the
+// [SZ_XR][SZ_XC] window, lane l < SZ_XC / 2 the columns 2 l, 2 l + 1.  The row
+// is uniform across the wave, so a row's address is scalar work and a lane's
+// column offset (clamped into the image) is formed once per tile; no load is
+// conditional, so all of them are in flight together.  Samples outside the
+// image or past the halo are masked when they are stored.
+constexpr int SZ_SROWS = SZ_XR / SZ_NW;   // staged rows per wave
+
+// The samples of tile t this lane stages.
+__device__ __forceinline__ void sz_load_tile(const SepZArgs& a, int t, int w, int lane, float (&sv)[SZ_SROWS][2]) {
     const int h = a.h;
     const int X0 = (t % a.tiles_x) * SZ_TW, Y0 = a.y_begin + (t / a.tiles_x) * SZ_TH;
-    // the per-thread indices are formed anew for every tile rather than kept
-    // in registers across the tile loop
-    int t0 = tid;
-    asm volatile("" : "+v"(t0));
+    // the per-lane offsets are formed anew for every tile rather than kept in
+    // registers across the tile loop
+    asm volatile("" : "+v"(lane));
+    uint32_t xb[2];
 #pragma unroll
-    for (int i = 0; i < SITER; ++i) {
-        const int q = t0 + i * SZ_NT;
-        const int r = q / (SZ_XC / 2), c = 2 * (q - r * (SZ_XC / 2));
-        const int gy = Y0 - h + r, gx = X0 - h + c;
-        const float* src = a.X + (size_t)min(max(gy, 0), a.H - 1) * a.W;
+    for (int e = 0; e < 2; ++e) xb[e] = 4u * (uint32_t)min(max(X0 - h + 2 * min(lane, SZ_XC / 2 - 1) + e, 0), a.W - 1);
 #pragma unroll
-        for (int e = 0; e < 2; ++e) sv[i][e] = src[min(max(gx + e, 0), a.W - 1)];
+    for (int k = 0; k < SZ_SROWS; ++k) {
+        const int gy = Y0 - h + w + SZ_NW * k;
+        const char* row = reinterpret_cast<const char*>(a.X + (size_t)min(max(gy, 0), a.H - 1) * a.W);
+#pragma unroll
+        for (int e = 0; e < 2; ++e) sv[k][e] = *reinterpret_cast<const float*>(row + xb[e]);
     }
 }
 
-// The loaded samples of tile t as (R - s) xscale split into hi / lo rows of
-// the staged tile, with R = 0 outside the image; 0 past the halo (zero taps
-// meet it).
-template <bool FP16, int SITER>
-__device__ __forceinline__ void sz_store_tile(const SepZArgs& a, int t, int tid, const float (&sv)[SITER][2],
-                                              uint16_t* xs) {
+// The staged samples of tile t as (R - s) xscale split into hi / lo rows of the
+// staged tile, with R = 0 outside the image; 0 past the halo (zero taps meet
+// it).
+template <bool FP16>
+__device__ __forceinline__ void sz_store_tile(const SepZArgs& a, int t, int w, int lane,
+                                              const float (&sv)[SZ_SROWS][2], uint16_t* xs) {
+    if (lane >= SZ_XC / 2) return;
     const float xscale = FP16 ? 0.25f : 1.f;
+    const float pscaled = a.ped * xscale;
     const int h = a.h;
     const int X0 = (t % a.tiles_x) * SZ_TW, Y0 = a.y_begin + (t / a.tiles_x) * SZ_TH;
     const int RA = SZ_TH + 2 * h, CA = SZ_TW + 2 * h;
-    int t0 = tid;
-    asm volatile("" : "+v"(t0));
+    asm volatile("" : "+v"(lane));
+    const int c = 2 * lane;
+    bool cin[2], cimg[2];
 #pragma unroll
-    for (int i = 0; i < SITER; ++i) {
-        const int q = t0 + i * SZ_NT;
-        if (q < SZ_XR * (SZ_XC / 2)) {
-            const int r = q / (SZ_XC / 2), c = 2 * (q - r * (SZ_XC / 2));
-            const int gy = Y0 - h + r, gx = X0 - h + c;
-            const bool yin = gy >= 0 && gy < a.H;
-            float v[2];
+    for (int e = 0; e < 2; ++e) {
+        cin[e] = c + e < CA;
+        cimg[e] = X0 - h + c + e >= 0 && X0 - h + c + e < a.W;
+    }
+    uint16_t* dst = xs + w * SZ_P + c;
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                // R is 0 outside the image
-                const float x = (yin & (gx + e >= 0) & (gx + e < a.W)) ? sv[i][e] : 0.f;
-                v[e] = (r < RA && c + e < CA) ? (x - a.ped) * xscale : 0.f;
-            }
-            uint32_t hi2, lo2;
-            sz_split2<FP16>(v[0], v[1], hi2, lo2);
-            *reinterpret_cast<uint32_t*>(xs + r * SZ_P + c) = hi2;
-            *reinterpret_cast<uint32_t*>(xs + (SZ_XR + r) * SZ_P + c) = lo2;
+    for (int k = 0; k < SZ_SROWS; ++k) {
+        const int r = w + SZ_NW * k, gy = Y0 - h + r;
+        const bool rin = r < RA, rimg = gy >= 0 && gy < a.H;
+        float v[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const float x = (rimg && cimg[e]) ? sv[k][e] : 0.f;
+            v[e] = (rin && cin[e]) ? fmaf(x, xscale, -pscaled) : 0.f;
         }
+        uint32_t hi2, lo2;
+        sz_split2<FP16>(v[0], v[1], hi2, lo2);
+        *reinterpret_cast<uint32_t*>(dst + SZ_NW * k * SZ_P) = hi2;
+        *reinterpret_cast<uint32_t*>(dst + (SZ_XR + SZ_NW * k) * SZ_P) = lo2;
     }
 }
 
@@ -445,7 +452,6 @@ template <bool FP16, int NT, int MP>
 __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs a) {
     extern __shared__ uint4 sz_lds[];
     uint16_t* xs = reinterpret_cast<uint16_t*>(sz_lds);   // [2][SZ_XR][SZ_P]
-    constexpr int SITER = (SZ_XR * (SZ_XC / 2) + SZ_NT - 1) / SZ_NT;
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int g4 = lane >> 4, j16 = lane & 15;
@@ -474,12 +480,14 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
     __shared__ float ep[16];
     if (tid < 16) ep[tid] = tid < 6 ? (tid < a.M ? a.zinv[tid] : 0.f) : (tid >= 8 && tid < 14 ? (float)a.gam[tid - 8] : 0.f);
 
-    float sv[SITER][2];
+    // the wave index as a scalar: the staged rows are uniform across a wave
+    const int ws = __builtin_amdgcn_readfirstlane(w);
     int it = blockIdx.x;
     if (it < a.n_tiles) {
         const int t = sep_xcd_remap(it, a.n_tiles);
-        sz_load_tile(a, t, tid, sv);
-        sz_store_tile<FP16>(a, t, tid, sv, xs);
+        float sv[SZ_SROWS][2];
+        sz_load_tile(a, t, ws, lane, sv);
+        sz_store_tile<FP16>(a, t, ws, lane, sv, xs);
     }
     __syncthreads();
     for (; it < a.n_tiles; it += G) {
@@ -567,8 +575,8 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
                     for (int c = 0; c < 2; ++c)
 #pragma unroll
                         for (int hl = 0; hl < 2; ++hl) cur[c][hl] = nxt[c][hl];
-                    sz_colpass<FP16, NT>(Z[mp], UAh, UAl, w1h, w1l, cur);
                     sz_load_tab(mp + 1 < MP ? ztA + (size_t)(mp + 1) * SZ_FRAG : (has_b ? ztB : rnext), lane, nxt);
+                    sz_colpass<FP16, NT>(Z[mp], UAh, UAl, w1h, w1l, cur);
                 }
             }
             if (has_b) {
@@ -589,8 +597,8 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
                     for (int c = 0; c < 2; ++c)
 #pragma unroll
                         for (int hl = 0; hl < 2; ++hl) cur[c][hl] = nxt[c][hl];
-                    sz_colpass<FP16, NT>(Z[mp], UBh, UBl, w1h, w1l, cur);
                     sz_load_tab(mp + 1 < MP ? ztB + (size_t)(mp + 1) * SZ_FRAG : rnext, lane, nxt);
+                    sz_colpass<FP16, NT>(Z[mp], UBh, UBl, w1h, w1l, cur);
                 }
             }
 #pragma unroll
@@ -606,10 +614,10 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
         constexpr int HB = SZ_OB / 2;
         const bool lowg = g4 < 2;
         const int x = X0 + 16 * w + j16;
-        // I at the pixels this lane finishes and the next tile's samples are
-        // requested together before the vector work below, all from clamped
-        // addresses (values past the image are loaded but never used), so that
-        // their latency overlaps it; without I, R stands in for the loads
+        // I at the pixels this lane finishes, requested before the vector work
+        // below from clamped addresses (values past the image are loaded but
+        // never used), so that its latency overlaps it; without I, R stands in
+        // for the loads
         float iv[HB][4];
         {
             const float* ip = a.I ? a.I : a.X;
@@ -622,7 +630,6 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
                     iv[q][e] = ip[(size_t)min(y, a.H - 1) * a.W + xc];
                 }
         }
-        if (more) sz_load_tile(a, tn, tid, sv);
 
         const double xh = a.sx * x + a.ox;
         const float xf = (float)xh;
@@ -685,10 +692,17 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
                 }
         }
 
-        // every wave is done with the staged tile: stage the next one
-        __syncthreads();
+        // the next tile's samples (their registers would not fit beside Z);
+        // once every wave is done with the staged tile, stage them.  Loads,
+        // barrier and stores sit under one branch (`more` is uniform), so the
+        // samples are not live across the passes.
         if (more) {
-            sz_store_tile<FP16>(a, tn, tid, sv, xs);
+            float sv[SZ_SROWS][2];
+            sz_load_tile(a, tn, ws, lane, sv);
+            __syncthreads();
+            sz_store_tile<FP16>(a, tn, ws, lane, sv, xs);
+            __syncthreads();
+        } else {
             __syncthreads();
         }
     }
