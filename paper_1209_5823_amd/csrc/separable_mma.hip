@@ -210,23 +210,37 @@ __global__ __launch_bounds__(SM_NT, smm_waves_per_simd(ADJ, DSM)) void contract_
     const int y_end = min(a.H, a.y_begin + a.n_rows);
 
     // stage (R - s) * xscale as hi / lo, two columns per thread (32-bit LDS
-    // writes); R = 0 outside the image; zero past the halo
-    for (int q = tid; q < SM_XR * (SM_XC / 2); q += SM_NT) {
-        const int r = q / (SM_XC / 2), c = 2 * (q - r * (SM_XC / 2));
-        float v[2];
+    // writes); R = 0 outside the image; zero past the halo.  Every sample is
+    // first loaded from a clamped, in-image address, none conditionally, so
+    // that all loads are in flight together; the masks apply when storing.
+    constexpr int SITER = (SM_XR * (SM_XC / 2) + SM_NT - 1) / SM_NT;
+    float sv[SITER][2];
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            v[e] = 0.f;
-            if (r < RA && c + e < CA) {
-                const int gy = Y0 - h + r, gx = X0 - h + c + e;
-                const float x = (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) ? a.X[(size_t)gy * a.W + gx] : 0.f;
-                v[e] = (x - a.ped) * xscale;
+    for (int i = 0; i < SITER; ++i) {
+        const int q = tid + i * SM_NT;
+        const int r = q / (SM_XC / 2), c = 2 * (q - r * (SM_XC / 2));
+        const float* src = a.X + (size_t)min(max(Y0 - h + r, 0), a.H - 1) * a.W;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) sv[i][e] = src[min(max(X0 - h + c + e, 0), a.W - 1)];
+    }
+#pragma unroll
+    for (int i = 0; i < SITER; ++i) {
+        const int q = tid + i * SM_NT;
+        if (q < SM_XR * (SM_XC / 2)) {
+            const int r = q / (SM_XC / 2), c = 2 * (q - r * (SM_XC / 2));
+            const int gy = Y0 - h + r;
+            float v[2];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int gx = X0 - h + c + e;
+                const float x = (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) ? sv[i][e] : 0.f;
+                v[e] = (r < RA && c + e < CA) ? (x - a.ped) * xscale : 0.f;
             }
+            uint32_t hi2, lo2;
+            smm_split2<FP16>(v[0], v[1], hi2, lo2);
+            *reinterpret_cast<uint32_t*>(xs + r * SM_P + c) = hi2;
+            *reinterpret_cast<uint32_t*>(xs + (SM_XR + r) * SM_P + c) = lo2;
         }
-        uint32_t hi2, lo2;
-        smm_split2<FP16>(v[0], v[1], hi2, lo2);
-        *reinterpret_cast<uint32_t*>(xs + r * SM_P + c) = hi2;
-        *reinterpret_cast<uint32_t*>(xs + (SM_XR + r) * SM_P + c) = lo2;
     }
     // row-response rows SM_XR .. SM_UR - 1 are read by the column windows and never
     // written: zeroed once, 8 entries per write
@@ -286,7 +300,8 @@ __global__ __launch_bounds__(SM_NT, smm_waves_per_simd(ADJ, DSM)) void contract_
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int y = Y0 + 16 * (rb0 + b) + 4 * g4 + e;
-                gq[b][e] = (x < a.W && y < y_end) ? a.I[(size_t)y * a.W + x] : 0.f;
+                const float gl = a.I[(size_t)min(y, a.H - 1) * a.W + min(x, a.W - 1)];
+                gq[b][e] = (x < a.W && y < y_end) ? gl : 0.f;
                 float tq = gq[b][e];
 #pragma unroll
                 for (int q = 0; q <= DSM; ++q) {
@@ -442,6 +457,18 @@ __global__ __launch_bounds__(SM_NT, smm_waves_per_simd(ADJ, DSM)) void contract_
         for (int q = 1; q <= DSM; ++q) xpow[q] = xpow[q - 1] * xh;
         double cy[DSM + 1];
         coef_in_x<DSM>(as_const(a.gammap), xpow, cy);
+        // I at this lane's pixels, all requested at once from clamped addresses
+        // (without I, R stands in for the loads)
+        float iv[2][4];
+        {
+            const float* ip = a.I ? a.I : a.X;
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    iv[b][e] = ip[(size_t)min(Y0 + 16 * (rb0 + b) + 4 * g4 + e, a.H - 1) * a.W + x];
+        }
+        const bool has_i = a.I != nullptr;
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -453,8 +480,8 @@ __global__ __launch_bounds__(SM_NT, smm_waves_per_simd(ADJ, DSM)) void contract_
 #pragma unroll
                     for (int q = DSM - 1; q >= 0; --q) pg = fma(pg, yh, cy[q]);
                     const size_t idx = (size_t)y * a.W + x;
-                    const double iv = a.I ? (double)a.I[idx] : 0.0;
-                    a.out[idx] = (float)(fma((double)acc32[b][e], unscale, (double)a.ped * pg) - iv);
+                    a.out[idx] = (float)(fma((double)acc32[b][e], unscale, (double)a.ped * pg) -
+                                         (has_i ? (double)iv[b][e] : 0.0));
                 }
             }
     }
@@ -594,8 +621,18 @@ __global__ __launch_bounds__(SM_NT, SM_MINW) void adjoint_r_sepmm_kernel(SepArgs
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const int yq = 2 * pr + e, gx = X0 - h + xq, gy = Y0 - h + yq;
-            gv[k][e] = (xq < CA && yq < CA && gx >= 0 && gx < a.W && gy >= 0 && gy < a.H)
-                           ? a.X[(size_t)gy * a.W + gx] : 0.f;
+            gv[k][e] = a.X[(size_t)min(max(gy, 0), a.H - 1) * a.W + min(max(gx, 0), a.W - 1)];
+        }
+    }
+    // (loaded from clamped addresses above so that no load is conditional;
+    // masked here)
+#pragma unroll
+    for (int k = 0; k < SA_NI; ++k) {
+        const int q = tid + k * SM_NT, xq = q / (SM_XR / 2), pr = q - xq * (SM_XR / 2);
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int yq = 2 * pr + e, gx = X0 - h + xq, gy = Y0 - h + yq;
+            if (!(xq < CA && yq < CA && gx >= 0 && gx < a.W && gy >= 0 && gy < a.H)) gv[k][e] = 0.f;
         }
     }
     smm_f4 accR[2];   // dR blocks w and w + 8 of the 4 x 4 output blocks

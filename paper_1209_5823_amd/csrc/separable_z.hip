@@ -557,6 +557,10 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
                 ubw[rb * 64] = make_uint4(sz_ror8<0x3>(c1h[0], c0h[0]), sz_ror8<0x3>(c1h[1], c0h[1]),
                                           sz_ror8<0x3>(c1l[0], c0l[0]), sz_ror8<0x3>(c1l[1], c0l[1]));
             };
+            // the row pass runs at raised wave priority: its vector work (splits,
+            // row moves) then fills the issue cycles that the other wave's
+            // column passes leave between their matrix-core products
+            __builtin_amdgcn_s_setprio(1);
             issue(0, acc[0]);
 #pragma unroll
             for (int rb = 1; rb < SZ_RB; ++rb) {
@@ -564,6 +568,7 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
                 split(rb - 1, acc[(rb - 1) & 1]);
             }
             split(SZ_RB - 1, acc[(SZ_RB - 1) & 1]);
+            __builtin_amdgcn_s_setprio(0);
 
             // ---- column passes: Z[s][ob] += g_{r, 2 mp + s} (x)_y U_r for both factors
             {
