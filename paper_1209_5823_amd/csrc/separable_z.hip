@@ -189,11 +189,10 @@ int build_sepz_rtab(const double* f1d, const int* rinfo, int R, int h, uint16_t*
 // Value of the regrouped column filter g_{r,m} at tap u (float64):
 // sum_j a[n(r,j)][m] f_j(u) over the column factors j of row factor r's
 // family (the family's factors are row factors r - i .. r - i + degree), from
-// the block's copies of a and of the factors.
-__device__ __forceinline__ double sz_gval(const float* as, const double* fcs, const int* __restrict__ rinfo,
-                                          const int* __restrict__ fam, int M, int k, int r, int m, int u) {
-    const int g = rinfo[2 * r], i = rinfo[2 * r + 1];
-    const int deg = fam[2 * g], base = fam[2 * g + 1];
+// the block's copies of a and of the factors; i is r's index in its family,
+// deg and base the family's degree and first basis.
+__device__ __forceinline__ double sz_gval(const float* as, const double* fcs, int i, int deg, int base, int M, int k,
+                                          int r, int m, int u) {
     double s = 0.0;
     for (int j = 0; j + i <= deg; ++j) {
         const int tt = i + j;
@@ -212,24 +211,59 @@ constexpr int kSzPrepMaxRows = 64;   // row factors (N <= 64)
 // outside [0, 2h] and for m >= M; S_m is the power of two that puts the
 // largest |g_{., m}| in [1, 2).  Blocks of r = 0 also write zinv[m] =
 // 1 / (S_m xscale), and block (0, 0) the padded pedestal sums
-// gam[m] = sum_n a[n][m] beta_n.  a and the factors are first copied into
-// LDS, so the sums read no global memory.
+// gam[m] = sum_n a[n][m] beta_n.  a, beta and the factors are first copied
+// into LDS (every load of a phase in flight together), so the sums read no
+// global memory; the maxima reduce across each wave by shuffles.
 template <bool FP16>
 __global__ __launch_bounds__(256) void sepz_prep_kernel(const float* __restrict__ a, const double* __restrict__ f1d,
                                                         const int* __restrict__ rinfo, const int* __restrict__ fam,
                                                         const double* __restrict__ beta, int R, int N, int M, int h,
                                                         float xscale, uint16_t* __restrict__ ztab,
                                                         float* __restrict__ zinv, double* __restrict__ gam) {
-    __shared__ double red[2][256];
+    constexpr int KMAX = 2 * kSepZMaxHalfWidth + 1;
+    __shared__ double red[2][4];
     __shared__ double scale[2];
-    __shared__ double fcs[kSzPrepMaxRows * (2 * kSepZMaxHalfWidth + 1)];
+    __shared__ double fcs[kSzPrepMaxRows * KMAX];
+    __shared__ double bt[kMaxFilters];
     __shared__ float as[kMaxFilters * 6];
+    __shared__ int ri[2 * kSzPrepMaxRows];
+    __shared__ int rfam[2 * kSzPrepMaxRows];   // per row factor: family degree, first basis
     const int r = blockIdx.x, mp = blockIdx.y, tid = threadIdx.x;
     const int k = 2 * h + 1;
-    for (int q = tid; q < N * M; q += 256) as[q] = a[q];
-    for (int q = tid; q < R * k; q += 256) {
-        const int rr = q / k, u = q - rr * k;
-        fcs[q] = f1d[((size_t)rinfo[2 * rr] * kSepMaxFactors + rinfo[2 * rr + 1]) * k + u];
+    // a, beta and the row factors' (family, index) pairs; clamped addresses,
+    // so that no load is conditional
+    constexpr int NA = (kMaxFilters * 6 + 255) / 256;
+    {
+        float av[NA];
+#pragma unroll
+        for (int i = 0; i < NA; ++i) av[i] = a[min(tid + 256 * i, N * M - 1)];
+        const int rv = rinfo[min(tid, 2 * R - 1)];
+        const double bv = beta[min(tid, N - 1)];
+#pragma unroll
+        for (int i = 0; i < NA; ++i)
+            if (tid + 256 * i < N * M) as[tid + 256 * i] = av[i];
+        if (tid < 2 * R) ri[tid] = rv;
+        if (tid < N) bt[tid] = bv;
+    }
+    __syncthreads();
+    constexpr int NF = (kSzPrepMaxRows * KMAX + 255) / 256;
+    {
+        double fv[NF];
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+            const int q = min(tid + 256 * i, R * k - 1);
+            const int rr = q / k, u = q - rr * k;
+            fv[i] = f1d[((size_t)ri[2 * rr] * kSepMaxFactors + ri[2 * rr + 1]) * k + u];
+        }
+        const int fr = min(tid, R - 1);
+        const int fd = fam[2 * ri[2 * fr]], fb = fam[2 * ri[2 * fr] + 1];
+#pragma unroll
+        for (int i = 0; i < NF; ++i)
+            if (tid + 256 * i < R * k) fcs[tid + 256 * i] = fv[i];
+        if (tid < R) {
+            rfam[2 * tid] = fd;
+            rfam[2 * tid + 1] = fb;
+        }
     }
     __syncthreads();
     // largest |g_{r', m}| over every row factor and tap, for m = 2 mp + s
@@ -239,21 +273,19 @@ __global__ __launch_bounds__(256) void sepz_prep_kernel(const float* __restrict_
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             const int m = 2 * mp + s;
-            if (m < M) mx[s] = fmax(mx[s], fabs(sz_gval(as, fcs, rinfo, fam, M, k, rr, m, u)));
+            if (m < M)
+                mx[s] = fmax(mx[s], fabs(sz_gval(as, fcs, ri[2 * rr + 1], rfam[2 * rr], rfam[2 * rr + 1], M, k, rr, m, u)));
         }
     }
-    red[0][tid] = mx[0];
-    red[1][tid] = mx[1];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) mx[s] = fmax(mx[s], __shfl_xor(mx[s], off));
+        if ((tid & 63) == 0) red[s][tid >> 6] = mx[s];
+    }
     __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if (tid < st) {
-            red[0][tid] = fmax(red[0][tid], red[0][tid + st]);
-            red[1][tid] = fmax(red[1][tid], red[1][tid + st]);
-        }
-        __syncthreads();
-    }
     if (tid < 2) {
-        const double v = red[tid][0];
+        const double v = fmax(fmax(red[tid][0], red[tid][1]), fmax(red[tid][2], red[tid][3]));
         double sc = 1.0;
         if (v > 0.0) {
             int e;
@@ -267,7 +299,7 @@ __global__ __launch_bounds__(256) void sepz_prep_kernel(const float* __restrict_
     if (r == 0 && mp == 0 && tid < kSepCoefPad) {
         double s = 0.0;
         if (tid < M)
-            for (int n = 0; n < N; ++n) s = fma((double)as[n * M + tid], beta[n], s);
+            for (int n = 0; n < N; ++n) s = fma((double)as[n * M + tid], bt[n], s);
         gam[tid] = s;
     }
     __syncthreads();
@@ -278,7 +310,7 @@ __global__ __launch_bounds__(256) void sepz_prep_kernel(const float* __restrict_
         const int m = 2 * mp + s;
         const int u = y + 2 * h - sz_col_row(ph, g, t);
         double v = 0.0;
-        if (m < M && u >= 0 && u < k) v = scale[s] * sz_gval(as, fcs, rinfo, fam, M, k, r, m, u);
+        if (m < M && u >= 0 && u < k) v = scale[s] * sz_gval(as, fcs, ri[2 * r + 1], rfam[2 * r], rfam[2 * r + 1], M, k, r, m, u);
         uint16_t hi, lo;
         sz_split_tap<FP16>(v, hi, lo);
         dst[((ph * 2 + 0) * 64 + lane) * 8 + t] = hi;
