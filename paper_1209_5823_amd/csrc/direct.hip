@@ -40,12 +40,27 @@ __global__ __launch_bounds__(DR_NT) void contract_direct_kernel(DirectArgs a) {
     const cptr<float> tp = as_const(a.taps);
     auto tap = [&](int m, int t) -> float { return DFB ? tp[(K * K - 1 - t) * M + m] : tp[m * K * K + t]; };
 
-    // stage R - s; R = 0 outside the image
-    for (int q = tid; q < SR * SC; q += DR_NT) {
+    // stage R - s; R = 0 outside the image.  Every sample is loaded from a
+    // clamped, in-image address and none conditionally, so that all loads are
+    // in flight together; the image mask applies when storing.
+    constexpr int SITER = (SR * SC + DR_NT - 1) / DR_NT;
+    float sv[SITER];
+#pragma unroll
+    for (int i = 0; i < SITER; ++i) {
+        const int q = min(tid + i * DR_NT, SR * SC - 1);
         const int r = q / SC, cc = q - r * SC;
-        const int gy = Y0 - H + r, gx = X0 - H + cc;
-        const float x = (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) ? a.X[(size_t)gy * a.W + gx] : 0.f;
-        tile[r][cc] = x - a.ped;
+        const int gy = min(max(Y0 - H + r, 0), a.H - 1), gx = min(max(X0 - H + cc, 0), a.W - 1);
+        sv[i] = a.X[(size_t)gy * a.W + gx];
+    }
+#pragma unroll
+    for (int i = 0; i < SITER; ++i) {
+        const int q = tid + i * DR_NT;
+        if (q < SR * SC) {
+            const int r = q / SC, cc = q - r * SC;
+            const int gy = Y0 - H + r, gx = X0 - H + cc;
+            const float x = (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) ? sv[i] : 0.f;
+            tile[r][cc] = x - a.ped;
+        }
     }
     // pedestal sums gamma_m = sum of Kt_m's taps (float64)
     if (tid < M) {
@@ -99,6 +114,14 @@ __global__ __launch_bounds__(DR_NT) void contract_direct_kernel(DirectArgs a) {
 
     const int x = X0 + c;
     if (x >= a.W) return;
+    // I at this thread's pixels, all requested at once from clamped addresses
+    // (without I, R stands in for the loads)
+    float iv[DR_RPT];
+    {
+        const float* ip = a.I ? a.I : a.X;
+#pragma unroll
+        for (int o = 0; o < DR_RPT; ++o) iv[o] = ip[(size_t)min(Y0 + DR_RPT * rg + o, a.H - 1) * a.W + x];
+    }
     const double xh = a.sx * x + a.ox;
     double xp[DS + 1];
     xp[0] = 1.0;
@@ -122,7 +145,7 @@ __global__ __launch_bounds__(DR_NT) void contract_direct_kernel(DirectArgs a) {
             for (int j = 0; j <= t; ++j, ++m)
                 v = fma(xp[t - j] * yp[j], fma((double)a.ped, gam_s[m], tot[o][m]), v);
         const size_t idx = (size_t)y * a.W + x;
-        a.out[idx] = (float)(a.I ? v - (double)a.I[idx] : v);
+        a.out[idx] = (float)(a.I ? v - (double)iv[o] : v);
     }
 }
 
