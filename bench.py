@@ -50,7 +50,17 @@ def time_form(plan, args, R, I, a, D, precision, form):
     except SvconvError as e:
         log("  %s/%s: %s" % (form, precision, e))
         return None
+    # the timed steps: one event on each side, none between the steps (an event
+    # between two launches adds its own few microseconds to every step)
     torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.steps):
+        plan.difference(R, I, a, out=D)
+    t1.record()
+    torch.cuda.synchronize()
+    mean = t0.elapsed_time(t1) / args.steps
+    # then the spread over as many steps again, each bracketed by events
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     ev[0].record()
     for k in range(args.steps):
@@ -59,7 +69,7 @@ def time_form(plan, args, R, I, a, D, precision, form):
     torch.cuda.synchronize()
     per = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps))
     time_form.last = {"median_ms": per[len(per) // 2], "min_ms": per[0]}
-    return ev[0].elapsed_time(ev[-1]) / args.steps
+    return mean
 
 
 def main():

@@ -501,9 +501,9 @@ __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs 
     // The tap tables are read one stage ahead: a stage is the row pass of a
     // pair of row factors or the column passes of one row factor for one pair
     // of spatial terms, and the next stage's entry is requested into `nxt`
-    // once the current stage's products are issued, so its latency overlaps
-    // their execution (the tables are read from L2).  The stage after a
-    // tile's last is the first one of the next tile.
+    // before the current stage's products are issued (into registers of its
+    // own), so its latency overlaps their execution (the tables are read from
+    // L2).  The stage after a tile's last is the first one of the next tile.
     uint4 cur[2][2], nxt[2][2];
     sz_load_tab(a.rtab, lane, cur);
 
