@@ -478,8 +478,9 @@ __device__ __forceinline__ void sz_store_tile(const SepZArgs& a, int t, int w, i
 }
 
 // Persistent workgroups: workgroup b takes tiles b, b + G, b + 2G, ... (G =
-// the grid) in the XCD-aware order; the loads of its next tile are in flight
-// during the current tile's epilogue.
+// the grid) in the XCD-aware order; each wave requests its rows of the next
+// tile once the current tile's epilogue is issued, and they are staged after
+// the barrier that ends the current tile.
 template <bool FP16, int NT, int MP>
 __global__ __launch_bounds__(SZ_NT, SZ_MINW) void contract_sepz_kernel(SepZArgs a) {
     extern __shared__ uint4 sz_lds[];
