@@ -197,7 +197,11 @@ F32Geometry f32_geometry(int k, int nb);
 LowpGeometry lowp_geometry(int k, int nb);
 int build_f32_fragments(const float* F, int NF, int k, float* frag, hipStream_t s);
 int build_lowp_fragments(const float* F, int NF, int k, int fp16, float* scale,
-                         uint16_t* frag, hipStream_t s);
+                         uint16_t* frag, hipStream_t s, bool packed = false);
+// true when launch_contract_lowp runs the two-column packed kernel for these
+// arguments (regrouped filters, at most 8 of them); its fragments must then be
+// built with packed = true
+bool lowp_packed(const ContractArgs& a, int nb);
 int regroup_filters(const double* F64, const double* beta, const float* a, int N, int M, int k,
                     float* Ft, double* betaT, hipStream_t s);
 int adjoint_filters(const double* F64, const float* a, int N, int M, int d_s, int k,

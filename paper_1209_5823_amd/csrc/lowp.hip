@@ -119,9 +119,12 @@ __global__ void lowp_scale_kernel(const float* __restrict__ F, int NF, int kk, i
 
 // A-operand fragments: element e of lane l, block b, row group r, chunk q is
 // filter f = 16 b + (l & 15) at (dv = 4 r + (l >> 4), du = 8 q + e), scaled.
-// Layout [r][q][b][half][lane][8], half 0 = hi, 1 = lo.
+// Packed (at most 8 filters, one block): rows 0..7 are filters 0..7 at du,
+// rows 8..15 the same filters at du - 1, i.e. the taps of the next output
+// column on the same input window.  Layout [r][q][b][half][lane][8], half 0 =
+// hi, 1 = lo.
 __global__ void frag_lowp_kernel(const float* __restrict__ F, const float* __restrict__ scale,
-                                 int NF, int k, int nb, int n_rg, int n_q, int fp16,
+                                 int NF, int k, int nb, int n_rg, int n_q, int fp16, int packed,
                                  uint16_t* __restrict__ frag) {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;   // one (r,q,b,lane,e)
     const long total = (long)n_rg * n_q * nb * 64 * 8;
@@ -133,11 +136,12 @@ __global__ void frag_lowp_kernel(const float* __restrict__ F, const float* __res
     rest /= nb;
     const int q = (int)(rest % n_q);
     const int r = (int)(rest / n_q);
-    const int f = 16 * b + (lane & 15);
+    const int fl = lane & 15;
+    const int f = packed ? (fl & 7) : 16 * b + fl;
     const int dv = 4 * r + (lane >> 4);
-    const int du = 8 * q + e;
+    const int du = 8 * q + e - (packed ? (fl >> 3) : 0);
     float v = 0.f;
-    if (f < NF && dv < k && du < k) v = F[((size_t)f * k + dv) * k + du] * scale[f];
+    if (f < NF && dv < k && du >= 0 && du < k) v = F[((size_t)f * k + dv) * k + du] * scale[f];
     uint32_t hi, lo;
     if (fp16) split16<true>(v, hi, lo);
     else split16<false>(v, hi, lo);
@@ -147,7 +151,7 @@ __global__ void frag_lowp_kernel(const float* __restrict__ F, const float* __res
 }
 
 int build_lowp_fragments(const float* F, int NF, int k, int fp16, float* scale,
-                         uint16_t* frag, hipStream_t s) {
+                         uint16_t* frag, hipStream_t s, bool packed) {
     // scale: 2 * kMaxFilters floats, [0, kMaxFilters) the scales s_f and
     // [kMaxFilters, 2 kMaxFilters) the inverse factors used by the epilogue
     if (k > 8 * LP_NQ) return SVCONV_OK;   // beyond the low-precision kernel's reach
@@ -159,7 +163,7 @@ int build_lowp_fragments(const float* F, int NF, int k, int fp16, float* scale,
     if (st) return st;
     const long total = (long)n_rg * n_q * nb * 64 * 8;
     hipLaunchKernelGGL(frag_lowp_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, F,
-                       scale, NF, k, nb, n_rg, n_q, fp16, frag);
+                       scale, NF, k, nb, n_rg, n_q, fp16, packed ? 1 : 0, frag);
     return hip_status(hipGetLastError(), "frag_lowp_kernel");
 }
 
@@ -427,6 +431,148 @@ __device__ __forceinline__ void lp_epilogue_setup(const ContractArgs& a, float (
     }
 }
 
+// ------------------------------------------- two-column packed contraction --
+//
+// With at most 8 filters (the regrouped form's M <= 8) half of a 16-row A
+// operand would be empty.  Packed, rows 8..15 hold the same filters shifted by
+// one kernel column, so each product yields the filters at two neighbouring
+// output columns x and x + 1 from one input window: wave w owns the column
+// pairs (2 w + 16 i, 2 w + 16 i + 1), i < LP_TP / 2, and issues half the
+// products.  The windows then start at an even sample, 2 w mod 8, i.e. on a
+// 32-bit word: no funnel shifts.
+constexpr int LP_PB = LP_TP / 2;                 // column pairs per wave
+constexpr int LP_PNCH = 2 * LP_PB + LP_NQ - 1;   // 16-byte chunks a packed lane loads per row
+
+// windows W_t = words [D, D + 4) of chunk t ++ chunk t + 1, formed in place
+template <int D>
+__device__ __forceinline__ void lp_word_windows(uint32_t (&c)[LP_PNCH][4]) {
+#pragma unroll
+    for (int t = 0; t + 1 < LP_PNCH; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) c[t][e] = (e + D < 4) ? c[t][e + D] : c[t + 1][e + D - 4];
+}
+
+template <bool FP16, bool SPLIT_R, bool SPLIT_B>
+__device__ __forceinline__ void lp_rowgroup_packed(f4 (&acc)[LP_PB], const uint16_t* hiT,
+                                                   const uint16_t* loT, int pitch, int row,
+                                                   const uint4* sl, int n_q, int lane, int w) {
+    constexpr int HALVES = SPLIT_B ? 2 : 1;
+    const int cb = w >> 2;   // the chunk that holds sample 2 w
+    uint32_t ch[LP_PNCH][4], cl[LP_PNCH][4];
+    {
+        const uint4* ph = reinterpret_cast<const uint4*>(hiT + row * pitch) + cb;
+        const uint4* pl = reinterpret_cast<const uint4*>(loT + row * pitch) + cb;
+#pragma unroll
+        for (int c = 0; c < LP_PNCH; ++c) {
+            const uint4 vh = ph[c];
+            ch[c][0] = vh.x; ch[c][1] = vh.y; ch[c][2] = vh.z; ch[c][3] = vh.w;
+            if (SPLIT_R) {
+                const uint4 vl = pl[c];
+                cl[c][0] = vl.x; cl[c][1] = vl.y; cl[c][2] = vl.z; cl[c][3] = vl.w;
+            }
+        }
+    }
+    switch (w & 3) {
+        case 0: break;
+        case 1: lp_word_windows<1>(ch); if (SPLIT_R) lp_word_windows<1>(cl); break;
+        case 2: lp_word_windows<2>(ch); if (SPLIT_R) lp_word_windows<2>(cl); break;
+        default: lp_word_windows<3>(ch); if (SPLIT_R) lp_word_windows<3>(cl); break;
+    }
+    uint32_t fh[4], fl[4];
+    auto load_frags = [&](int q, uint32_t (&h_)[4], uint32_t (&l_)[4]) {
+        const uint4 vh = sl[(q * HALVES + 0) * 64 + lane];
+        h_[0] = vh.x; h_[1] = vh.y; h_[2] = vh.z; h_[3] = vh.w;
+        if (SPLIT_B) {
+            const uint4 vl = sl[(q * HALVES + 1) * 64 + lane];
+            l_[0] = vl.x; l_[1] = vl.y; l_[2] = vl.z; l_[3] = vl.w;
+        }
+    };
+    load_frags(0, fh, fl);
+#pragma unroll
+    for (int q = 0; q < LP_NQ; ++q) {
+        if (q < n_q) {
+            uint32_t nh[4], nl[4];
+            if (q + 1 < n_q) load_frags(q + 1, nh, nl);
+#pragma unroll
+            for (int i = 0; i < LP_PB; ++i) acc[i] = mfma16<FP16>(fh, ch[2 * i + q], acc[i]);
+            if (SPLIT_R)
+#pragma unroll
+                for (int i = 0; i < LP_PB; ++i) acc[i] = mfma16<FP16>(fh, cl[2 * i + q], acc[i]);
+            if (SPLIT_B)
+#pragma unroll
+                for (int i = 0; i < LP_PB; ++i) acc[i] = mfma16<FP16>(fl, ch[2 * i + q], acc[i]);
+            if (q + 1 < n_q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    fh[e] = nh[e];
+                    if (SPLIT_B) fl[e] = nl[e];
+                }
+        }
+    }
+}
+
+// A fragments of the packed epilogue's U product: lane (k, m_l) holds, for
+// register e of the contraction, 1 / (s_f xscale) when filter f = 4 (k & 1) +
+// e is term m = m_l & 7 of the same output column (m_l >> 3 == k >> 1).
+__device__ __forceinline__ void lp_epilogue_setup_packed(const ContractArgs& a, float (&afr)[4], int lane) {
+    const int k = lane >> 4, ml = lane & 15;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int f = 4 * (k & 1) + e, m = ml & 7;
+        float v = 0.f;
+        if ((ml >> 3) == (k >> 1) && f == m && f < a.NF && m < a.M) v = a.fscale ? a.fscale[f] : 1.f;
+        afr[e] = v;
+    }
+}
+
+// Packed epilogue (regrouped form): lane (g, j) register e holds T_f, f =
+// 4 (g & 1) + e, at column x_i + (g >> 1), x_i = X0 + 2 w + 16 i, row Y0 + j;
+// the U product leaves U_m of column x_i in lane groups 0, 1 and of x_i + 1 in
+// groups 2, 3 (m = 4 (g & 1) + e').
+__device__ __forceinline__ void lp_epilogue_packed(const ContractArgs& a, const f4 (&acc)[LP_PB],
+                                                   const float (&afr)[4], const float* gamma_s, int X0,
+                                                   int Y0, int w, int g, int j) {
+    const int y = Y0 + j;
+    const int xoff = 2 * w + (g >> 1);
+    float iv[LP_PB];
+#pragma unroll
+    for (int i = 0; i < LP_PB; ++i) {
+        const int x = X0 + xoff + 16 * i;
+        iv[i] = (a.I && (g & 1) == 0 && x < a.W && y < a.y_begin + a.n_rows) ? a.I[(size_t)y * a.W + x] : 0.f;
+    }
+    const float yh = (float)(a.sy * y + a.oy);
+    int ei[4], ej[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int m = 4 * (g & 1) + e;
+        int tt = 0;
+        while ((tt + 1) * (tt + 2) / 2 <= m) ++tt;
+        ej[e] = m - tt * (tt + 1) / 2;
+        ei[e] = tt - ej[e];
+    }
+#pragma unroll
+    for (int i = 0; i < LP_PB; ++i) {
+        f4 u = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) u = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[e], acc[i][e], u, 0, 0, 0);
+        const int x = X0 + xoff + 16 * i;
+        const float xh = (float)(a.sx * x + a.ox);
+        float part = 0.f;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int m = 4 * (g & 1) + e;
+            if (m < a.M) {
+                float px = 1.f, py = 1.f;
+                for (int q = 0; q < ei[e]; ++q) px *= xh;
+                for (int q = 0; q < ej[e]; ++q) py *= yh;
+                part += px * py * (u[e] + a.ped * gamma_s[m]);
+            }
+        }
+        part += __shfl_xor(part, 16);
+        if ((g & 1) == 0 && x < a.W && y < a.y_begin + a.n_rows) a.out[(size_t)y * a.W + x] = part - iv[i];
+    }
+}
+
 __device__ __forceinline__ int lp_xcd_remap(int bid, int n) {
     const int x8 = bid & 7, tt = bid >> 3, q8 = n >> 3, r8 = n & 7;
     return x8 * q8 + (x8 < r8 ? x8 : r8) + tt;
@@ -507,7 +653,7 @@ __global__ __launch_bounds__(512, 1) void contract_lowp_kernel(
 // each tile's staging.
 constexpr int LP_PF = 4;   // staged element pairs per thread and tile (rows * pitch <= 1024 * LP_PF)
 
-template <int NB, int MB, bool FP16, bool SPLIT_R, bool SPLIT_B, bool REG>
+template <int NB, int MB, bool FP16, bool SPLIT_R, bool SPLIT_B, bool REG, bool PACK>
 __global__ __launch_bounds__(512, 1) void contract_lowp_resident_kernel(
     ContractArgs a, const uint16_t* __restrict__ frag, int k, int n_rg, int n_q, int pitch,
     int rows, int tiles_x, int n_tiles, int tiles_per_wg, float xscale) {
@@ -529,6 +675,8 @@ __global__ __launch_bounds__(512, 1) void contract_lowp_resident_kernel(
 
     float afr[NB][4][MB];
     lp_epilogue_setup<NB, MB, REG>(a, afr, gamma_s, tid, lane);
+    float afp[4];
+    if constexpr (PACK) lp_epilogue_setup_packed(a, afp, lane);
     // whole table: unit (r, q, b, hf, lane) from the [r][q][b][2][lane] global layout
     for (int u = tid; u < n_rg * rg_u4; u += 512) {
         const int ln = u & 63;
@@ -594,16 +742,26 @@ __global__ __launch_bounds__(512, 1) void contract_lowp_resident_kernel(
         const int X0 = (t % tiles_x) * LP_TW;
         const int Y0 = a.y_begin + (t / tiles_x) * LP_TH;
         if (t + 1 < t_end) fetch(t + 1);
-        f4 acc[NB][LP_TP];
+        if constexpr (PACK) {
+            f4 acc[LP_PB];
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
+            for (int i = 0; i < LP_PB; ++i) acc[i] = f4{0.f, 0.f, 0.f, 0.f};
+            for (int r = 0; r < n_rg; ++r)
+                lp_rowgroup_packed<FP16, SPLIT_R, SPLIT_B>(acc, hiT, loT, pitch, j + 4 * r + g,
+                                                           table + r * rg_u4, n_q, lane, w);
+            lp_epilogue_packed(a, acc, afp, gamma_s, X0, Y0, w, g, j);
+        } else {
+            f4 acc[NB][LP_TP];
 #pragma unroll
-            for (int i = 0; i < LP_TP; ++i) acc[b][i] = f4{0.f, 0.f, 0.f, 0.f};
-        auto nohook = [](int, int) {};
-        for (int r = 0; r < n_rg; ++r)
-            lp_rowgroup<NB, FP16, SPLIT_R, SPLIT_B>(acc, hiT, loT, pitch, j + 4 * r + g,
-                                                   table + r * rg_u4, n_q, lane, w, nohook);
-        lp_epilogue<NB, MB>(a, acc, afr, gamma_s, X0, Y0, w, g, j);
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int i = 0; i < LP_TP; ++i) acc[b][i] = f4{0.f, 0.f, 0.f, 0.f};
+            auto nohook = [](int, int) {};
+            for (int r = 0; r < n_rg; ++r)
+                lp_rowgroup<NB, FP16, SPLIT_R, SPLIT_B>(acc, hiT, loT, pitch, j + 4 * r + g,
+                                                       table + r * rg_u4, n_q, lane, w, nohook);
+            lp_epilogue<NB, MB>(a, acc, afr, gamma_s, X0, Y0, w, g, j);
+        }
     }
 }
 
@@ -621,30 +779,61 @@ static int num_cus() {
     return g_num_cus;
 }
 
-template <int NB, int MB, bool FP16, bool SR, bool SB>
-static int launch_lowp_t(const ContractArgs& a, const uint16_t* frag, bool reg, hipStream_t s) {
-    constexpr int HALVES = SB ? 2 : 1;
+// Whether the persistent kernel with the whole fragment table in LDS runs for
+// these arguments (else the slab kernel).
+static bool lowp_resident(const ContractArgs& a, int nb, bool split_b, int* n_tiles_out = nullptr,
+                          int* tiles_x_out = nullptr) {
+    const int HALVES = split_b ? 2 : 1;
     const int k = 2 * a.h + 1;
-    const LowpGeometry g = lowp_geometry(k, NB);
+    const LowpGeometry g = lowp_geometry(k, nb);
     const int tiles_x = (a.W + g.tile_w - 1) / g.tile_w;
     const int tiles_y = (a.n_rows + g.tile_h - 1) / g.tile_h;
     const int n_tiles = tiles_x * tiles_y;
+    if (n_tiles_out) *n_tiles_out = n_tiles;
+    if (tiles_x_out) *tiles_x_out = tiles_x;
+    const size_t tile_bytes = (size_t)g.lds_rows * g.lds_pitch * 2 * 2;
+    const size_t table_bytes = (size_t)g.n_rg * g.n_q * nb * HALVES * 64 * 16;
+    const size_t coef_bytes = (size_t)kMaxSpatialTerms * 4;   // gamma
+    const bool fits_pf = (size_t)g.lds_rows * g.lds_pitch <= (size_t)1024 * LP_PF;
+    return tile_bytes + table_bytes + coef_bytes <= (size_t)160 * 1024 && fits_pf && n_tiles >= 2 * num_cus();
+}
+
+bool lowp_packed(const ContractArgs& a, int nb) {
+    const int k = 2 * a.h + 1;
+    // every split precision keeps the lo half of the fragments (SPLIT_B) except
+    // fp16x2, whose table is half as large: the resident test with the larger
+    // table holds for both
+    return a.coef == nullptr && nb == 1 && a.M <= 8 && k <= 8 * LP_NQ && lowp_resident(a, nb, true);
+}
+
+template <int NB, int MB, bool FP16, bool SR, bool SB>
+static int launch_lowp_t(const ContractArgs& a, const uint16_t* frag, bool reg, hipStream_t s) {
+    const int k = 2 * a.h + 1;
+    const LowpGeometry g = lowp_geometry(k, NB);
+    int n_tiles = 0, tiles_x = 0;
+    const bool resident = lowp_resident(a, NB, SB, &n_tiles, &tiles_x);
     if (n_tiles == 0) return SVCONV_OK;
     const float xs = FP16 ? FP16_XSCALE : 1.f;
-    const size_t tile_bytes = (size_t)g.lds_rows * g.lds_pitch * 2 * 2;
-    const size_t table_bytes = (size_t)g.n_rg * g.n_q * NB * HALVES * 64 * 16;
-    const size_t coef_bytes = (size_t)kMaxSpatialTerms * 4;   // gamma
-    const size_t resident_bytes = tile_bytes + table_bytes + coef_bytes;
-    const bool fits_pf = (size_t)g.lds_rows * g.lds_pitch <= (size_t)1024 * LP_PF;
-    if (resident_bytes <= (size_t)160 * 1024 && fits_pf && n_tiles >= 2 * num_cus()) {
+    constexpr int HALVES = SB ? 2 : 1;
+    const size_t resident_bytes = (size_t)g.lds_rows * g.lds_pitch * 2 * 2 +
+                                  (size_t)g.n_rg * g.n_q * NB * HALVES * 64 * 16 + (size_t)kMaxSpatialTerms * 4;
+    if (resident) {
         const int n_wg = num_cus();
         const int per = (n_tiles + n_wg - 1) / n_wg;
+        if constexpr (NB == 1 && MB == 1) {
+            if (lowp_packed(a, NB)) {
+                hipLaunchKernelGGL((contract_lowp_resident_kernel<NB, MB, FP16, SR, SB, true, true>), dim3(n_wg),
+                                   dim3(512), resident_bytes, s, a, frag, k, g.n_rg, g.n_q, g.lds_pitch,
+                                   g.lds_rows, tiles_x, n_tiles, per, xs);
+                return hip_status(hipGetLastError(), "contract_lowp_resident_kernel");
+            }
+        }
         if (reg)
-            hipLaunchKernelGGL((contract_lowp_resident_kernel<NB, MB, FP16, SR, SB, true>), dim3(n_wg),
+            hipLaunchKernelGGL((contract_lowp_resident_kernel<NB, MB, FP16, SR, SB, true, false>), dim3(n_wg),
                                dim3(512), resident_bytes, s, a, frag, k, g.n_rg, g.n_q, g.lds_pitch,
                                g.lds_rows, tiles_x, n_tiles, per, xs);
         else
-            hipLaunchKernelGGL((contract_lowp_resident_kernel<NB, MB, FP16, SR, SB, false>), dim3(n_wg),
+            hipLaunchKernelGGL((contract_lowp_resident_kernel<NB, MB, FP16, SR, SB, false, false>), dim3(n_wg),
                                dim3(512), resident_bytes, s, a, frag, k, g.n_rg, g.n_q, g.lds_pitch,
                                g.lds_rows, tiles_x, n_tiles, per, xs);
         return hip_status(hipGetLastError(), "contract_lowp_resident_kernel");

@@ -369,9 +369,10 @@ int run_forward(svconv_plan* p, const float* R, const float* I, const float* a, 
     }
     const bool h16 = is_fp16(p->precision);
     uint16_t* frag = h16 ? p->dFragTH : p->dFragTB;
-    st = build_lowp_fragments(p->dFt32, p->M, p->k, h16 ? 1 : 0, p->dScaleT, frag, p->stream);
-    if (st) return st;
     c.fscale = p->dScaleT + kMaxFilters;
+    st = build_lowp_fragments(p->dFt32, p->M, p->k, h16 ? 1 : 0, p->dScaleT, frag, p->stream,
+                              lowp_packed(c, nb));
+    if (st) return st;
     return launch_contract_lowp(c, frag, nb, p->precision, p->stream);
 }
 
