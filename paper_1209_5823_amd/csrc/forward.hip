@@ -59,8 +59,16 @@ constexpr int F32_TW = 64;   // output tile width: 4 waves x 16 columns
 
 // Output rows per tile (= 16-pixel blocks per wave): fewer rows for more
 // filter blocks so that the float32 sub-chain and float64 total fit in 256
-// registers (two waves per SIMD) without spilling.
+// registers (two waves per SIMD) without spilling.  The two-row packed form
+// keeps the 8 rows of one block: 16 rows per tile measured slower.
 constexpr int f32_tile_h(int nb) { return nb >= 4 ? 3 : nb >= 2 ? 4 : 8; }
+
+// Two-row packing: with at most 8 filters, rows 8..15 of the 16-row A operand
+// would be zeros.  They carry the same filters shifted down by one kernel row
+// instead, so that the product over the input rows of output row y also yields
+// output row y + 1 (the taps (dv, du) of row y + 1 see the input rows of taps
+// (dv + 1, du) of row y).  Only every other output row then needs products.
+bool f32_packed(int NF) { return NF <= 8; }
 
 F32Geometry f32_geometry(int k, int nb) {
     F32Geometry g;
@@ -84,9 +92,11 @@ size_t f32_fragment_floats(int k, int nb) {
 
 // A-operand fragments of v_mfma_f32_16x16x4_f32.  Chunk c = r * k + du holds
 // the taps (dv = 4r + g, du), g = 0..3; lane l of block b carries filter
-// 16 b + (l & 15) at tap g = l >> 4.  Filters beyond NF and rows beyond k are 0.
+// 16 b + (l & 15) at tap g = l >> 4.  Packed (one block): lane l carries filter
+// l & 7 at tap (dv - s, du) with s = (l >> 3) & 1, the shifted copy for the
+// next output row.  Filters beyond NF and rows outside 0..k-1 are 0.
 __global__ void frag_f32_kernel(const float* __restrict__ F, int NF, int k, int nb, int n_chunks,
-                                float* __restrict__ frag) {
+                                int packed, float* __restrict__ frag) {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const long total = (long)n_chunks * nb * 64;
     if (idx >= total) return;
@@ -94,10 +104,10 @@ __global__ void frag_f32_kernel(const float* __restrict__ F, int NF, int k, int 
     const int b = (int)((idx >> 6) % nb);
     const int c = (int)((idx >> 6) / nb);
     const int r = c / k, du = c - r * k;
-    const int dv = 4 * r + (lane >> 4);
-    const int f = 16 * b + (lane & 15);
+    const int dv = 4 * r + (lane >> 4) - (packed ? (lane >> 3) & 1 : 0);
+    const int f = packed ? (lane & 7) : 16 * b + (lane & 15);
     // chunks past the last row group (padding to a group of 4) carry zeros
-    frag[idx] = (f < NF && dv < k) ? F[((size_t)f * k + dv) * k + du] : 0.f;
+    frag[idx] = (f < NF && dv >= 0 && dv < k) ? F[((size_t)f * k + dv) * k + du] : 0.f;
 }
 
 int build_f32_fragments(const float* F, int NF, int k, float* frag, hipStream_t s) {
@@ -105,17 +115,21 @@ int build_f32_fragments(const float* F, int NF, int k, float* frag, hipStream_t 
     const F32Geometry g = f32_geometry(k, nb);
     const long total = (long)g.n_chunks * nb * 64;
     hipLaunchKernelGGL(frag_f32_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, F,
-                       NF, k, nb, g.n_chunks, frag);
+                       NF, k, nb, g.n_chunks, f32_packed(NF) ? 1 : 0, frag);
     return hip_status(hipGetLastError(), "frag_f32_kernel");
 }
 
 // ------------------------------------------------ FP32 contraction ----
 
-template <int NB, int TH, bool REG>
+template <int NB, int TH, bool REG, bool PACK>
 __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
                                                            const float* __restrict__ frag, int k,
                                                            int n_rg, int pitch, int rows, int cols,
                                                            int tiles_x, int n_tiles) {
+    static_assert(!PACK || (NB == 1 && TH % 2 == 0), "packed form: one filter block, row pairs");
+    // products per chunk and filter block, and the tile-row step between them
+    constexpr int RI = PACK ? TH / 2 : TH;
+    constexpr int RS = PACK ? 2 : 1;
     extern __shared__ __align__(16) float smem[];
     float* tile = smem;
     float* coef_s = smem + rows * pitch;
@@ -150,13 +164,20 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
     const int g = lane >> 4, j = lane & 15;
     const int n_chunks = (n_rg * k + 3) / 4 * 4;
 
+    // Lane (g, j) of product i ends with T_f at pixel column j of output row
+    // Y0 + RS i + yo for f = 16 b + fo + e, e = 0..3; lanes with g_lead sum
+    // the filters of their row and write it.
+    const int fo = PACK ? 4 * (g & 1) : 4 * g;
+    const int yo = PACK ? (g >> 1) : 0;
+    const bool g_lead = PACK ? ((g & 1) == 0) : (g == 0);
+
     // I at this lane's output pixels, loaded now so that its latency hides
     // behind the contraction
-    float iv[TH];
+    float iv[RI];
 #pragma unroll
-    for (int i = 0; i < TH; ++i) {
-        const int x = X0 + 16 * w + j, y = Y0 + i;
-        iv[i] = (a.I != nullptr && a.out != nullptr && g == 0 && x < a.W && y < y_end)
+    for (int i = 0; i < RI; ++i) {
+        const int x = X0 + 16 * w + j, y = Y0 + RS * i + yo;
+        iv[i] = (a.I != nullptr && a.out != nullptr && g_lead && x < a.W && y < y_end)
                     ? a.I[(size_t)y * a.W + x] : 0.f;
     }
 
@@ -166,11 +187,11 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
     // bright stars; short chains keep the rounding of each partial sum small
     // and the float64 total adds none.  The A fragments of the next group of
     // 4 chunks are requested from L2 while this group's products run.
-    double tot[NB][TH][4];
+    double tot[NB][RI][4];
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int i = 0; i < TH; ++i)
+        for (int i = 0; i < RI; ++i)
 #pragma unroll
             for (int e = 0; e < 4; ++e) tot[b][i][e] = 0.0;
 
@@ -192,11 +213,11 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
         for (int u = 0; u < 2; ++u)
 #pragma unroll
             for (int b = 0; b < NB; ++b) na[u][b] = fp[(size_t)((cn + u) * NB + b) * 64];
-        f4 acc[NB][TH];
+        f4 acc[NB][RI];
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
-            for (int i = 0; i < TH; ++i) acc[b][i] = f4{0.f, 0.f, 0.f, 0.f};
+            for (int i = 0; i < RI; ++i) acc[b][i] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             if (u == 2) {
@@ -208,11 +229,11 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
             // padded chunks past the last row group read row group n_rg - 1
             // (in the tile) with zero weights
             const float* rb = tb + 4 * (r < n_rg ? r : n_rg - 1) * pitch + du;
-            float xb[TH];
+            float xb[RI];
 #pragma unroll
-            for (int i = 0; i < TH; ++i) xb[i] = rb[i * pitch];
+            for (int i = 0; i < RI; ++i) xb[i] = rb[RS * i * pitch];
 #pragma unroll
-            for (int i = 0; i < TH; ++i)
+            for (int i = 0; i < RI; ++i)
 #pragma unroll
                 for (int b = 0; b < NB; ++b)
                     acc[b][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[u][b], xb[i], acc[b][i], 0, 0, 0);
@@ -224,7 +245,7 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
-            for (int i = 0; i < TH; ++i)
+            for (int i = 0; i < RI; ++i)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) tot[b][i][e] += (double)acc[b][i][e];
 #pragma unroll
@@ -237,7 +258,6 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
     }
 
     // Epilogue in float64: out = sum_f w_f (T_f + ped * beta_f) - I.
-    // Lane (g, j) holds T_f for f = 16 b + 4 g + e at pixel column j.
     const int x = X0 + 16 * w + j;
     const double xh = a.sx * x + a.ox;
     double xp[kMaxSpatialDegree + 1];
@@ -246,8 +266,8 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
     for (int q = 1; q <= kMaxSpatialDegree; ++q) xp[q] = xp[q - 1] * xh;
 
 #pragma unroll
-    for (int i = 0; i < TH; ++i) {
-        const int y = Y0 + i;
+    for (int i = 0; i < RI; ++i) {
+        const int y = Y0 + RS * i + yo;
         const double yh = a.sy * y + a.oy;
         double yp[kMaxSpatialDegree + 1];
         yp[0] = 1.0;
@@ -258,7 +278,7 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
         for (int b = 0; b < NB; ++b)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int f = 16 * b + 4 * g + e;
+                const int f = 16 * b + fo + e;
                 if (f < a.NF) {
                     double wgt = 0.0;
                     if (!want_d) {
@@ -286,13 +306,13 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
                 }
             }
         part += __shfl_xor(part, 16);
-        part += __shfl_xor(part, 32);
-        if (a.out != nullptr && g == 0 && x < a.W && y < y_end)
+        if (!PACK) part += __shfl_xor(part, 32);
+        if (a.out != nullptr && g_lead && x < a.W && y < y_end)
             a.out[(size_t)y * a.W + x] = (float)(part - (double)iv[i]);
     }
 }
 
-template <int NB, bool REG>
+template <int NB, bool REG, bool PACK = false>
 static int launch_f32_t(const ContractArgs& a, const float* frag, hipStream_t s) {
     constexpr int TH = f32_tile_h(NB);
     const int k = 2 * a.h + 1;
@@ -302,13 +322,17 @@ static int launch_f32_t(const ContractArgs& a, const float* frag, hipStream_t s)
     const int n_tiles = tiles_x * tiles_y;
     if (n_tiles == 0) return SVCONV_OK;
     if (g.lds_bytes > 64 * 1024) return fail(SVCONV_EUNSUPPORTED, "FP32 tile exceeds 64 KiB of LDS");
-    hipLaunchKernelGGL((contract_f32_kernel<NB, TH, REG>), dim3(n_tiles), dim3(256), g.lds_bytes, s,
-                       a, frag, k, g.n_rg, g.lds_pitch, g.lds_rows, g.lds_cols, tiles_x, n_tiles);
+    hipLaunchKernelGGL((contract_f32_kernel<NB, TH, REG, PACK>), dim3(n_tiles), dim3(256),
+                       g.lds_bytes, s, a, frag, k, g.n_rg, g.lds_pitch, g.lds_rows, g.lds_cols,
+                       tiles_x, n_tiles);
     return hip_status(hipGetLastError(), "contract_f32_kernel");
 }
 
 int launch_contract_f32(const ContractArgs& a, const float* frag, int nb, hipStream_t s) {
     const bool reg = (a.coef == nullptr);
+    if (nb == 1 && f32_packed(a.NF))
+        return reg ? launch_f32_t<1, true, true>(a, frag, s)
+                   : launch_f32_t<1, false, true>(a, frag, s);
     switch (nb) {
         case 1: return reg ? launch_f32_t<1, true>(a, frag, s) : launch_f32_t<1, false>(a, frag, s);
         case 2: return reg ? launch_f32_t<2, true>(a, frag, s) : launch_f32_t<2, false>(a, frag, s);

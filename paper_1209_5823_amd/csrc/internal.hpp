@@ -195,6 +195,10 @@ size_t f32_fragment_floats(int k, int nb);
 size_t lowp_fragment_elems(int k, int nb);  // hi and lo halves together
 F32Geometry f32_geometry(int k, int nb);
 LowpGeometry lowp_geometry(int k, int nb);
+// With at most 8 filters (f32_packed) the FP32 fragments and contraction take
+// the two-row packed layout; both sides decide it from NF alone, so a fragment
+// buffer built for NF filters serves every launch with the same NF.
+bool f32_packed(int NF);
 int build_f32_fragments(const float* F, int NF, int k, float* frag, hipStream_t s);
 int build_lowp_fragments(const float* F, int NF, int k, int fp16, float* scale,
                          uint16_t* frag, hipStream_t s, bool packed = false);

@@ -37,14 +37,19 @@ def test_loss_grad(svc, orc):
             assert np.array_equal(G, np.where(sel, 2 * D, 0).astype(np.float32))
 
 
+# 9 bases take one 16-filter block of the contraction; 6 bases (at most 8)
+# take its two-row packed form, whose basis responses come out of both halves
+# of the matrix-core accumulator
+@pytest.mark.parametrize("basis", [((0.7, 1.5), (2, 1)), ((1.5,), (2,))], ids=["n9", "n6"])
 @pytest.mark.parametrize("with_mask", [False, True])
-def test_normal_matrix_vs_oracle(svc, orc, with_mask):
-    R, C, a_star, B, (H, W, h, sig, deg, d_s) = small_case(orc)
+def test_normal_matrix_vs_oracle(svc, orc, with_mask, basis):
+    sig, deg = basis
+    R, C, a_star, B, (H, W, h, sig, deg, d_s) = small_case(orc, H=53, sig=sig, deg=deg)
     mask = None
     if with_mask:
         mask = (synth.uniform_image(H, W, seed=11) > -0.5).astype(np.uint8)
     JtJ_ref, _ = orc.normal_equations(R, None, h, B, d_s, mask=mask)
-    say("normal matrix", with_mask)
+    say("normal matrix", with_mask, len(B))
     with svc.Plan(H, W, h, sig, deg, d_s) as plan:
         JtJ = to_host(plan.normal_matrix(to_dev(R), None if mask is None else to_dev(mask)))
     err = np.abs(JtJ - JtJ_ref).max() / np.abs(JtJ_ref).max()
