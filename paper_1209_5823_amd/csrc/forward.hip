@@ -47,21 +47,21 @@ __device__ __forceinline__ void term_exponents(int m, int& i, int& j) {
     j = o;
 }
 
-static int pitch_16mod64(int cols) {
-    int p = 16;
-    while (p < cols) p += 64;
-    return p;
-}
-
 // ------------------------------------------------------ FP32 geometry ----
 
 constexpr int F32_TW = 64;   // output tile width: 4 waves x 16 columns
+// LDS row pitch in floats for every kernel width: at least the widest tile
+// row (64 + 2 kMaxHalfWidth samples) and 16 mod 64, so that the four rows a
+// B-operand read spans fall on disjoint banks; a fixed pitch makes every row
+// offset of the contraction an immediate.
+constexpr int F32_PITCH = 144;
+static_assert(F32_TW + 2 * kMaxHalfWidth <= F32_PITCH && F32_PITCH % 64 == 16, "FP32 LDS pitch");
 
 // Output rows per tile (= 16-pixel blocks per wave): fewer rows for more
 // filter blocks so that the float32 sub-chain and float64 total fit in 256
 // registers (two waves per SIMD) without spilling.  The two-row packed form
 // keeps the 8 rows of one block: 16 rows per tile measured slower.
-constexpr int f32_tile_h(int nb) { return nb >= 4 ? 3 : nb >= 2 ? 4 : 8; }
+constexpr int f32_tile_h(int nb) { return nb >= 3 ? 3 : nb >= 2 ? 4 : 8; }
 
 // Two-row packing: with at most 8 filters, rows 8..15 of the 16-row A operand
 // would be zeros.  They carry the same filters shifted down by one kernel row
@@ -80,7 +80,7 @@ F32Geometry f32_geometry(int k, int nb) {
     g.tile_h = f32_tile_h(nb);
     g.lds_rows = g.tile_h + 4 * g.n_rg - 1;
     g.lds_cols = g.tile_w + k - 1;
-    g.lds_pitch = pitch_16mod64(g.lds_cols);
+    g.lds_pitch = F32_PITCH;
     g.lds_bytes = (size_t)g.lds_rows * g.lds_pitch * 4 + (size_t)kMaxFilters * kMaxSpatialTerms * 4;
     return g;
 }
@@ -124,7 +124,7 @@ int build_f32_fragments(const float* F, int NF, int k, float* frag, hipStream_t 
 template <int NB, int TH, bool REG, bool PACK>
 __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
                                                            const float* __restrict__ frag, int k,
-                                                           int n_rg, int pitch, int rows, int cols,
+                                                           int n_rg, int rows, int cols,
                                                            int tiles_x, int n_tiles) {
     static_assert(!PACK || (NB == 1 && TH % 2 == 0), "packed form: one filter block, row pairs");
     // products per chunk and filter block, and the tile-row step between them
@@ -132,6 +132,7 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
     constexpr int RS = PACK ? 2 : 1;
     extern __shared__ __align__(16) float smem[];
     float* tile = smem;
+    constexpr int pitch = F32_PITCH;
     float* coef_s = smem + rows * pitch;
 
     const int tid = threadIdx.x;
@@ -146,16 +147,41 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
         for (int q = tid; q < a.NF * a.M; q += 256) coef_s[q] = a.coef[q];
 
     // Stage X[Y0-h .. Y0-h+rows) x [X0-h .. X0-h+cols) minus the pedestal;
-    // outside the image X is 0, so the staged value is -pedestal there.
-    for (int r = tid >> 6; r < rows; r += 4) {
-        const int gy = Y0 - h + r;
-        const bool row_in = (gy >= 0) && (gy < a.H);
-        const float* src = a.X + (size_t)(row_in ? gy : 0) * a.W;
-        for (int c = tid & 63; c < cols; c += 64) {
+    // outside the image X is 0, so the staged value is -pedestal there.  A
+    // lane covers columns c and c + 64 (cols <= 64 + 2 kMaxHalfWidth < 128)
+    // of every fourth row; the loads of F32_SB rows are issued together from
+    // clamped addresses and the masks apply when storing, so that a batch
+    // waits for memory once.
+    {
+        constexpr int F32_SB = 4;
+        int gxc[2];
+        bool cin[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int c = (tid & 63) + 64 * q;
             const int gx = X0 - h + c;
-            float v = 0.f;
-            if (row_in && gx >= 0 && gx < a.W) v = src[gx];
-            tile[r * pitch + c] = v - a.ped;
+            cin[q] = c < cols && gx >= 0 && gx < a.W;
+            gxc[q] = gx < 0 ? 0 : (gx < a.W ? gx : a.W - 1);
+        }
+        for (int r0 = tid >> 6; r0 < rows; r0 += 4 * F32_SB) {
+            float v[F32_SB][2];
+#pragma unroll
+            for (int sb = 0; sb < F32_SB; ++sb) {
+                const int gy = Y0 - h + r0 + 4 * sb;
+                const float* src = a.X + (size_t)(gy < 0 ? 0 : (gy < a.H ? gy : a.H - 1)) * a.W;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) v[sb][q] = src[gxc[q]];
+            }
+#pragma unroll
+            for (int sb = 0; sb < F32_SB; ++sb) {
+                const int r = r0 + 4 * sb, gy = Y0 - h + r;
+                const bool rin = gy >= 0 && gy < a.H;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int c = (tid & 63) + 64 * q;
+                    if (r < rows && c < cols) tile[r * pitch + c] = (rin && cin[q] ? v[sb][q] : 0.f) - a.ped;
+                }
+            }
         }
     }
     __syncthreads();
@@ -172,21 +198,24 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
     const bool g_lead = PACK ? ((g & 1) == 0) : (g == 0);
 
     // I at this lane's output pixels, loaded now so that its latency hides
-    // behind the contraction
+    // behind the contraction; clamped addresses (X stands in when there is no
+    // I), the values of pixels outside the band are never used
     float iv[RI];
+    {
+        const float* ip = (a.I != nullptr) ? a.I : a.X;
+        const int x = X0 + 16 * w + j, xc = x < a.W ? x : a.W - 1;
 #pragma unroll
-    for (int i = 0; i < RI; ++i) {
-        const int x = X0 + 16 * w + j, y = Y0 + RS * i + yo;
-        iv[i] = (a.I != nullptr && a.out != nullptr && g_lead && x < a.W && y < y_end)
-                    ? a.I[(size_t)y * a.W + x] : 0.f;
+        for (int i = 0; i < RI; ++i) {
+            const int y = Y0 + RS * i + yo, yc = y < y_end ? y : y_end - 1;
+            iv[i] = ip[(size_t)yc * a.W + xc];
+        }
     }
 
     // T_f accumulates on the matrix cores in float32 over sub-chains of 4
     // chunks (16 taps), and every sub-chain is added into a float64 total.
     // Long float32 chains over all k^2 taps lose up to a few ulp of T at
     // bright stars; short chains keep the rounding of each partial sum small
-    // and the float64 total adds none.  The A fragments of the next group of
-    // 4 chunks are requested from L2 while this group's products run.
+    // and the float64 total adds none.
     double tot[NB][RI][4];
 #pragma unroll
     for (int b = 0; b < NB; ++b)
@@ -195,37 +224,28 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
 #pragma unroll
             for (int e = 0; e < 4; ++e) tot[b][i][e] = 0.0;
 
+    // The A fragments of a group of 4 chunks go to one of two register sets
+    // while the other set's group runs: the loop takes two groups per turn so
+    // that no set is copied (a copy of a value still in flight waits for it),
+    // and a scheduling barrier keeps each group's loads ahead of the products
+    // of the group before it.
     const float* fp = frag + lane;
-    float fa[4][NB];
+    auto load_group = [&](float (&f)[4][NB], int c0) {
+        const int cc = (c0 < n_chunks) ? c0 : n_chunks - 4;   // past the end: unused
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int b = 0; b < NB; ++b) fa[u][b] = fp[(size_t)(u * NB + b) * 64];
-
+            for (int b = 0; b < NB; ++b) f[u][b] = fp[(size_t)((cc + u) * NB + b) * 64];
+    };
     const float* tb = tile + g * pitch + 16 * w + j;
     int r = 0, du = 0;       // row group and column of the chunk being issued
-    for (int c0 = 0; c0 < n_chunks; c0 += 4) {
-        // next group's fragments: chunks +4, +5 now, +6, +7 once the first two
-        // chunks of this group no longer need their registers
-        const int cn = (c0 + 4 < n_chunks) ? c0 + 4 : c0;
-        float na[2][NB], nb2[2][NB];
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-            for (int b = 0; b < NB; ++b) na[u][b] = fp[(size_t)((cn + u) * NB + b) * 64];
-        f4 acc[NB][RI];
+    auto run_group = [&](const float (&f)[4][NB], f4 (&acc)[NB][RI]) {
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
             for (int i = 0; i < RI; ++i) acc[b][i] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            if (u == 2) {
-#pragma unroll
-                for (int v = 0; v < 2; ++v)
-#pragma unroll
-                    for (int b = 0; b < NB; ++b) nb2[v][b] = fp[(size_t)((cn + 2 + v) * NB + b) * 64];
-            }
             // padded chunks past the last row group read row group n_rg - 1
             // (in the tile) with zero weights
             const float* rb = tb + 4 * (r < n_rg ? r : n_rg - 1) * pitch + du;
@@ -236,25 +256,52 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
             for (int i = 0; i < RI; ++i)
 #pragma unroll
                 for (int b = 0; b < NB; ++b)
-                    acc[b][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[u][b], xb[i], acc[b][i], 0, 0, 0);
+                    acc[b][i] = __builtin_amdgcn_mfma_f32_16x16x4f32(f[u][b], xb[i], acc[b][i], 0, 0, 0);
             if (++du == k) {
                 du = 0;
                 ++r;
             }
         }
+    };
+    auto add_total = [&](const f4 (&acc)[NB][RI]) {
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
             for (int i = 0; i < RI; ++i)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) tot[b][i][e] += (double)acc[b][i][e];
+    };
+    // With one or two filter blocks the sub-chains of the two groups of a turn
+    // are added in float32 (one more rounding per 32 taps) before their sum
+    // goes into the float64 total: half the conversions and float64 adds.
+    constexpr bool PAIR = NB <= 2;
+    // (The loop body is one basic block: loads in a block of their own would
+    // be sunk next to their first use.)
+    float fA[4][NB], fB[4][NB];
+    load_group(fA, 0);
+    int c0 = 0;
+    for (; c0 + 8 <= n_chunks; c0 += 8) {
+        load_group(fB, c0 + 4);
+        if (NB < 3) __builtin_amdgcn_sched_barrier(0);
+        f4 accA[NB][RI];
+        run_group(fA, accA);
+        if (!PAIR) add_total(accA);
+        load_group(fA, c0 + 8);
+        if (NB < 3) __builtin_amdgcn_sched_barrier(0);
+        f4 accB[NB][RI];
+        run_group(fB, accB);
+        if (PAIR) {
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            fa[0][b] = na[0][b];
-            fa[1][b] = na[1][b];
-            fa[2][b] = nb2[0][b];
-            fa[3][b] = nb2[1][b];
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int i = 0; i < RI; ++i) accB[b][i] += accA[b][i];
         }
+        add_total(accB);
+    }
+    if (c0 < n_chunks) {   // an odd number of groups
+        f4 accA[NB][RI];
+        run_group(fA, accA);
+        add_total(accA);
     }
 
     // Epilogue in float64: out = sum_f w_f (T_f + ped * beta_f) - I.
@@ -265,6 +312,36 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
 #pragma unroll
     for (int q = 1; q <= kMaxSpatialDegree; ++q) xp[q] = xp[q - 1] * xh;
 
+    // Per-filter terms of this lane's accumulator entries, formed once per
+    // tile: ped * beta_f (loaded together from clamped indices) and, in the
+    // regrouped form, the x power of monomial f and the exponent of its y power.
+    double pbf[NB][4], wxf[NB][4];
+    int jyf[NB][4];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int f = 16 * b + fo + e;
+            pbf[b][e] = 0.0;
+            wxf[b][e] = 0.0;
+            jyf[b][e] = 0;
+            if (REG && want_d) {
+                int ii, jj;
+                term_exponents(f < a.NF ? f : 0, ii, jj);
+                wxf[b][e] = ipow_d(xh, ii);
+                jyf[b][e] = jj;
+            }
+        }
+    if (a.beta != nullptr) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int f = 16 * b + fo + e;
+                pbf[b][e] = (double)a.ped * a.beta[f < a.NF ? f : a.NF - 1];
+            }
+    }
+
 #pragma unroll
     for (int i = 0; i < RI; ++i) {
         const int y = Y0 + RS * i + yo;
@@ -273,6 +350,8 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
         yp[0] = 1.0;
 #pragma unroll
         for (int q = 1; q <= kMaxSpatialDegree; ++q) yp[q] = yp[q - 1] * yh;
+        // yh^j for j <= 7 from its binary digits, without branches
+        const double yh2 = yh * yh, yh4 = yh2 * yh2;
         double part = 0.0;
 #pragma unroll
         for (int b = 0; b < NB; ++b)
@@ -283,9 +362,9 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
                     double wgt = 0.0;
                     if (!want_d) {
                     } else if (REG) {
-                        int ii, jj;
-                        term_exponents(f, ii, jj);
-                        wgt = ipow_d(xh, ii) * ipow_d(yh, jj);
+                        const int jj = jyf[b][e];
+                        wgt = wxf[b][e] * (((jj & 1) ? yh : 1.0) * ((jj & 2) ? yh2 : 1.0)) *
+                              ((jj & 4) ? yh4 : 1.0);
                     } else {
                         const float* cf = coef_s + f * a.M;
                         int m = 0;
@@ -298,7 +377,7 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
                             m += tt + 1;
                         }
                     }
-                    const double pb = (a.beta != nullptr) ? (double)a.ped * a.beta[f] : 0.0;
+                    const double pb = pbf[b][e];
                     part += wgt * (tot[b][i][e] + pb);
                     if (a.tout != nullptr && x < a.W && y < y_end)
                         a.tout[(size_t)f * a.n_rows * a.W + (size_t)(y - a.y_begin) * a.W + x] =
@@ -308,7 +387,7 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
         part += __shfl_xor(part, 16);
         if (!PACK) part += __shfl_xor(part, 32);
         if (a.out != nullptr && g_lead && x < a.W && y < y_end)
-            a.out[(size_t)y * a.W + x] = (float)(part - (double)iv[i]);
+            a.out[(size_t)y * a.W + x] = (float)(part - (a.I != nullptr ? (double)iv[i] : 0.0));
     }
 }
 
@@ -323,7 +402,7 @@ static int launch_f32_t(const ContractArgs& a, const float* frag, hipStream_t s)
     if (n_tiles == 0) return SVCONV_OK;
     if (g.lds_bytes > 64 * 1024) return fail(SVCONV_EUNSUPPORTED, "FP32 tile exceeds 64 KiB of LDS");
     hipLaunchKernelGGL((contract_f32_kernel<NB, TH, REG, PACK>), dim3(n_tiles), dim3(256),
-                       g.lds_bytes, s, a, frag, k, g.n_rg, g.lds_pitch, g.lds_rows, g.lds_cols,
+                       g.lds_bytes, s, a, frag, k, g.n_rg, g.lds_rows, g.lds_cols,
                        tiles_x, n_tiles);
     return hip_status(hipGetLastError(), "contract_f32_kernel");
 }
