@@ -213,13 +213,19 @@ __device__ __forceinline__ void lp_stage(const ContractArgs& a, uint16_t* hiT, u
         const bool row_in = (gy >= 0) && (gy < a.H);
         const float* src = a.X + (size_t)(row_in ? gy : 0) * a.W;
         for (int c2 = tid & 63; c2 < half; c2 += 64) {
+            // both loads from clamped addresses, the masks applied after
+            float xr[2];
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                const int gx = X0 - a.h + 2 * c2 + v;
+                xr[v] = src[gx < 0 ? 0 : (gx < a.W ? gx : a.W - 1)];
+            }
             uint32_t hw = 0, lw = 0;
 #pragma unroll
             for (int v = 0; v < 2; ++v) {
                 const int c = 2 * c2 + v;
                 const int gx = X0 - a.h + c;
-                float x = 0.f;
-                if (row_in && gx >= 0 && gx < a.W && c < cols) x = src[gx];
+                const float x = (row_in && gx >= 0 && gx < a.W) ? xr[v] : 0.f;
                 const float xv = (c < cols) ? (x - a.ped) * xscale : 0.f;
                 uint32_t hi, lo;
                 split16<FP16>(xv, hi, lo);
@@ -317,15 +323,25 @@ __device__ __forceinline__ void lp_rowgroup(f4 (&acc)[NB][LP_TP], const uint16_t
     }
 }
 
-// I at the lane's pixels (0 where not needed).
-__device__ __forceinline__ void lp_fetch_i(const ContractArgs& a, float (&iv)[LP_TP], int X0, int Y0,
-                                           int s, int g, int j) {
-    const int y = Y0 + j;
+// I at the lane's pixels, all requested together from clamped addresses (X
+// stands in when there is no I); values of pixels outside the band, or with
+// no I, are never used.
+template <int N>
+__device__ __forceinline__ void lp_fetch_i(const ContractArgs& a, float (&iv)[N], int x0, int dx,
+                                           int y) {
+    const float* ip = a.I ? a.I : a.X;
+    const int y_last = a.y_begin + a.n_rows - 1;
+    const size_t row = (size_t)(y < y_last ? y : y_last) * a.W;
 #pragma unroll
-    for (int i = 0; i < LP_TP; ++i) {
-        const int x = X0 + s + 8 * i;
-        iv[i] = (a.I && g == 0 && x < a.W && y < a.y_begin + a.n_rows) ? a.I[(size_t)y * a.W + x] : 0.f;
+    for (int i = 0; i < N; ++i) {
+        const int x = x0 + dx * i;
+        iv[i] = ip[row + (x < a.W ? x : a.W - 1)];
     }
+}
+
+// x^e for 0 <= e <= 7 from the binary digits of e (no branches)
+__device__ __forceinline__ float lp_pow(float x, float x2, float x4, int e) {
+    return ((e & 1) ? x : 1.f) * ((e & 2) ? x2 : 1.f) * ((e & 4) ? x4 : 1.f);
 }
 
 // Epilogue.  With U_m(p) = sum_f coef[f][m] T_f(p) / (s_f xscale) and
@@ -348,21 +364,27 @@ __device__ __forceinline__ void lp_epilogue(const ContractArgs& a, const f4 (&ac
     // I at the lane's pixels, requested first so that the matrix-core work
     // below hides its latency (the contraction's registers are free by now)
     float iv[LP_TP];
-    lp_fetch_i(a, iv, X0, Y0, s, g, j);
     const int y = Y0 + j;
+    lp_fetch_i(a, iv, X0 + s, 8, y);
     const float yh = (float)(a.sy * y + a.oy);
     // exponents of the lane's four terms per term block
-    int ei[MB][4], ej[MB][4];
+    // and the y power of each, formed once
+    int ei[MB][4];
+    float py[MB][4];
+    {
+        const float yh2 = yh * yh, yh4 = yh2 * yh2;
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
+        for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int m = 16 * mb + 4 * g + e;
-            int tt = 0;
-            while ((tt + 1) * (tt + 2) / 2 <= m) ++tt;
-            ej[mb][e] = m - tt * (tt + 1) / 2;
-            ei[mb][e] = tt - ej[mb][e];
-        }
+            for (int e = 0; e < 4; ++e) {
+                const int m = 16 * mb + 4 * g + e;
+                int tt = 0;
+                while ((tt + 1) * (tt + 2) / 2 <= m) ++tt;
+                const int ej = m - tt * (tt + 1) / 2;
+                ei[mb][e] = tt - ej;
+                py[mb][e] = lp_pow(yh, yh2, yh4, ej);
+            }
+    }
 #pragma unroll
     for (int i = 0; i < LP_TP; ++i) {
         f4 u[MB];
@@ -377,23 +399,20 @@ __device__ __forceinline__ void lp_epilogue(const ContractArgs& a, const f4 (&ac
                     for (int mb = 0; mb < MB; ++mb)
                         u[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[b][e][mb], acc[b][i][e], u[mb], 0, 0, 0);
         const int x = X0 + s + 8 * i;
-        const float xh = (float)(a.sx * x + a.ox);
+        const float xh = (float)(a.sx * x + a.ox), xh2 = xh * xh, xh4 = xh2 * xh2;
         float part = 0.f;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int m = 16 * mb + 4 * g + e;
-                if (m < a.M) {
-                    float px = 1.f, py = 1.f;
-                    for (int q = 0; q < ei[mb][e]; ++q) px *= xh;
-                    for (int q = 0; q < ej[mb][e]; ++q) py *= yh;
-                    part += px * py * (u[mb][e] + a.ped * gamma_s[m]);
-                }
+                if (m < a.M)
+                    part += lp_pow(xh, xh2, xh4, ei[mb][e]) * py[mb][e] * (u[mb][e] + a.ped * gamma_s[m]);
             }
         part += __shfl_xor(part, 16);
         part += __shfl_xor(part, 32);
-        if (g == 0 && x < a.W && y < a.y_begin + a.n_rows) a.out[(size_t)y * a.W + x] = part - iv[i];
+        if (g == 0 && x < a.W && y < a.y_begin + a.n_rows)
+            a.out[(size_t)y * a.W + x] = part - (a.I ? iv[i] : 0.f);
     }
 }
 
@@ -535,20 +554,19 @@ __device__ __forceinline__ void lp_epilogue_packed(const ContractArgs& a, const 
     const int y = Y0 + j;
     const int xoff = 2 * w + (g >> 1);
     float iv[LP_PB];
-#pragma unroll
-    for (int i = 0; i < LP_PB; ++i) {
-        const int x = X0 + xoff + 16 * i;
-        iv[i] = (a.I && (g & 1) == 0 && x < a.W && y < a.y_begin + a.n_rows) ? a.I[(size_t)y * a.W + x] : 0.f;
-    }
-    const float yh = (float)(a.sy * y + a.oy);
-    int ei[4], ej[4];
+    lp_fetch_i(a, iv, X0 + xoff, 16, y);
+    const float yh = (float)(a.sy * y + a.oy), yh2 = yh * yh, yh4 = yh2 * yh2;
+    // x exponent and y power of the lane's four terms
+    int ei[4];
+    float py[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int m = 4 * (g & 1) + e;
         int tt = 0;
         while ((tt + 1) * (tt + 2) / 2 <= m) ++tt;
-        ej[e] = m - tt * (tt + 1) / 2;
-        ei[e] = tt - ej[e];
+        const int ej = m - tt * (tt + 1) / 2;
+        ei[e] = tt - ej;
+        py[e] = lp_pow(yh, yh2, yh4, ej);
     }
 #pragma unroll
     for (int i = 0; i < LP_PB; ++i) {
@@ -556,20 +574,16 @@ __device__ __forceinline__ void lp_epilogue_packed(const ContractArgs& a, const 
 #pragma unroll
         for (int e = 0; e < 4; ++e) u = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[e], acc[i][e], u, 0, 0, 0);
         const int x = X0 + xoff + 16 * i;
-        const float xh = (float)(a.sx * x + a.ox);
+        const float xh = (float)(a.sx * x + a.ox), xh2 = xh * xh, xh4 = xh2 * xh2;
         float part = 0.f;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int m = 4 * (g & 1) + e;
-            if (m < a.M) {
-                float px = 1.f, py = 1.f;
-                for (int q = 0; q < ei[e]; ++q) px *= xh;
-                for (int q = 0; q < ej[e]; ++q) py *= yh;
-                part += px * py * (u[e] + a.ped * gamma_s[m]);
-            }
+            if (m < a.M) part += lp_pow(xh, xh2, xh4, ei[e]) * py[e] * (u[e] + a.ped * gamma_s[m]);
         }
         part += __shfl_xor(part, 16);
-        if ((g & 1) == 0 && x < a.W && y < a.y_begin + a.n_rows) a.out[(size_t)y * a.W + x] = part - iv[i];
+        if ((g & 1) == 0 && x < a.W && y < a.y_begin + a.n_rows)
+            a.out[(size_t)y * a.W + x] = part - (a.I ? iv[i] : 0.f);
     }
 }
 
@@ -692,9 +706,27 @@ __global__ __launch_bounds__(512, 1) void contract_lowp_resident_kernel(
     }
 
     // raw input of a tile: element pair (2 e, 2 e + 1), e = tid + 512 p, of
-    // the rows x pitch tile (pitch is even), stored as one 32-bit word per part
+    // the rows x pitch tile (pitch is even), stored as one 32-bit word per part.
+    // The loads go out together from clamped addresses; the masks (X = 0
+    // outside the image) apply when the tile is stored.
     float pf[LP_PF][2];
     auto fetch = [&](int t) {
+        const int X0 = (t % tiles_x) * LP_TW;
+        const int Y0 = a.y_begin + (t / tiles_x) * LP_TH;
+#pragma unroll
+        for (int p = 0; p < LP_PF; ++p) {
+            const int e2 = 2 * (tid + 512 * p);
+            const int r = e2 / pitch, c = e2 - r * pitch;
+            const int gy = Y0 - a.h + r, gx = X0 - a.h + c;
+            const size_t row = (size_t)(gy < 0 ? 0 : (gy < a.H ? gy : a.H - 1)) * a.W;
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                const int xv = gx + v;
+                pf[p][v] = a.X[row + (xv < 0 ? 0 : (xv < a.W ? xv : a.W - 1))];
+            }
+        }
+    };
+    auto store = [&](int t) {
         const int X0 = (t % tiles_x) * LP_TW;
         const int Y0 = a.y_begin + (t / tiles_x) * LP_TH;
         const int cols = 8 * (LP_TP + LP_NQ);
@@ -702,28 +734,14 @@ __global__ __launch_bounds__(512, 1) void contract_lowp_resident_kernel(
         for (int p = 0; p < LP_PF; ++p) {
             const int e2 = 2 * (tid + 512 * p);
             const int r = e2 / pitch, c = e2 - r * pitch;
-            const int gy = Y0 - a.h + r, gx = X0 - a.h + c;
-            const bool row_ok = r < rows && gy >= 0 && gy < a.H;
-#pragma unroll
-            for (int v = 0; v < 2; ++v) {
-                float x = 0.f;
-                if (row_ok && c + v < cols && gx + v >= 0 && gx + v < a.W)
-                    x = a.X[(size_t)gy * a.W + gx + v];
-                pf[p][v] = x;
-            }
-        }
-    };
-    auto store = [&]() {
-        const int cols = 8 * (LP_TP + LP_NQ);
-#pragma unroll
-        for (int p = 0; p < LP_PF; ++p) {
-            const int e2 = 2 * (tid + 512 * p);
-            const int r = e2 / pitch, c = e2 - r * pitch;
             if (r < rows) {
+                const int gy = Y0 - a.h + r, gx = X0 - a.h + c;
+                const bool row_in = gy >= 0 && gy < a.H;
                 uint32_t hw = 0, lw = 0;
 #pragma unroll
                 for (int v = 0; v < 2; ++v) {
-                    const float xv = (c + v < cols) ? (pf[p][v] - a.ped) * xscale : 0.f;
+                    const bool in = row_in && gx + v >= 0 && gx + v < a.W;
+                    const float xv = (c + v < cols) ? ((in ? pf[p][v] : 0.f) - a.ped) * xscale : 0.f;
                     uint32_t hi, lo;
                     split16<FP16>(xv, hi, lo);
                     hw |= hi << (16 * v);
@@ -737,7 +755,7 @@ __global__ __launch_bounds__(512, 1) void contract_lowp_resident_kernel(
     fetch(t_begin);
     for (int t = t_begin; t < t_end; ++t) {
         __syncthreads();           // previous tile's LDS reads are done
-        store();
+        store(t);
         __syncthreads();           // tile (and, first time, table) visible
         const int X0 = (t % tiles_x) * LP_TW;
         const int Y0 = a.y_begin + (t / tiles_x) * LP_TH;
