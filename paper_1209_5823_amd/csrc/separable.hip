@@ -118,13 +118,29 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
     const int Y0 = a.y_begin + (t / a.tiles_x) * TH;
     const int y_end = min(a.H, a.y_begin + a.n_rows);
 
-    // stage R - s; outside the image R is 0, so the staged value is -s there
-    for (int q = tid; q < RA * CA; q += NT) {
-        const int r = q / CA, c = q - r * CA;
-        const int gy = Y0 - H + r, gx = X0 - H + c;
-        float v = 0.f;
-        if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) v = a.X[(size_t)gy * a.W + gx];
-        tile[r * TP + c] = v - a.ped;
+    // stage R - s; outside the image R is 0, so the staged value is -s there.
+    // The loads of SEP_SB elements per thread are issued together from
+    // clamped addresses and the masks apply when storing, so that a batch
+    // waits for memory once.
+    constexpr int SEP_SB = 8;
+    for (int q0 = tid; q0 < RA * CA; q0 += NT * SEP_SB) {
+        float v[SEP_SB];
+#pragma unroll
+        for (int sb = 0; sb < SEP_SB; ++sb) {
+            const int q = q0 + NT * sb;
+            const int r = q / CA, c = q - r * CA;
+            const int gy = Y0 - H + r, gx = X0 - H + c;
+            v[sb] = a.X[(size_t)(gy < 0 ? 0 : (gy < a.H ? gy : a.H - 1)) * a.W +
+                        (gx < 0 ? 0 : (gx < a.W ? gx : a.W - 1))];
+        }
+#pragma unroll
+        for (int sb = 0; sb < SEP_SB; ++sb) {
+            const int q = q0 + NT * sb;
+            const int r = q / CA, c = q - r * CA;
+            const int gy = Y0 - H + r, gx = X0 - H + c;
+            const bool in = gy >= 0 && gy < a.H && gx >= 0 && gx < a.W;
+            if (q < RA * CA) tile[r * TP + c] = (in ? v[sb] : 0.f) - a.ped;
+        }
     }
 
     const int lane = tid & 63, w = tid >> 6;
@@ -220,6 +236,15 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
         }
     }
     if (!TONLY && x < a.W) {
+        // I of the thread's rows, requested together from clamped rows (X
+        // stands in when there is no I; unused values are never read)
+        float ivr[RPT];
+        const float* ip = a.I ? a.I : a.X;
+#pragma unroll
+        for (int o = 0; o < RPT; ++o) {
+            const int y = Y0 + RPT * w + o;
+            ivr[o] = ip[(size_t)(y < y_end ? y : y_end - 1) * a.W + x];
+        }
         // pedestal restore: s sum_n beta_n c_n = s sum_m gamma_m P_m
         double cy[DSM + 1];
         coef_in_x<DSM>(as_const(a.gammap), xpow, cy);
@@ -231,7 +256,7 @@ __global__ __launch_bounds__(64 * SEP_NW) void contract_sep_kernel(SepArgs a) {
 #pragma unroll
                 for (int q = DSM - 1; q >= 0; --q) pg = fma(pg, yh[o], cy[q]);
                 const size_t idx = (size_t)y * a.W + x;
-                const double iv = a.I ? (double)a.I[idx] : 0.0;
+                const double iv = a.I ? (double)ivr[o] : 0.0;
                 a.out[idx] = (float)(fma((double)a.ped, pg, dacc[o]) - iv);
             }
         }

@@ -120,12 +120,27 @@ __global__ __launch_bounds__(64 * SA_NW) void adjoint_a_sep_kernel(SepAdjArgs a)
             for (int ty = ty0; ty < ty1; ++ty) {
                 const int Y0 = ty * SA_TH;
                 __syncthreads();   // V cleared / previous tile's rc consumed
-                for (int q = tid; q < RA * CA; q += NT) {
-                    const int r = q / CA, c = q - r * CA;
-                    const int gy = Y0 - H + r, gx = X0 - H + c;
-                    float v = 0.f;
-                    if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) v = a.R[(size_t)gy * a.W + gx];
-                    tile[r * TP + c] = v - a.ped;
+                // stage R - s: the loads of SA_SB elements per thread go out
+                // together from clamped addresses, the masks apply at the store
+                constexpr int SA_SB = 8;
+                for (int q0 = tid; q0 < RA * CA; q0 += NT * SA_SB) {
+                    float v[SA_SB];
+#pragma unroll
+                    for (int sb = 0; sb < SA_SB; ++sb) {
+                        const int q = q0 + NT * sb;
+                        const int r = q / CA, c = q - r * CA;
+                        const int gy = Y0 - H + r, gx = X0 - H + c;
+                        v[sb] = a.R[(size_t)(gy < 0 ? 0 : (gy < a.H ? gy : a.H - 1)) * a.W +
+                                    (gx < 0 ? 0 : (gx < a.W ? gx : a.W - 1))];
+                    }
+#pragma unroll
+                    for (int sb = 0; sb < SA_SB; ++sb) {
+                        const int q = q0 + NT * sb;
+                        const int r = q / CA, c = q - r * CA;
+                        const int gy = Y0 - H + r, gx = X0 - H + c;
+                        const bool in = gy >= 0 && gy < a.H && gx >= 0 && gx < a.W;
+                        if (q < RA * CA) tile[r * TP + c] = (in ? v[sb] : 0.f) - a.ped;
+                    }
                 }
                 __syncthreads();
                 // row pass (as in the forward)
@@ -162,11 +177,21 @@ __global__ __launch_bounds__(64 * SA_NW) void adjoint_a_sep_kernel(SepAdjArgs a)
                 __syncthreads();
                 // column pass per basis, moments of G T_n over this thread's rows
                 double gv[SA_RPT], yv[SA_RPT];
+                {
+                    // requested together from clamped addresses, masked after
+                    float gr[SA_RPT];
+                    const int xc = x < a.W ? x : a.W - 1;
 #pragma unroll
-                for (int o = 0; o < SA_RPT; ++o) {
-                    const int y = Y0 + SA_RPT * w + o;
-                    gv[o] = (x < a.W && y < a.H) ? (double)a.G[(size_t)y * a.W + x] : 0.0;
-                    yv[o] = a.sy * y + a.oy;
+                    for (int o = 0; o < SA_RPT; ++o) {
+                        const int y = Y0 + SA_RPT * w + o;
+                        gr[o] = a.G[(size_t)(y < a.H ? y : a.H - 1) * a.W + xc];
+                    }
+#pragma unroll
+                    for (int o = 0; o < SA_RPT; ++o) {
+                        const int y = Y0 + SA_RPT * w + o;
+                        gv[o] = (x < a.W && y < a.H) ? (double)gr[o] : 0.0;
+                        yv[o] = a.sy * y + a.oy;
+                    }
                 }
                 if (first) {
                     double ones[SA_RPT];
@@ -399,7 +424,9 @@ __global__ __launch_bounds__(SR_NT, SR_WG_PER_CU) void adjoint_r_sep_kernel(SepR
         for (int q = tid; q < RA * CA; q += SR_NT) {
             const int r = q / CA, c = q - r * CA;
             const int gy = Y0 - H + r, gx = X0 - H + c;
-            gt[r * CP + c] = (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) ? a.G[(size_t)gy * a.W + gx] : 0.f;
+            const float v = a.G[(size_t)(gy < 0 ? 0 : (gy < a.H ? gy : a.H - 1)) * a.W +
+                                (gx < 0 ? 0 : (gx < a.W ? gx : a.W - 1))];
+            gt[r * CP + c] = (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) ? v : 0.f;
         }
     // row-pass role: output row rr, columns q8 .. q8 + 7
     const int rr = tid >> 3, q8 = (tid & 7) * SR_RPT;
@@ -441,8 +468,11 @@ __global__ __launch_bounds__(SR_NT, SR_WG_PER_CU) void adjoint_r_sep_kernel(SepR
                     for (int jj = a.d_s; jj >= 0; --jj) cn = fma(cn, yh, cyt[c * DSM + jj]);
                     float gv;
                     if (SR_GLOBAL_G) {
+                        // clamped address, masked after (no branch around the load)
                         const int gy = Y0 - H + r, gx = X0 - H + c;
-                        gv = (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) ? a.G[(size_t)gy * a.W + gx] : 0.f;
+                        const float v = a.G[(size_t)(gy < 0 ? 0 : (gy < a.H ? gy : a.H - 1)) * a.W +
+                                            (gx < 0 ? 0 : (gx < a.W ? gx : a.W - 1))];
+                        gv = (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) ? v : 0.f;
                     } else {
                         gv = gt[r * CP + c];
                     }
