@@ -51,7 +51,8 @@ static AdjointQGeometry aq_geometry(int H, int W, int k, int M) {
     if (cap < 1) cap = 1;
     g.n_wg = g.n_tiles < 512 ? g.n_tiles : 512;
     if (g.n_wg > cap) g.n_wg = cap;
-    g.lds_bytes = (size_t)g.rows * g.pitch * sizeof(float);
+    // R tile plus its halo, then the G tile
+    g.lds_bytes = ((size_t)g.rows * g.pitch + AQ_TW * AQ_TH) * sizeof(float);
     return g;
 }
 
@@ -60,10 +61,9 @@ size_t adjoint_scratch_doubles(int H, int W, int k, int M) {
     return (size_t)g.n_wg * 16 * g.mb * g.taps_pad + (size_t)16 * g.mb * g.taps_pad;
 }
 
-__device__ __forceinline__ double ipow_q(double x, int e) {
-    double r = 1.0;
-    for (int t = 0; t < e; ++t) r *= x;
-    return r;
+// x^e for 0 <= e <= 7 from the binary digits of e (no branches)
+__device__ __forceinline__ double pow_q(double x, double x2, double x4, int e) {
+    return ((e & 1) ? x : 1.0) * ((e & 2) ? x2 : 1.0) * ((e & 4) ? x4 : 1.0);
 }
 
 template <int MB, int TBW>
@@ -72,6 +72,7 @@ __global__ __launch_bounds__(256, 2) void adjoint_q_kernel(
     double sx, double ox, double sy, double oy, int tiles_x, int n_tiles, int n_wg, int taps_pad,
     int pitch, int rows, int cols, double* __restrict__ part) {
     extern __shared__ __align__(16) float tile[];
+    float* gtile = tile + rows * pitch;   // G of the tile's AQ_TH x AQ_TW pixels
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int kq = lane >> 4, j = lane & 15;
     const int kk = k * k;
@@ -109,13 +110,35 @@ __global__ __launch_bounds__(256, 2) void adjoint_q_kernel(
         const int X0 = (ti % tiles_x) * AQ_TW;
         const int Y0 = (ti / tiles_x) * AQ_TH;
         __syncthreads();   // the previous tile's reads are done
-        for (int r = tid >> 6; r < rows; r += AQ_WAVES) {
-            const int gy = Y0 - h + r;
-            const bool row_in = gy >= 0 && gy < H;
-            const float* src = R + (size_t)(row_in ? gy : 0) * W;
-            for (int c = tid & 63; c < cols; c += 64) {
-                const int gx = X0 - h + c;
-                tile[r * pitch + c] = (row_in && gx >= 0 && gx < W) ? src[gx] : 0.f;
+        // R with its halo and G: the loads of AQ_SB elements per thread go
+        // out together from clamped addresses, the masks apply at the store
+        constexpr int AQ_SB = 8;
+        for (int q0 = tid; q0 < rows * cols; q0 += 256 * AQ_SB) {
+            float v[AQ_SB];
+#pragma unroll
+            for (int sb = 0; sb < AQ_SB; ++sb) {
+                const int q = q0 + 256 * sb, r = q / cols, c = q - r * cols;
+                const int gy = Y0 - h + r, gx = X0 - h + c;
+                v[sb] = R[(size_t)(gy < 0 ? 0 : (gy < H ? gy : H - 1)) * W + (gx < 0 ? 0 : (gx < W ? gx : W - 1))];
+            }
+#pragma unroll
+            for (int sb = 0; sb < AQ_SB; ++sb) {
+                const int q = q0 + 256 * sb, r = q / cols, c = q - r * cols;
+                const int gy = Y0 - h + r, gx = X0 - h + c;
+                if (q < rows * cols) tile[r * pitch + c] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? v[sb] : 0.f;
+            }
+        }
+        {
+            float v[AQ_TW * AQ_TH / 256];
+#pragma unroll
+            for (int sb = 0; sb < AQ_TW * AQ_TH / 256; ++sb) {
+                const int p = tid + 256 * sb, x = X0 + p % AQ_TW, y = Y0 + p / AQ_TW;
+                v[sb] = G[(size_t)(y < H ? y : H - 1) * W + (x < W ? x : W - 1)];
+            }
+#pragma unroll
+            for (int sb = 0; sb < AQ_TW * AQ_TH / 256; ++sb) {
+                const int p = tid + 256 * sb, x = X0 + p % AQ_TW, y = Y0 + p / AQ_TW;
+                gtile[p] = (x < W && y < H) ? v[sb] : 0.f;
             }
         }
         __syncthreads();
@@ -130,13 +153,14 @@ __global__ __launch_bounds__(256, 2) void adjoint_q_kernel(
             const int p = 4 * s + kq;
             const int px = p % AQ_TW, py = p / AQ_TW;
             const int x = X0 + px, y = Y0 + py;
-            const bool in = (x < W) && (y < H);
-            const double gv = in ? (double)G[(size_t)y * W + x] : 0.0;
+            const double gv = (double)gtile[p];
             const double xh = sx * x + ox, yh = sy * y + oy;
+            const double xh2 = xh * xh, xh4 = xh2 * xh2, yh2 = yh * yh, yh4 = yh2 * yh2;
             float af[MB];
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb)
-                af[mb] = mv[mb] ? (float)(gv * ipow_q(xh, ei[mb]) * ipow_q(yh, ej[mb])) : 0.f;
+                af[mb] = mv[mb] ? (float)(gv * pow_q(xh, xh2, xh4, ei[mb]) * pow_q(yh, yh2, yh4, ej[mb]))
+                                : 0.f;
             const float* tb = tile + py * pitch + px;
 #pragma unroll
             for (int t = 0; t < TBW; ++t) {
