@@ -295,13 +295,22 @@ __global__ __launch_bounds__(SM_NT, smm_waves_per_simd(ADJ, DSM)) void contract_
         float S[DSM + 1];
 #pragma unroll
         for (int q = 0; q <= DSM; ++q) S[q] = 0.f;
+        // all eight loads first (clamped addresses), the masks after: a load
+        // next to its mask is compiled into a branch of its own and waited for
+        float gl[2][4];
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int y = Y0 + 16 * (rb0 + b) + 4 * g4 + e;
-                const float gl = a.I[(size_t)min(y, a.H - 1) * a.W + min(x, a.W - 1)];
-                gq[b][e] = (x < a.W && y < y_end) ? gl : 0.f;
+                gl[b][e] = a.I[(size_t)min(y, a.H - 1) * a.W + min(x, a.W - 1)];
+            }
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int y = Y0 + 16 * (rb0 + b) + 4 * g4 + e;
+                gq[b][e] = (x < a.W && y < y_end) ? gl[b][e] : 0.f;
                 float tq = gq[b][e];
 #pragma unroll
                 for (int q = 0; q <= DSM; ++q) {
