@@ -124,27 +124,88 @@ __global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ T, 
     // (the k slot of instruction s is pixel x0 + 4 kq + s in both operands),
     // so each lane reads 4 consecutive floats of a filter row
     const bool vec = (W & 3) == 0;
-    for (int x0 = x_begin; x0 < x_end; x0 += 16) {
+    // x^ea from the binary digits of ea (ea <= 12, uniform over the workgroup)
+    auto xpow = [&](int x) {
+        const double xh = sx * x + ox, x2 = xh * xh, x4 = x2 * x2, x8 = x4 * x4;
+        return ((ea & 1) ? xh : 1.0) * ((ea & 2) ? x2 : 1.0) * ((ea & 4) ? x4 : 1.0) * ((ea & 8) ? x8 : 1.0);
+    };
+    // the lane's block rows of its (up to 3) block pairs; a wave with 2 pairs
+    // repeats its last one in slot 2 (loaded, never used), so that every
+    // operand load below is unconditional, from a clamped row
+    const float* tb = T + (size_t)row * W + 4 * kq;
+    size_t offa[3], offb[3];
+    bool use[3], ina[3], inb[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int pi = p_begin + (q < p_count ? q : p_count - 1);
+        const int rb = PAIRS[pi][0], cb = PAIRS[pi][1];
+        use[q] = q < p_count && 16 * rb < N && 16 * cb < N;   // uniform
+        ina[q] = 16 * rb + j < N;
+        inb[q] = 16 * cb + j < N;
+        offa[q] = (size_t)min(16 * rb + j, N - 1) * band_px;
+        offb[q] = (size_t)min(16 * cb + j, N - 1) * band_px;
+    }
+    int x0 = x_begin;
+    if (vec) {
+        // the steps whose 16 pixels are all inside the segment, two per turn:
+        // the operands of one step are requested (into a register set of
+        // their own) before the products of the step before it
+        const int x_full = x_begin + (x_end - x_begin) / 16 * 16;
+        auto load_step = [&](int xs, float4 (&o)[3][2]) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                o[q][0] = *reinterpret_cast<const float4*>(tb + offa[q] + xs);
+                o[q][1] = *reinterpret_cast<const float4*>(tb + offb[q] + xs);
+            }
+        };
+        auto run_step = [&](int xs, const float4 (&o)[3][2]) {
+            const int xb = xs + 4 * kq;
+            double wq[4];
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4)
+                wq[s4] = in_mask(mask, H, W, h, xb + s4, y) ? xpow(xb + s4) : 0.0;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                if (use[q]) {
+                    const float av[4] = {o[q][0].x, o[q][0].y, o[q][0].z, o[q][0].w};
+                    const float bv[4] = {o[q][1].x, o[q][1].y, o[q][1].z, o[q][1].w};
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4)
+                        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                            ina[q] ? (double)av[s4] : 0.0, inb[q] ? (double)bv[s4] * wq[s4] : 0.0,
+                            acc[q], 0, 0, 0);
+                }
+            }
+        };
+        float4 oA[3][2], oB[3][2];
+        if (x0 < x_full) load_step(x0, oA);
+        for (; x0 + 32 <= x_full; x0 += 32) {
+            load_step(x0 + 16, oB);
+            run_step(x0, oA);
+            load_step(x0 + 32 < x_full ? x0 + 32 : x0 + 16, oA);   // past the end: unused
+            run_step(x0 + 16, oB);
+        }
+        if (x0 < x_full) {
+            run_step(x0, oA);
+            x0 += 16;
+        }
+    }
+    // the remaining pixels (all of them when W is not a multiple of 4)
+    for (; x0 < x_end; x0 += 16) {
         const int xb = x0 + 4 * kq;
         const size_t pb = (size_t)row * W + xb;
         double wq[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int x = xb + s;
-            wq[s] = (x < x_end && in_mask(mask, H, W, h, x, y)) ? ipow_f(sx * x + ox, ea) : 0.0;
+            wq[s] = (x < x_end && in_mask(mask, H, W, h, x, y)) ? xpow(x) : 0.0;
         }
-        const bool full = vec && xb + 3 < x_end;
         auto load4 = [&](int nrow, float* v) {
             v[0] = v[1] = v[2] = v[3] = 0.f;
             if (nrow < N) {
                 const float* src = T + (size_t)nrow * band_px + pb;
-                if (full) {
-                    const float4 t4 = *reinterpret_cast<const float4*>(src);
-                    v[0] = t4.x; v[1] = t4.y; v[2] = t4.z; v[3] = t4.w;
-                } else {
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) v[s] = (xb + s < x_end) ? src[s] : 0.f;
-                }
+                for (int s = 0; s < 4; ++s) v[s] = (xb + s < x_end) ? src[s] : 0.f;
             }
         };
 #pragma unroll
