@@ -98,7 +98,9 @@ __device__ __forceinline__ double ipow_f(double x, int e) {
 // The 16 x 16 blocks with row block <= column block are formed (the waves
 // share them out); blocks whose rows or columns are all padding are skipped.
 // A operand: T_n(p_k); B operand: T_n'(p_k) xh^a mask.
-__global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ T, int N, int band_px,
+constexpr int GRAM_WAVES = 5;   // two of the 10 block pairs per wave
+
+__global__ __launch_bounds__(64 * GRAM_WAVES) void gram_kernel(const float* __restrict__ T, int N, int band_px,
                                                    int y_begin, int W, int H, int h, int cpr,
                                                    const unsigned char* __restrict__ mask,
                                                    double sx, double ox, int n_a,
@@ -112,34 +114,40 @@ __global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ T, 
     const int y = y_begin + row;
 
     // G is symmetric: only the 10 blocks (rb, cb) with rb <= cb of the 4 x 4
-    // block grid are formed, 3, 3, 2 and 2 of them by waves 0..3
+    // block grid are formed, two of them by each of the 5 waves (equal work
+    // on every SIMD)
     constexpr int PAIRS[10][2] = {{0, 0}, {0, 1}, {0, 2}, {0, 3}, {1, 1},
                                   {1, 2}, {1, 3}, {2, 2}, {2, 3}, {3, 3}};
-    const int p_begin = (w == 0) ? 0 : (w == 1) ? 3 : (w == 2) ? 6 : 8;
-    const int p_count = (w < 2) ? 3 : 2;
-    d4 acc[3];
+    constexpr int PQ = 2;
+    const int p_begin = PQ * w;
+    d4 acc[PQ];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < PQ; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
     // 16 pixels per step: lane group kq takes pixels x0 + 4 kq .. x0 + 4 kq + 3
     // (the k slot of instruction s is pixel x0 + 4 kq + s in both operands),
     // so each lane reads 4 consecutive floats of a filter row
     const bool vec = (W & 3) == 0;
-    // x^ea from the binary digits of ea (ea <= 12, uniform over the workgroup)
-    auto xpow = [&](int x) {
+    // pixel weights xh^ea (0 outside the mask) of the segment, formed once
+    // per workgroup (x^ea from the binary digits of ea <= 12)
+    __shared__ double wsh[NM_PIX_CHUNK];
+    for (int i = threadIdx.x; i < x_end - x_begin; i += 64 * GRAM_WAVES) {
+        const int x = x_begin + i;
         const double xh = sx * x + ox, x2 = xh * xh, x4 = x2 * x2, x8 = x4 * x4;
-        return ((ea & 1) ? xh : 1.0) * ((ea & 2) ? x2 : 1.0) * ((ea & 4) ? x4 : 1.0) * ((ea & 8) ? x8 : 1.0);
-    };
-    // the lane's block rows of its (up to 3) block pairs; a wave with 2 pairs
-    // repeats its last one in slot 2 (loaded, never used), so that every
-    // operand load below is unconditional, from a clamped row
+        wsh[i] = in_mask(mask, H, W, h, x, y) ? ((ea & 1) ? xh : 1.0) * ((ea & 2) ? x2 : 1.0) *
+                                                     ((ea & 4) ? x4 : 1.0) * ((ea & 8) ? x8 : 1.0)
+                                               : 0.0;
+    }
+    __syncthreads();
+    // the lane's block rows of its two block pairs; every operand load
+    // below is unconditional, from a clamped row
     const float* tb = T + (size_t)row * W + 4 * kq;
-    size_t offa[3], offb[3];
-    bool use[3], ina[3], inb[3];
+    size_t offa[PQ], offb[PQ];
+    bool use[PQ], ina[PQ], inb[PQ];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const int pi = p_begin + (q < p_count ? q : p_count - 1);
+    for (int q = 0; q < PQ; ++q) {
+        const int pi = p_begin + q;
         const int rb = PAIRS[pi][0], cb = PAIRS[pi][1];
-        use[q] = q < p_count && 16 * rb < N && 16 * cb < N;   // uniform
+        use[q] = 16 * rb < N && 16 * cb < N;   // uniform
         ina[q] = 16 * rb + j < N;
         inb[q] = 16 * cb + j < N;
         offa[q] = (size_t)min(16 * rb + j, N - 1) * band_px;
@@ -151,21 +159,20 @@ __global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ T, 
         // the operands of one step are requested (into a register set of
         // their own) before the products of the step before it
         const int x_full = x_begin + (x_end - x_begin) / 16 * 16;
-        auto load_step = [&](int xs, float4 (&o)[3][2]) {
+        auto load_step = [&](int xs, float4 (&o)[PQ][2]) {
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
+            for (int q = 0; q < PQ; ++q) {
                 o[q][0] = *reinterpret_cast<const float4*>(tb + offa[q] + xs);
                 o[q][1] = *reinterpret_cast<const float4*>(tb + offb[q] + xs);
             }
         };
-        auto run_step = [&](int xs, const float4 (&o)[3][2]) {
-            const int xb = xs + 4 * kq;
+        auto run_step = [&](int xs, const float4 (&o)[PQ][2]) {
+            const double* wp = wsh + (xs - x_begin + 4 * kq);
             double wq[4];
 #pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4)
-                wq[s4] = in_mask(mask, H, W, h, xb + s4, y) ? xpow(xb + s4) : 0.0;
+            for (int s4 = 0; s4 < 4; ++s4) wq[s4] = wp[s4];
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
+            for (int q = 0; q < PQ; ++q) {
                 if (use[q]) {
                     const float av[4] = {o[q][0].x, o[q][0].y, o[q][0].z, o[q][0].w};
                     const float bv[4] = {o[q][1].x, o[q][1].y, o[q][1].z, o[q][1].w};
@@ -177,7 +184,7 @@ __global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ T, 
                 }
             }
         };
-        float4 oA[3][2], oB[3][2];
+        float4 oA[PQ][2], oB[PQ][2];
         if (x0 < x_full) load_step(x0, oA);
         for (; x0 + 32 <= x_full; x0 += 32) {
             load_step(x0 + 16, oB);
@@ -196,10 +203,7 @@ __global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ T, 
         const size_t pb = (size_t)row * W + xb;
         double wq[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int x = xb + s;
-            wq[s] = (x < x_end && in_mask(mask, H, W, h, x, y)) ? xpow(x) : 0.0;
-        }
+        for (int s = 0; s < 4; ++s) wq[s] = (xb + s < x_end) ? wsh[xb + s - x_begin] : 0.0;
         auto load4 = [&](int nrow, float* v) {
             v[0] = v[1] = v[2] = v[3] = 0.f;
             if (nrow < N) {
@@ -209,8 +213,8 @@ __global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ T, 
             }
         };
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            if (q < p_count) {   // uniform
+        for (int q = 0; q < PQ; ++q) {
+            {
                 const int rb = PAIRS[p_begin + q][0], cb = PAIRS[p_begin + q][1];
                 if (16 * rb < N && 16 * cb < N) {   // uniform
                     float av[4], bv[4];
@@ -230,12 +234,10 @@ __global__ __launch_bounds__(256) void gram_kernel(const float* __restrict__ T, 
     // G[n = 16 rb + 4 e + kq][n' = 16 cb + j]
     double* dst = part + ((size_t)seg * n_a + ea) * 64 * 64;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        if (q < p_count) {
-            const int rb = PAIRS[p_begin + q][0], cb = PAIRS[p_begin + q][1];
+    for (int q = 0; q < PQ; ++q) {
+        const int rb = PAIRS[p_begin + q][0], cb = PAIRS[p_begin + q][1];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) dst[(16 * rb + 4 * e + kq) * 64 + 16 * cb + j] = acc[q][e];
-        }
+        for (int e = 0; e < 4; ++e) dst[(16 * rb + 4 * e + kq) * 64 + 16 * cb + j] = acc[q][e];
     }
 }
 
@@ -420,7 +422,7 @@ int launch_normal_matrix(svconv_plan* p, const float* R, const float* I, const u
             if (st) return st;
         }
         const int segs = rows * cpr;
-        hipLaunchKernelGGL(gram_kernel, dim3(n_a, segs), dim3(256), 0, p->stream, p->dTband, planes,
+        hipLaunchKernelGGL(gram_kernel, dim3(n_a, segs), dim3(64 * GRAM_WAVES), 0, p->stream, p->dTband, planes,
                            band_px, y0, p->W, p->H, p->h, cpr, mask, sx, ox, n_a, p->dNMpart);
         st = hip_status(hipGetLastError(), "gram_kernel");
         if (st) return st;
