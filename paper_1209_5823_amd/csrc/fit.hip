@@ -242,21 +242,38 @@ __global__ __launch_bounds__(64 * GRAM_WAVES) void gram_kernel(const float* __re
 }
 
 // S[(a, b)][.][.] += sum over segments (fixed order) of yh(segment row)^b G_a
-__global__ void gram_reduce(const double* __restrict__ part, int n_seg, int cpr, int n_a, int n_mu,
+__global__ void gram_reduce(const double* __restrict__ part, int n_seg, int cpr, int n_a,
                             int y_begin, double sy, double oy, double* __restrict__ S) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n_mu * 4096) return;
-    const int mu = idx >> 12, e = idx & 4095;
+    // thread (a, e): entry e of the partial sums of x power a, read once and
+    // added into S[mu(a, b)] for every y power b <= 2 d - a (n_a = 2 d + 1);
+    // yh^b by repeated products, the same sums as one power at a time
+    constexpr int NB_MAX = 2 * kMaxSpatialDegree + 1;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ea = blockIdx.y;
+    if (e >= 4096) return;
     if (((e >> 6) >> 4) > ((e & 63) >> 4)) return;   // lower blocks are not formed (S symmetric)
-    int tt = 0;
-    while ((tt + 1) * (tt + 2) / 2 <= mu) ++tt;
-    const int eb = mu - tt * (tt + 1) / 2, ea = tt - eb;
-    double s = 0.0;
+    const int n_eb = n_a - ea;                        // uniform
+    double acc[NB_MAX];
+#pragma unroll
+    for (int eb = 0; eb < NB_MAX; ++eb) acc[eb] = 0.0;
+#pragma unroll 4
     for (int c = 0; c < n_seg; ++c) {
+        const double v = part[((size_t)c * n_a + ea) * 4096 + e];
         const double yh = sy * (y_begin + c / cpr) + oy;
-        s += ipow_f(yh, eb) * part[((size_t)c * n_a + ea) * 4096 + e];
+        double pw = 1.0;
+#pragma unroll
+        for (int eb = 0; eb < NB_MAX; ++eb) {
+            if (eb < n_eb) acc[eb] += pw * v;
+            pw *= yh;
+        }
     }
-    S[idx] += s;
+#pragma unroll
+    for (int eb = 0; eb < NB_MAX; ++eb) {
+        if (eb < n_eb) {
+            const int tt = ea + eb;
+            S[(size_t)(tt * (tt + 1) / 2 + eb) * 4096 + e] += acc[eb];
+        }
+    }
 }
 
 __global__ void zero_kernel(double* __restrict__ v, size_t n) {
@@ -426,8 +443,8 @@ int launch_normal_matrix(svconv_plan* p, const float* R, const float* I, const u
                            band_px, y0, p->W, p->H, p->h, cpr, mask, sx, ox, n_a, p->dNMpart);
         st = hip_status(hipGetLastError(), "gram_kernel");
         if (st) return st;
-        hipLaunchKernelGGL(gram_reduce, dim3((n_mu * 4096 + 255) / 256), dim3(256), 0, p->stream,
-                           p->dNMpart, segs, cpr, n_a, n_mu, y0, sy, oy, S);
+        hipLaunchKernelGGL(gram_reduce, dim3(4096 / 256, n_a), dim3(256), 0, p->stream,
+                           p->dNMpart, segs, cpr, n_a, y0, sy, oy, S);
         st = hip_status(hipGetLastError(), "gram_reduce");
         if (st) return st;
     }
