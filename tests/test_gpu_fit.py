@@ -39,12 +39,15 @@ def test_loss_grad(svc, orc):
 
 # 9 bases take one 16-filter block of the contraction; 6 bases (at most 8)
 # take its two-row packed form, whose basis responses come out of both halves
-# of the matrix-core accumulator
+# of the matrix-core accumulator.  Width 56 runs the Gram sums on whole
+# 16-pixel steps plus a ragged one; width 61 (not a multiple of 4) runs them
+# all on the element-wise path.
+@pytest.mark.parametrize("width", [56, 61])
 @pytest.mark.parametrize("basis", [((0.7, 1.5), (2, 1)), ((1.5,), (2,))], ids=["n9", "n6"])
 @pytest.mark.parametrize("with_mask", [False, True])
-def test_normal_matrix_vs_oracle(svc, orc, with_mask, basis):
+def test_normal_matrix_vs_oracle(svc, orc, with_mask, basis, width):
     sig, deg = basis
-    R, C, a_star, B, (H, W, h, sig, deg, d_s) = small_case(orc, H=53, sig=sig, deg=deg)
+    R, C, a_star, B, (H, W, h, sig, deg, d_s) = small_case(orc, H=53, W=width, sig=sig, deg=deg)
     mask = None
     if with_mask:
         mask = (synth.uniform_image(H, W, seed=11) > -0.5).astype(np.uint8)
