@@ -212,10 +212,11 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
     }
 
     // T_f accumulates on the matrix cores in float32 over sub-chains of 4
-    // chunks (16 taps), and every sub-chain is added into a float64 total.
-    // Long float32 chains over all k^2 taps lose up to a few ulp of T at
-    // bright stars; short chains keep the rounding of each partial sum small
-    // and the float64 total adds none.
+    // chunks (16 taps), and every sub-chain (with up to two filter blocks, the
+    // float32 sum of two) is added into a float64 total.  Long float32 chains
+    // over all k^2 taps lose up to a few ulp of T at bright stars; short
+    // chains keep the rounding of each partial sum small and the float64
+    // total adds none.
     double tot[NB][RI][4];
 #pragma unroll
     for (int b = 0; b < NB; ++b)
@@ -226,9 +227,10 @@ __global__ __launch_bounds__(256, 2) void contract_f32_kernel(ContractArgs a,
 
     // The A fragments of a group of 4 chunks go to one of two register sets
     // while the other set's group runs: the loop takes two groups per turn so
-    // that no set is copied (a copy of a value still in flight waits for it),
-    // and a scheduling barrier keeps each group's loads ahead of the products
-    // of the group before it.
+    // that no set is copied (a copy of a value still in flight waits for it).
+    // With up to two filter blocks a scheduling barrier keeps each group's
+    // loads ahead of the products of the group before it; with more, the
+    // compiler keeps that order by itself and the barrier would cost spills.
     const float* fp = frag + lane;
     auto load_group = [&](float (&f)[4][NB], int c0) {
         const int cc = (c0 < n_chunks) ? c0 : n_chunks - 4;   // past the end: unused
