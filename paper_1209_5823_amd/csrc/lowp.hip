@@ -427,15 +427,13 @@ __device__ __forceinline__ void lp_epilogue_setup(const ContractArgs& a, float (
         for (int e = 0; e < 4; ++e)
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) {
+                // loads from clamped indices, masked after (no load under a branch)
                 const int f = 16 * b + 4 * k + e;
                 const int m = 16 * mb + ml;
-                float v = 0.f;
-                if (f < a.NF && m < a.M) {
-                    const float inv = a.fscale ? a.fscale[f] : 1.f;
-                    const float c = REG ? (f == m ? 1.f : 0.f) : a.coef[f * a.M + m];
-                    v = c * inv;
-                }
-                afr[b][e][mb] = v;
+                const int fc = f < a.NF ? f : a.NF - 1, mc = m < a.M ? m : a.M - 1;
+                const float inv = a.fscale ? a.fscale[fc] : 1.f;
+                const float c = REG ? (f == m ? 1.f : 0.f) : a.coef[fc * a.M + mc];
+                afr[b][e][mb] = (f < a.NF && m < a.M) ? c * inv : 0.f;
             }
     if (tid < a.M) {
         double gm = 0.0;
